@@ -1,0 +1,274 @@
+"""Seeded synthetic inputs: voxel phase maps, per-phase constants, load paths.
+
+This module holds no arithmetic of the solver itself.  It only draws the
+inputs that the paper's problem statement asks for (Alg. 2 inputs): a voxel
+phase image, the isotropic constants of each phase (Eq. 6 moduli, Eqs. 13-18
+plastic constants), and a macroscopic strain / curvature path E(t), Gamma(t).
+Both the HIP path and the CPU oracle take their inputs from here.
+
+Tensor components use the 9-vector index 3*k + l for V_kl (k = row).
+Phase images are uint8 arrays of shape (n2, n1, n0) = (z, y, x): x fastest.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, asdict
+
+import numpy as np
+
+INF = float("inf")
+
+PHASE_KEYS = ("lam", "mu", "kappa", "alpha", "beta", "gamma",
+              "tY", "tH", "mY", "mH", "a1", "b1")
+
+
+@dataclass
+class Phase:
+    """Isotropic micropolar elastoplastic constants of one phase.
+
+    Elastic moduli of Eq. 6 (lam, mu, kappa, alpha, beta, gamma); macro yield
+    stress / hardening tY, tH (Eq. 15); micro yield / hardening mY, mH (Eq. 18);
+    plastic weights a1, b1 (Eqs. 14, 17).  tY = mY = inf gives an elastic phase.
+    """
+    lam: float
+    mu: float
+    kappa: float
+    alpha: float
+    beta: float
+    gamma: float
+    tY: float = INF
+    tH: float = 0.0
+    mY: float = INF
+    mH: float = 0.0
+    a1: float = 1.5
+    b1: float = 1.5
+
+    def as_tuple(self):
+        return tuple(float(getattr(self, k)) for k in PHASE_KEYS)
+
+    def scaled_moduli(self, c: float, elastic: bool = True) -> "Phase":
+        """Same phase with every elastic modulus multiplied by c."""
+        p = Phase(**asdict(self))
+        for k in ("lam", "mu", "kappa", "alpha", "beta", "gamma"):
+            setattr(p, k, getattr(p, k) * c)
+        if elastic:
+            p.tY = p.mY = INF
+            p.tH = p.mH = 0.0
+        return p
+
+
+def matrix_phase(lam=1.0, mu=1.0, kappa=0.1, length=2.0, h=1.0,
+                 tY=0.005, tH=0.1, mY=None, mH=None, a1=1.5, b1=1.5) -> Phase:
+    """Matrix of the sphere-inclusion workloads.
+
+    beta = gamma = mu * l^2 with l given in voxels (times the voxel size h),
+    alpha = 0; micro yield and hardening equal the macro ones unless given.
+    """
+    lg = length * h
+    bg = mu * lg * lg
+    return Phase(lam=lam, mu=mu, kappa=kappa, alpha=0.0, beta=bg, gamma=bg,
+                 tY=tY, tH=tH, mY=tY if mY is None else mY,
+                 mH=tH if mH is None else mH, a1=a1, b1=b1)
+
+
+# ----------------------------------------------------------------------------
+# microstructures
+# ----------------------------------------------------------------------------
+
+def _voxel_centres(n):
+    """Continuous coordinates of voxel centres, h = 1, arrays shaped (z, y, x)."""
+    z, y, x = np.meshgrid(np.arange(n[2]) + 0.5, np.arange(n[1]) + 0.5,
+                          np.arange(n[0]) + 0.5, indexing="ij")
+    return x, y, z
+
+
+def _paint_sphere(phase, n, c, r, value):
+    """Mark voxels whose centre lies within r of c (periodic minimum image)."""
+    x, y, z = _voxel_centres(n)
+    d2 = np.zeros(phase.shape)
+    for coord, cc, L in ((x, c[0], n[0]), (y, c[1], n[1]), (z, c[2], n[2])):
+        d = coord - cc
+        d -= L * np.round(d / L)
+        d2 += d * d
+    phase[d2 <= r * r] = value
+
+
+def centred_sphere(n: int, vf: float) -> np.ndarray:
+    """One sphere at the cell centre with nominal volume fraction vf."""
+    r = (3.0 * vf * n ** 3 / (4.0 * math.pi)) ** (1.0 / 3.0)
+    ph = np.zeros((n, n, n), np.uint8)
+    _paint_sphere(ph, (n, n, n), (n / 2.0, n / 2.0, n / 2.0), r, 1)
+    return ph
+
+
+def random_spheres(n: int, seed: int, count: int | None, rmin: float, rmax: float,
+                   target_vf: float | None = None, max_tries: int = 200000):
+    """Random sequential addition of non-overlapping periodic spheres.
+
+    Radii ~ U[rmin, rmax], centres ~ U[0, n)^3; a candidate is kept when its
+    periodic distance to every kept centre is at least the sum of the radii.
+    Stops after `count` spheres, or once the painted volume fraction reaches
+    target_vf.  Returns (phase image, list of (cx, cy, cz, r)).
+    """
+    rng = np.random.default_rng(seed)
+    spheres = []
+    ph = np.zeros((n, n, n), np.uint8)
+    tries = 0
+    while tries < max_tries:
+        if count is not None and len(spheres) >= count:
+            break
+        if target_vf is not None and len(spheres) and (ph.mean() >= target_vf):
+            break
+        tries += 1
+        r = rng.uniform(rmin, rmax)
+        c = rng.uniform(0.0, n, size=3)
+        ok = True
+        for (cx, cy, cz, rr) in spheres:
+            d = np.array([cx, cy, cz]) - c
+            d -= n * np.round(d / n)
+            if float(np.sqrt(d @ d)) < r + rr:
+                ok = False
+                break
+        if not ok:
+            continue
+        spheres.append((float(c[0]), float(c[1]), float(c[2]), float(r)))
+        _paint_sphere(ph, (n, n, n), c, r, 1)
+    return ph, spheres
+
+
+def laminate(n: int, axis: int = 0) -> np.ndarray:
+    """Two-phase laminate, 50 % volume fraction, layers normal to `axis` (0 = x)."""
+    ph = np.zeros((n, n, n), np.uint8)
+    idx = [slice(None)] * 3
+    idx[2 - axis] = slice(n // 2, n)
+    ph[tuple(idx)] = 1
+    return ph
+
+
+# ----------------------------------------------------------------------------
+# load paths
+# ----------------------------------------------------------------------------
+
+def ramp_path(n_steps: int, E_end=None, G_end=None, t_end: float = 1.0):
+    """Linear ramp from the zero state: times[0] = 0, times[s] = s * t_end / S.
+
+    Returns times (S+1,), E (S, 9), G (S, 9); E[s-1] is the target at times[s].
+    """
+    times = np.linspace(0.0, t_end, n_steps + 1)
+    E_end = np.zeros(9) if E_end is None else np.asarray(E_end, float).reshape(9)
+    G_end = np.zeros(9) if G_end is None else np.asarray(G_end, float).reshape(9)
+    frac = times[1:] / t_end
+    return times, frac[:, None] * E_end[None, :], frac[:, None] * G_end[None, :]
+
+
+def unit(idx_kl, value=1.0):
+    v = np.zeros(9)
+    v[3 * idx_kl[0] + idx_kl[1]] = value
+    return v
+
+
+# ----------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    phase_map: np.ndarray            # (n2, n1, n0) uint8
+    phases: list                     # list[Phase]
+    times: np.ndarray                # (S+1,)
+    E: np.ndarray                    # (S, 9)
+    G: np.ndarray                    # (S, 9)
+    tol: float
+    h: float = 1.0
+    err_norm: str = "local"          # Eq. 38 ("local") or Eq. 37 ("average")
+    ref_mode: str = "phase_mean"
+    info: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        s = self.phase_map.shape
+        return (s[2], s[1], s[0])
+
+    @property
+    def voxels(self):
+        return int(self.phase_map.size)
+
+
+def single_sphere_16(contrast: float = 5.0) -> Workload:
+    """16^3 cell, one centred elastic sphere (vf 0.2) in an elastoplastic matrix;
+    uniaxial E11 ramped to 0.01 in 10 equal steps; tolerance 1e-8."""
+    mat = matrix_phase()
+    inc = mat.scaled_moduli(contrast)
+    times, E, G = ramp_path(10, E_end=unit((0, 0), 0.01), t_end=10.0)
+    return Workload("sphere16_fp64", centred_sphere(16, 0.2), [mat, inc], times, E, G,
+                    tol=1e-8, info={"contrast": contrast})
+
+
+def random_spheres_128(seed: int = 1, n_steps: int = 50) -> Workload:
+    """128^3 cell, 40 random elastic spheres r ~ U[6, 12], contrast 10;
+    E11 ramped to 0.02 with curvature Gamma12 ramped to 0.002 over 50 steps."""
+    ph, sp = random_spheres(128, seed, 40, 6.0, 12.0)
+    mat = matrix_phase()
+    inc = mat.scaled_moduli(10.0)
+    S = 50
+    times, E, G = ramp_path(S, E_end=unit((0, 0), 0.02), G_end=unit((0, 1), 0.002),
+                            t_end=float(S))
+    times, E, G = times[: n_steps + 1], E[:n_steps], G[:n_steps]
+    return Workload("spheres128_fp64", ph, [mat, inc], times, E, G, tol=1e-8,
+                    info={"spheres": len(sp), "vf": float(ph.mean())})
+
+
+def random_spheres_256(seed: int = 2, n_steps: int = 20) -> Workload:
+    """256^3 cell, spheres r ~ U[5, 15] added until the volume fraction is
+    at least 0.25, contrast 10; E11 ramped to 0.01 over 20 steps; tol 1e-6."""
+    ph, sp = random_spheres(256, seed, None, 5.0, 15.0, target_vf=0.25)
+    mat = matrix_phase()
+    inc = mat.scaled_moduli(10.0)
+    S = 20
+    times, E, G = ramp_path(S, E_end=unit((0, 0), 0.01), t_end=float(S))
+    times, E, G = times[: n_steps + 1], E[:n_steps], G[:n_steps]
+    return Workload("spheres256_mixed", ph, [mat, inc], times, E, G, tol=1e-6,
+                    info={"spheres": len(sp), "vf": float(ph.mean())})
+
+
+def random_rve(seed: int, n: int, n_steps: int = 20) -> Workload:
+    """One RVE of the many-RVE batch: 1-60 spheres r ~ U[n/20, n/10], contrast
+    U[2, 20], l ~ U[0.5, 4] voxels, tY ~ U[0.003, 0.01]; random symmetric unit
+    strain direction with norm ramped to 0.01; tol 1e-6."""
+    rng = np.random.default_rng(seed)
+    count = int(rng.integers(1, 61))
+    contrast = float(rng.uniform(2.0, 20.0))
+    length = float(rng.uniform(0.5, 4.0))
+    tY = float(rng.uniform(0.003, 0.01))
+    v = rng.standard_normal(6)
+    sym = np.array([[v[0], v[5], v[4]], [v[5], v[1], v[3]], [v[4], v[3], v[2]]])
+    sym /= np.linalg.norm(sym)
+    ph, sp = random_spheres(n, int(rng.integers(0, 2**31)), count, n / 20.0, n / 10.0)
+    mat = matrix_phase(length=length, tY=tY)
+    inc = mat.scaled_moduli(contrast)
+    times, E, G = ramp_path(n_steps, E_end=0.01 * sym.reshape(9), t_end=float(n_steps))
+    return Workload(f"rve{n}_s{seed}", ph, [mat, inc], times, E, G, tol=1e-6,
+                    info={"spheres": len(sp), "contrast": contrast, "l": length, "tY": tY})
+
+
+def mnms_cube4():
+    """4^3 cube used for manufactured solutions: inner centred 2^3 block is
+    phase 0, the outer layer phase 1 (constants of the paper's code check)."""
+    ph = np.ones((4, 4, 4), np.uint8)
+    ph[1:3, 1:3, 1:3] = 0
+    p1 = Phase(lam=1.0, mu=1.0, kappa=0.5, alpha=0.0, beta=0.5, gamma=1.0,
+               tY=4.0, tH=0.0, mY=4.0, mH=0.0, a1=1.5, b1=1.5)
+    p2 = Phase(lam=1.5, mu=1.5, kappa=0.75, alpha=0.0, beta=0.25, gamma=1.5,
+               tY=4.5, tH=0.0, mY=4.5, mH=0.0, a1=1.5, b1=1.5)
+    return ph, [p1, p2]
+
+
+def random_state(nvox: int, seed: int, scale: float = 1e-2):
+    """Random pointwise inputs for return-map checks: e, g, e_n, g_n, t_n, m_n
+    as (9, nvox) arrays, p_n, q_n >= 0 as (nvox,)."""
+    rng = np.random.default_rng(seed)
+    f = lambda: scale * rng.standard_normal((9, nvox))
+    return dict(e=f(), g=f(), e_n=f(), g_n=f(), t_n=f(), m_n=f(),
+                p_n=np.abs(scale * rng.standard_normal(nvox)),
+                q_n=np.abs(scale * rng.standard_normal(nvox)))

@@ -1,0 +1,173 @@
+/*
+ * mp.h -- C ABI of the MI355X micropolar elastoplastic FFT-based solver.
+ *
+ * The library runs the elastoplastic FFT-based basic scheme of Francis,
+ * Lebensohn, Pourahmadian and Dingreville (micropolar elastoplasticity with an
+ * FFT-based solver): a Moulinec-Suquet fixed-point iteration on a periodic
+ * voxel grid (Alg. 2) whose every iteration
+ *   (a) forms the polarization stresses tau, mu (Eq. 34),
+ *   (b) forward-transforms their 18 components,
+ *   (c) applies the reference-medium Green operator per frequency (Eq. 35),
+ *   (d) inverse-transforms to the strain and curvature fields and adds the
+ *       prescribed averages E, Gamma,
+ *   (e) runs the micropolar radial return (Alg. 1) at every voxel, and
+ *   (f) evaluates the error measure of Eqs. 36-38.
+ *
+ * Conventions shared by every entry point
+ *   - Grid n[0] x n[1] x n[2] voxels of size h, x fastest: voxel (x, y, z) has
+ *     linear index (z * n[1] + y) * n[0] + x.  Every n[i] must be even, in
+ *     [4, 256], and a product of 2s and 3s.
+ *   - Tensor V_kl is component 3 * k + l (k = row).  t_kl acts on the face of
+ *     normal k (Eq. 2); e_kl = u_l,k + eps_lkm phi_m, gamma_kl = phi_k,l (Eq. 1);
+ *     m_kl = B_lkmn gamma_mn (Eq. 5).
+ *   - Device fields are structure-of-arrays: component c of a 9-component
+ *     field occupies n voxels starting at c * n.
+ *   - Frequencies are the continuous ones, xi = 2 pi m / (n h).  The
+ *     fluctuating strain and curvature are zero at k = 0 and at every Nyquist
+ *     index.
+ *   - All work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *     void*; NULL = default stream).  Device memory comes from the caller: the
+ *     library allocates none.  Host arrays are copied during the call and
+ *     never retained.
+ *   - Errors are returned as mp_status; mp_last_error() gives a thread-local
+ *     message.  No C++ exception crosses this boundary.
+ */
+#ifndef MP_H
+#define MP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MP_OK = 0,
+  MP_E_INVALID = 1,        /* bad argument or unsupported problem */
+  MP_E_NOMEM = 2,          /* workspace smaller than mp_plan_workspace_size */
+  MP_E_DEVICE = 3,         /* a HIP call failed */
+  MP_E_NOT_CONVERGED = 4,  /* max_iter reached in a step; that step is committed */
+  MP_E_DIVERGED = 5,       /* non-finite or exploding error measure; step committed */
+  MP_E_STATE = 6           /* call not valid in the plan's current state */
+} mp_status;
+
+enum { MP_FP64 = 0, MP_MIXED = 1 };                 /* arithmetic of the bulk fields */
+enum { MP_ERR_LOCAL = 0, MP_ERR_AVERAGE = 1 };      /* Eq. 38 | Eq. 37 */
+enum { MP_REF_PHASE_MEAN = 0, MP_REF_VOLUME_MEAN = 1, MP_REF_EXPLICIT = 2 };
+enum { MP_FIELD_E = 0, MP_FIELD_GAMMA = 1, MP_FIELD_T = 2, MP_FIELD_M = 3,
+       MP_FIELD_P = 4, MP_FIELD_Q = 5 };
+
+/* Constants of one isotropic phase: Eq. 6 moduli, Eqs. 13-18 plastic
+ * constants.  tY = +inf (resp. mY = +inf) makes the macro (micro) level
+ * purely elastic.  Alg. 1 derives a2 = a1 mu / kappa and
+ * b2 = b1 (gamma + beta) / (gamma - beta); gamma == beta is accepted and
+ * means a vanishing skew couple-stress modulus (the b2 term then drops). */
+typedef struct {
+  double lambda, mu, kappa, alpha, beta, gamma;
+  double tY, tH, mY, mH, a1, b1;
+} mp_phase;
+
+/* Problem statement (inputs of Alg. 2). */
+typedef struct {
+  int32_t n[3];             /* voxels along x, y, z */
+  double h;                 /* voxel size */
+  const uint8_t* phase;     /* host, n[0]*n[1]*n[2] phase ids, each < n_phases */
+  int32_t n_phases;         /* 1..256 */
+  const mp_phase* phases;   /* host, n_phases records */
+  int32_t ref_mode;         /* MP_REF_*: reference medium A0, B0 */
+  mp_phase ref;             /* elastic constants used with MP_REF_EXPLICIT */
+  double tol;               /* epsilon of Alg. 2 (> 0) */
+  int32_t max_iter;         /* loop cap per step (>= 1) */
+  int32_t err_norm;         /* MP_ERR_LOCAL | MP_ERR_AVERAGE */
+  int32_t precision;        /* MP_FP64 (MP_MIXED is rejected by this build) */
+} mp_problem;
+
+typedef struct mp_plan_s* mp_plan;
+
+/* Bytes of device workspace a plan for `prob` needs.  Validates `prob`
+ * (Eq. 7 bounds with gamma - beta >= 0 allowed, kappa > 0, alpha = 0 in any
+ * phase with finite mY, tY > 0, mY > 0, grid sizes) and returns
+ * MP_E_INVALID on violation. */
+mp_status mp_plan_workspace_size(const mp_problem* prob, size_t* bytes);
+
+/* Create a plan: carves `dev_workspace` (>= mp_plan_workspace_size bytes,
+ * 256-byte aligned, owned by the caller, must outlive the plan), uploads the
+ * phase map and constants, computes the reference medium (Alg. 2: A0 from
+ * the phases; default the unweighted mean of each modulus over the phases
+ * present) and sets the zero initial state of Alg. 2.  Work goes to
+ * `hip_stream`. */
+mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t bytes,
+                         void* hip_stream, mp_plan* out);
+
+/* Solve load steps with Alg. 2, continuing from the plan's current state.
+ * times: n_steps + 1 values; times[0] is the time of the current state (the
+ * zero state for a fresh plan), times[s] the end of step s.  E, Gam:
+ * [n_steps][9] prescribed average strain and curvature at times[1..].
+ * iters: optional [n_steps] output of loop iterations per step.
+ * The first step of a fresh plan starts from the uniform E; later steps start
+ * from the linear extrapolation of the last two committed states.  Returns
+ * at the first step that does not converge (MP_E_NOT_CONVERGED,
+ * MP_E_DIVERGED) after committing it.  Blocks until the work is done. */
+mp_status mp_solve_load_path(mp_plan plan, int32_t n_steps, const double* times,
+                             const double* E, const double* Gam, int32_t* iters);
+
+/* Homogenized response of committed step `step` (1-based, counted over the
+ * plan's life).  out[42] = T[9] M[9] <e>[9] <gamma>[9] <p> <q> <t_eq> <m_eq>
+ * err iterations, all volume averages in FP64. */
+mp_status mp_homogenized_response(mp_plan plan, int32_t step, double out[42]);
+
+/* Copy one field of the current state (after the last committed step) to
+ * host memory as FP64: MP_FIELD_E/GAMMA/T/M write 9*n doubles (SoA),
+ * MP_FIELD_P/Q write n doubles.  Blocks. */
+mp_status mp_get_fields(mp_plan plan, int32_t field, double* host_dst);
+
+/* Test hook: when n_fixed > 0 every later step runs exactly n_fixed loop
+ * iterations regardless of the tolerance (0 restores the tolerance test).
+ * Lets parity tests follow a given iteration schedule. */
+mp_status mp_set_fixed_iterations(mp_plan plan, int32_t n_fixed);
+
+/* Number of committed steps. */
+mp_status mp_plan_steps(mp_plan plan, int32_t* steps);
+
+/* Apply the spectral part of one iteration (rows b-d above) to given
+ * polarization fields: in = 18*n device doubles (tau then mu, SoA), out =
+ * 18*n device doubles receiving the fluctuating strain then curvature
+ * (no averages added).  Uses the plan's transforms and reference medium. */
+mp_status mp_green_apply(mp_plan plan, const void* dev_in, void* dev_out);
+
+/* Forward transform of 18 real fields (device, 18*n doubles) to their half
+ * spectra: dev_out receives 18 * n[2] * n[1] * (n[0]/2) complex doubles
+ * (interleaved re, im), layout [c][kz][ky][kx], kx = 0 .. n[0]/2 - 1 (the
+ * x-Nyquist bin is not kept), unnormalised forward DFT. */
+mp_status mp_spectrum_forward(mp_plan plan, const void* dev_in, void* dev_out);
+
+/* Radial return (Alg. 1) at n_vox independent points on the device, FP64.
+ * phase: n_vox uint8 ids into the plan's phase table.  e, g, e_n, g_n, t_n,
+ * m_n: 9*n_vox SoA; p_n, q_n: n_vox.  Outputs t, m (9*n_vox), p, q (n_vox).
+ * Uses the same device code as the solver (trial stresses formed from the
+ * history base t_n - A e_n, m_n - B g_n). */
+mp_status mp_radial_return(mp_plan plan, int64_t n_vox, const void* phase,
+                           const void* e, const void* g, const void* e_n, const void* g_n,
+                           const void* t_n, const void* m_n, const void* p_n, const void* q_n,
+                           void* t, void* m, void* p, void* q);
+
+/* Per-kernel timing of loop iterations, for measurement.  With enable != 0
+ * the plan records hipEvents on its stream between the kernels of every
+ * iteration that runs and accumulates their durations (counters reset on
+ * every call).  mp_profile_read fills ms_total[j] (milliseconds) and
+ * launches[j] for j < min(n, 7), kernel j in iteration order: 0 y forward,
+ * 1 z forward, 2 Green operator, 3 z inverse, 4 y inverse, 5 x pass (inverse
+ * x transform, return maps, error partials, polarization, forward x
+ * transform), 6 error reduction.  Adds event records between kernels. */
+mp_status mp_profile(mp_plan plan, int32_t enable);
+mp_status mp_profile_read(mp_plan plan, int32_t n, double* ms_total, int64_t* launches);
+
+void mp_plan_destroy(mp_plan plan);
+const char* mp_last_error(void);
+const char* mp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MP_H */

@@ -1,0 +1,404 @@
+// Device building blocks of the micropolar FFT solver (gfx950).
+//
+//   cx<T>            interleaved complex value (re, im), 2*sizeof(T) aligned
+//   fft_inplace      self-sorting mixed-radix Stockham FFT of a batch of
+//                    pencils held in LDS (radices 2, 3, 4, 8); each stage
+//                    gathers its butterflies into registers, barriers, then
+//                    scatters, so one LDS buffer suffices
+//   PhaseC           per-phase constants with the derived a2, b2 of Alg. 1
+//   return_map       micropolar radial return of Alg. 1 at one voxel
+//   green_apply      reference-medium Green operator at one frequency
+//                    (closed-form solve of the 6x6 Fourier symbol of the
+//                    balance equations, Eqs. 1, 2, 6, 33-35)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mp {
+
+template <class T>
+struct __align__(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <class T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <class T, bool INV>
+__device__ __forceinline__ cx<T> rot90(cx<T> a) {
+  return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+template <class T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.im, a.re}; }
+
+// ---------------------------------------------------------------------------
+// small DFTs in registers: X_s = sum_r a_r exp(-+ 2 pi i r s / R)
+// ---------------------------------------------------------------------------
+template <class T, int R, bool INV>
+struct Dft;
+
+template <class T, bool INV>
+struct Dft<T, 2, INV> {
+  static __device__ __forceinline__ void run(cx<T>* a) {
+    cx<T> t = a[1];
+    a[1] = csub(a[0], t);
+    a[0] = cadd(a[0], t);
+  }
+};
+
+template <class T, bool INV>
+struct Dft<T, 4, INV> {
+  static __device__ __forceinline__ void run(cx<T>* a) {
+    cx<T> t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    cx<T> t2 = cadd(a[1], a[3]), t3 = rot90<T, INV>(csub(a[1], a[3]));
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+  }
+};
+
+template <class T, bool INV>
+struct Dft<T, 8, INV> {
+  static __device__ __forceinline__ void run(cx<T>* a) {
+    cx<T> ev[4] = {a[0], a[2], a[4], a[6]};
+    cx<T> od[4] = {a[1], a[3], a[5], a[7]};
+    Dft<T, 4, INV>::run(ev);
+    Dft<T, 4, INV>::run(od);
+    const T c = T(0.70710678118654752440084436210484903928);
+    // W8^s with W8 = exp(-+ i pi / 4)
+    cx<T> w1 = INV ? cx<T>{c, c} : cx<T>{c, -c};
+    cx<T> w3 = INV ? cx<T>{-c, c} : cx<T>{-c, -c};
+    cx<T> o0 = od[0];
+    cx<T> o1 = cmul(od[1], w1);
+    cx<T> o2 = rot90<T, INV>(od[2]);
+    cx<T> o3 = cmul(od[3], w3);
+    a[0] = cadd(ev[0], o0);
+    a[4] = csub(ev[0], o0);
+    a[1] = cadd(ev[1], o1);
+    a[5] = csub(ev[1], o1);
+    a[2] = cadd(ev[2], o2);
+    a[6] = csub(ev[2], o2);
+    a[3] = cadd(ev[3], o3);
+    a[7] = csub(ev[3], o3);
+  }
+};
+
+template <class T, bool INV>
+struct Dft<T, 3, INV> {
+  static __device__ __forceinline__ void run(cx<T>* a) {
+    const T h = T(0.86602540378443864676372317075293618347);  // sqrt(3) / 2
+    cx<T> s = cadd(a[1], a[2]);
+    cx<T> d = csub(a[1], a[2]);
+    cx<T> m = {a[0].re - T(0.5) * s.re, a[0].im - T(0.5) * s.im};
+    cx<T> r = rot90<T, INV>(cx<T>{d.re * h, d.im * h});
+    a[0] = cadd(a[0], s);
+    a[1] = cadd(m, r);
+    a[2] = csub(m, r);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Stockham stage, in place in LDS.
+//   pencil b, point i lives at buf[b * bs + i * ps]; N points per pencil,
+//   nb pencils.  p = product of the radices already applied.  Butterfly w
+//   reads points i + r N/R, twiddles them by exp(-+2 pi i r k/(pR)),
+//   k = i mod p, and writes points (i - k) R + k + s p.
+//   MB = butterflies a thread can hold; the host guarantees
+//   ceil(nb N / R / nthr) <= MB.
+// ---------------------------------------------------------------------------
+template <class T, int R, bool INV, int MB>
+__device__ __forceinline__ void stage_inplace(cx<T>* buf, int N, int p, int nb, int ps, int bs,
+                                              bool bfast, const cx<T>* __restrict__ tw,
+                                              int tid, int nthr) {
+  const int nbf = N / R;
+  const int total = nbf * nb;
+  const int tws = N / (p * R);
+  cx<T> u[MB][R];
+#pragma unroll
+  for (int j = 0; j < MB; ++j) {
+    const int w = tid + j * nthr;
+    if (w < total) {
+      int i, b;
+      if (bfast) { b = w % nb; i = w / nb; } else { i = w % nbf; b = w / nbf; }
+      const cx<T>* src = buf + b * bs + i * ps;
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[j][r] = src[r * nbf * ps];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < MB; ++j) {
+    const int w = tid + j * nthr;
+    if (w < total) {
+      int i, b;
+      if (bfast) { b = w % nb; i = w / nb; } else { i = w % nbf; b = w / nbf; }
+      const int k = i % p;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cx<T> t = tw[r * k * tws];
+        if (INV) t.im = -t.im;
+        u[j][r] = cmul(u[j][r], t);
+      }
+      Dft<T, R, INV>::run(u[j]);
+      cx<T>* dst = buf + b * bs + ((i - k) * R + k) * ps;
+#pragma unroll
+      for (int s = 0; s < R; ++s) dst[s * p * ps] = u[j][s];
+    }
+  }
+  __syncthreads();
+}
+
+// Radix schedule: 4 bits per stage, first stage in the low bits, 0 ends.
+// tw: N-entry table exp(-2 pi i m / N).  Unnormalised in both directions.
+template <class T, bool INV, int MAXP>
+__device__ __forceinline__ void fft_inplace(cx<T>* buf, int N, int nb, int ps, int bs, bool bfast,
+                                            uint32_t sched, const cx<T>* __restrict__ tw,
+                                            int tid, int nthr) {
+  int p = 1;
+  for (int st = 0; st < 8; ++st) {
+    const int R = (sched >> (4 * st)) & 15;
+    if (R == 0) break;
+    if (R == 8)
+      stage_inplace<T, 8, INV, MAXP / 8>(buf, N, p, nb, ps, bs, bfast, tw, tid, nthr);
+    else if (R == 4)
+      stage_inplace<T, 4, INV, MAXP / 4>(buf, N, p, nb, ps, bs, bfast, tw, tid, nthr);
+    else if (R == 2)
+      stage_inplace<T, 2, INV, MAXP / 2>(buf, N, p, nb, ps, bs, bfast, tw, tid, nthr);
+    else
+      stage_inplace<T, 3, INV, MAXP / 3>(buf, N, p, nb, ps, bs, bfast, tw, tid, nthr);
+    p *= R;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1: micropolar radial return at one voxel.
+// ---------------------------------------------------------------------------
+struct PhaseC {
+  double lam, mu, kap, alp, bet, gam;
+  double tY, tH, mY, mH, a1, b1;
+  double a2;      // a1 mu / kappa
+  double b2;      // b1 (gamma + beta) / (gamma - beta); 0 when gamma == beta
+  double b2gmb;   // b2 (gamma - beta); b1 (gamma + beta) when gamma == beta
+  double pad;
+};
+
+// t_kl = lam tr(e) d_kl + (mu + kappa) e_kl + (mu - kappa) e_lk      (Eq. 6)
+template <class T>
+__device__ __forceinline__ void apply_A(T lam, T mu, T kap, const T* e, T* t) {
+  const T tr = e[0] + e[4] + e[8];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      t[3 * k + l] = (mu + kap) * e[3 * k + l] + (mu - kap) * e[3 * l + k] + (k == l ? lam * tr : T(0));
+}
+
+// m_kl = B_lkmn g_mn = alpha tr(g) d_kl + beta g_kl + gamma g_lk       (Eq. 6)
+template <class T>
+__device__ __forceinline__ void apply_B(T alp, T bet, T gam, const T* g, T* m) {
+  const T tr = g[0] + g[4] + g[8];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      m[3 * k + l] = bet * g[3 * k + l] + gam * g[3 * l + k] + (k == l ? alp * tr : T(0));
+}
+
+// Trial stresses from the history base bt = t_n - A e_n, bm = m_n - B g_n
+// (Eq. 30: t_trial = t_n + A (e - e_n) = bt + A e), then the macro and
+// micro returns with the closed-form p, q of Eq. 32.
+template <class T>
+__device__ __forceinline__ void return_map(const PhaseC& c, const T* e, const T* g, const T* bt,
+                                           const T* bm, double pn, double qn, T* t, T* m,
+                                           double& p, double& q) {
+  apply_A<T>(T(c.lam), T(c.mu), T(c.kap), e, t);
+  apply_B<T>(T(c.alp), T(c.bet), T(c.gam), g, m);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    t[i] += bt[i];
+    m[i] += bm[i];
+  }
+  // macro level: deviatoric sym / skew parts, Eq. 14
+  const T vol = (t[0] + t[4] + t[8]) / T(3);
+  T ss[9], sk[9];
+  T n_sym = 0, n_skw = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const T skl = t[3 * k + l] - (k == l ? vol : T(0));
+      const T slk = t[3 * l + k] - (k == l ? vol : T(0));
+      ss[3 * k + l] = T(0.5) * (skl + slk);
+      sk[3 * k + l] = T(0.5) * (skl - slk);
+      n_sym += ss[3 * k + l] * ss[3 * k + l];
+      n_skw += sk[3 * k + l] * sk[3 * k + l];
+    }
+  const double teq = sqrt(c.a1 * double(n_sym) + c.a2 * double(n_skw));
+  if (teq < c.tY + c.tH * pn) {
+    p = pn;
+  } else {
+    const double den = c.tH + 2.0 * c.a1 * c.mu;
+    p = pn * (2.0 * c.a1 * c.mu) / den + (teq - c.tY) / den;
+    const double R1 = c.tY + c.tH * p;
+    const T fs = T(R1 / (R1 + 2.0 * (p - pn) * c.a1 * c.mu));
+    const T fk = T(R1 / (R1 + 2.0 * (p - pn) * c.a2 * c.kap));
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+        t[3 * k + l] = (k == l ? vol : T(0)) + fs * ss[3 * k + l] + fk * sk[3 * k + l];
+  }
+  // micro level: full couple stress, Eq. 17
+  T ms[9], mk[9];
+  T m_sym = 0, m_skw = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      ms[3 * k + l] = T(0.5) * (m[3 * k + l] + m[3 * l + k]);
+      mk[3 * k + l] = T(0.5) * (m[3 * k + l] - m[3 * l + k]);
+      m_sym += ms[3 * k + l] * ms[3 * k + l];
+      m_skw += mk[3 * k + l] * mk[3 * k + l];
+    }
+  const double meq = sqrt(c.b1 * double(m_sym) + c.b2 * double(m_skw));
+  if (meq < c.mY + c.mH * qn) {
+    q = qn;
+  } else {
+    const double bgb = c.b1 * (c.gam + c.bet);
+    const double den = c.mH + bgb;
+    q = qn * bgb / den + (meq - c.mY) / den;
+    const double R2 = c.mY + c.mH * q;
+    const T gs = T(R2 / (R2 + (q - qn) * bgb));
+    const T gk = T(R2 / (R2 + (q - qn) * c.b2gmb));
+#pragma unroll
+    for (int i = 0; i < 9; ++i) m[i] = gs * ms[i] + gk * mk[i];
+  }
+}
+
+// t_eq and m_eq of a final state (Eqs. 14, 17), FP64.
+template <class T>
+__device__ __forceinline__ void equivalent_stresses(const PhaseC& c, const T* t, const T* m,
+                                                    double& teq, double& meq) {
+  const double vol = (double(t[0]) + double(t[4]) + double(t[8])) / 3.0;
+  double n_sym = 0, n_skw = 0, m_sym = 0, m_skw = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const double skl = double(t[3 * k + l]) - (k == l ? vol : 0.0);
+      const double slk = double(t[3 * l + k]) - (k == l ? vol : 0.0);
+      n_sym += 0.25 * (skl + slk) * (skl + slk);
+      n_skw += 0.25 * (skl - slk) * (skl - slk);
+      const double a = 0.5 * (double(m[3 * k + l]) + double(m[3 * l + k]));
+      const double b = 0.5 * (double(m[3 * k + l]) - double(m[3 * l + k]));
+      m_sym += a * a;
+      m_skw += b * b;
+    }
+  teq = sqrt(c.a1 * n_sym + c.a2 * n_skw);
+  meq = sqrt(c.b1 * m_sym + c.b2 * m_skw);
+}
+
+// ---------------------------------------------------------------------------
+// Green operator at one frequency.
+//   Sources of the reference-medium balance equations (Eq. 2 with the
+//   polarization as eigenstress): bu_l = i xi_k tau_kl,
+//   bp_l = i xi_k mu_kl + eps_lkm tau_km.  The 6x6 Hermitian symbol
+//     K = [[(mu0+k0) s^2 I + (lam0+mu0-k0) xi xi^T, -2 i k0 W],
+//          [-2 i k0 W, (g0 s^2 + 4 k0) I + (a0 + b0) xi xi^T]],  W v = xi x v,
+//   splits into a longitudinal part along n = xi/s and a 2x2 transverse
+//   block, solved in closed form.  Then e_kl = i xi_k u_l + eps_lkm phi_m and
+//   g_kl = i xi_l phi_k (Eq. 1), scaled by `scale` (the inverse-DFT 1/N).
+// ---------------------------------------------------------------------------
+struct RefC {
+  double lam, mu, kap, alp, bet, gam;
+};
+
+template <class T>
+__device__ __forceinline__ void green_apply(const RefC& r, T x1, T x2, T x3, T scale,
+                                            cx<T>* tau /*9 in, e out*/, cx<T>* mu /*9 in, g out*/) {
+  const T xi[3] = {x1, x2, x3};
+  cx<T> bu[3], bp[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    cx<T> su = {0, 0}, sp = {0, 0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      su = cadd(su, cscale(tau[3 * k + l], xi[k]));
+      sp = cadd(sp, cscale(mu[3 * k + l], xi[k]));
+    }
+    bu[l] = mul_i(su);
+    bp[l] = mul_i(sp);
+  }
+  // eps_lkm tau_km
+  bp[0] = cadd(bp[0], csub(tau[5], tau[7]));
+  bp[1] = cadd(bp[1], csub(tau[6], tau[2]));
+  bp[2] = cadd(bp[2], csub(tau[1], tau[3]));
+
+  const T s2 = x1 * x1 + x2 * x2 + x3 * x3;
+  const T s = sqrt(s2);
+  const T n[3] = {x1 / s, x2 / s, x3 / s};
+  const T lam = T(r.lam), mu0 = T(r.mu), kap = T(r.kap), alp = T(r.alp), bet = T(r.bet),
+          gam = T(r.gam);
+  cx<T> nbu = {0, 0}, nbp = {0, 0};
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    nbu = cadd(nbu, cscale(bu[l], n[l]));
+    nbp = cadd(nbp, cscale(bp[l], n[l]));
+  }
+  const T a = (mu0 + kap) * s2;
+  const T c = gam * s2 + T(4) * kap;
+  const T D = s2 * ((mu0 + kap) * gam * s2 + T(4) * mu0 * kap);
+  const T iD = T(1) / D;
+  const T iL = T(1) / ((lam + T(2) * mu0) * s2);
+  const T iP = T(1) / ((alp + bet + gam) * s2 + T(4) * kap);
+  const T ks2 = T(2) * kap * s;
+  // n x b (the longitudinal part drops out of the cross product)
+  cx<T> nxu[3], nxp[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const int a1 = (l + 1) % 3, a2 = (l + 2) % 3;
+    nxu[l] = csub(cscale(bu[a2], n[a1]), cscale(bu[a1], n[a2]));
+    nxp[l] = csub(cscale(bp[a2], n[a1]), cscale(bp[a1], n[a2]));
+  }
+  cx<T> u[3], ph[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const cx<T> buT = csub(bu[l], cscale(nbu, n[l]));
+    const cx<T> bpT = csub(bp[l], cscale(nbp, n[l]));
+    const cx<T> uT = cscale(cadd(cscale(buT, c), mul_i(cscale(nxp[l], ks2))), iD);
+    const cx<T> pT = cscale(cadd(mul_i(cscale(nxu[l], ks2)), cscale(bpT, a)), iD);
+    u[l] = cadd(uT, cscale(nbu, n[l] * iL));
+    ph[l] = cadd(pT, cscale(nbp, n[l] * iP));
+  }
+  // e_kl = i xi_k u_l + eps_lkm phi_m ; g_kl = i xi_l phi_k
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      tau[3 * k + l] = mul_i(cscale(u[l], xi[k]));
+      mu[3 * k + l] = mul_i(cscale(ph[k], xi[l]));
+    }
+  tau[1] = csub(tau[1], ph[2]);
+  tau[2] = cadd(tau[2], ph[1]);
+  tau[3] = cadd(tau[3], ph[2]);
+  tau[5] = csub(tau[5], ph[0]);
+  tau[6] = csub(tau[6], ph[1]);
+  tau[7] = cadd(tau[7], ph[0]);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    tau[i] = cscale(tau[i], scale);
+    mu[i] = cscale(mu[i], scale);
+  }
+}
+
+}  // namespace mp

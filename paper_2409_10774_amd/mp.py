@@ -1,0 +1,250 @@
+"""Python binding of the C ABI in include/mp.h (argument marshalling only).
+
+Every step of the solver runs in the HIP library `_lib/libmp.so`; PyTorch
+supplies device memory (the plan's workspace) and the stream.  Importing this
+module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libmp.so")
+
+MP_OK, MP_E_INVALID, MP_E_NOMEM, MP_E_DEVICE, MP_E_NOT_CONVERGED, MP_E_DIVERGED, MP_E_STATE = range(7)
+STATUS_NAMES = {0: "MP_OK", 1: "MP_E_INVALID", 2: "MP_E_NOMEM", 3: "MP_E_DEVICE",
+                4: "MP_E_NOT_CONVERGED", 5: "MP_E_DIVERGED", 6: "MP_E_STATE"}
+MP_FP64, MP_MIXED = 0, 1
+MP_ERR_LOCAL, MP_ERR_AVERAGE = 0, 1
+MP_REF_PHASE_MEAN, MP_REF_VOLUME_MEAN, MP_REF_EXPLICIT = 0, 1, 2
+FIELDS = {"e": 0, "g": 1, "t": 2, "m": 3, "p": 4, "q": 5}
+
+
+class mp_phase(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("lam", "mu", "kappa", "alpha", "beta", "gamma",
+                                          "tY", "tH", "mY", "mH", "a1", "b1")]
+
+
+class mp_problem(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double), ("phase", C.POINTER(C.c_uint8)),
+                ("n_phases", C.c_int32), ("phases", C.POINTER(mp_phase)), ("ref_mode", C.c_int32),
+                ("ref", mp_phase), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("err_norm", C.c_int32), ("precision", C.c_int32)]
+
+
+class MPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                          "(run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    sig = {
+        "mp_plan_workspace_size": (C.c_int, [C.POINTER(mp_problem), C.POINTER(C.c_size_t)]),
+        "mp_plan_create": (C.c_int, [C.POINTER(mp_problem), vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "mp_solve_load_path": (C.c_int, [vp, i32, dp, dp, dp, C.POINTER(i32)]),
+        "mp_homogenized_response": (C.c_int, [vp, i32, dp]),
+        "mp_get_fields": (C.c_int, [vp, i32, dp]),
+        "mp_set_fixed_iterations": (C.c_int, [vp, i32]),
+        "mp_plan_steps": (C.c_int, [vp, C.POINTER(i32)]),
+        "mp_green_apply": (C.c_int, [vp, vp, vp]),
+        "mp_spectrum_forward": (C.c_int, [vp, vp, vp]),
+        "mp_radial_return": (C.c_int, [vp, i64] + [vp] * 13),
+        "mp_profile": (C.c_int, [vp, i32]),
+        "mp_profile_read": (C.c_int, [vp, i32, dp, C.POINTER(C.c_int64)]),
+        "mp_plan_destroy": (None, [vp]),
+        "mp_last_error": (C.c_char_p, []),
+        "mp_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def check(status):
+    if status != MP_OK:
+        raise MPError(status, lib.mp_last_error().decode())
+    return status
+
+
+def _phase_struct(p) -> mp_phase:
+    if hasattr(p, "as_tuple"):
+        vals = p.as_tuple()
+    elif isinstance(p, dict):
+        vals = tuple(p[k] for k in ("lam", "mu", "kappa", "alpha", "beta", "gamma",
+                                    "tY", "tH", "mY", "mH", "a1", "b1"))
+    else:
+        vals = tuple(p)
+    return mp_phase(*[float(v) for v in vals])
+
+
+def make_problem(phase_map, phases, h=1.0, tol=1e-8, max_iter=20000, err_norm="local",
+                 ref_mode="phase_mean", ref=None, precision="fp64"):
+    """Build an mp_problem (and keep its host arrays alive on the returned object)."""
+    pm = np.ascontiguousarray(phase_map, dtype=np.uint8)
+    if pm.ndim != 3:
+        raise ValueError("phase_map must be (n2, n1, n0)")
+    n2, n1, n0 = pm.shape
+    arr = (mp_phase * len(phases))(*[_phase_struct(p) for p in phases])
+    prob = mp_problem()
+    prob.n[0], prob.n[1], prob.n[2] = n0, n1, n2
+    prob.h = float(h)
+    prob.phase = pm.ctypes.data_as(C.POINTER(C.c_uint8))
+    prob.n_phases = len(phases)
+    prob.phases = C.cast(arr, C.POINTER(mp_phase))
+    prob.ref_mode = {"phase_mean": MP_REF_PHASE_MEAN, "volume_mean": MP_REF_VOLUME_MEAN,
+                     "explicit": MP_REF_EXPLICIT}[ref_mode]
+    if ref is not None:
+        prob.ref = mp_phase(*(list(float(v) for v in ref) + [0.0] * (12 - len(ref))))
+    prob.tol = float(tol)
+    prob.max_iter = int(max_iter)
+    prob.err_norm = {"local": MP_ERR_LOCAL, "average": MP_ERR_AVERAGE}[err_norm]
+    prob.precision = {"fp64": MP_FP64, "mixed": MP_MIXED}[precision]
+    prob._keep = (pm, arr)
+    return prob
+
+
+def mp_plan_workspace_size(prob) -> int:
+    n = C.c_size_t()
+    check(lib.mp_plan_workspace_size(C.byref(prob), C.byref(n)))
+    return n.value
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One solver plan on a GPU: owns a torch workspace, wraps the C plan."""
+
+    def __init__(self, phase_map, phases, device="cuda:0", stream=None, **kw):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.prob = make_problem(phase_map, phases, **kw)
+        pm = self.prob._keep[0]
+        self.shape = pm.shape
+        self.nvox = int(pm.size)
+        nbytes = mp_plan_workspace_size(self.prob)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        check(lib.mp_plan_create(C.byref(self.prob), _ptr(self.workspace), nbytes,
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    # -- Alg. 2 -------------------------------------------------------------
+    def solve(self, times, E, G, raise_on_error=True):
+        times = np.ascontiguousarray(times, dtype=np.float64)
+        S = len(times) - 1
+        E = np.ascontiguousarray(np.asarray(E, np.float64).reshape(S, 9))
+        G = np.ascontiguousarray(np.asarray(G, np.float64).reshape(S, 9))
+        it = (C.c_int32 * max(S, 1))()
+        dp = C.POINTER(C.c_double)
+        st = lib.mp_solve_load_path(self.handle, S, times.ctypes.data_as(dp), E.ctypes.data_as(dp),
+                                    G.ctypes.data_as(dp), it)
+        iters = [int(it[i]) for i in range(S)]
+        if raise_on_error:
+            check(st)
+            return iters
+        return st, iters
+
+    def steps(self):
+        n = C.c_int32()
+        check(lib.mp_plan_steps(self.handle, C.byref(n)))
+        return n.value
+
+    def response(self, step):
+        out = (C.c_double * 42)()
+        check(lib.mp_homogenized_response(self.handle, int(step), out))
+        return np.array(out[:])
+
+    def responses(self):
+        return np.array([self.response(s) for s in range(1, self.steps() + 1)])
+
+    def field(self, name):
+        n = self.nvox
+        count = 9 * n if name in ("e", "g", "t", "m") else n
+        out = np.empty(count, np.float64)
+        check(lib.mp_get_fields(self.handle, FIELDS[name],
+                                out.ctypes.data_as(C.POINTER(C.c_double))))
+        if count == n:
+            return out.reshape(self.shape)
+        return out.reshape((9,) + self.shape)
+
+    def set_fixed_iterations(self, n):
+        check(lib.mp_set_fixed_iterations(self.handle, int(n)))
+
+    # -- single steps of the hot path ---------------------------------------
+    def green_apply(self, tau_mu):
+        """tau_mu: torch float64 (18, n2, n1, n0) on the plan's device."""
+        x = tau_mu.contiguous()
+        assert x.dtype == self.torch.float64 and x.numel() == 18 * self.nvox and x.device == self.device
+        out = self.torch.empty_like(x)
+        check(lib.mp_green_apply(self.handle, _ptr(x), _ptr(out)))
+        return out
+
+    def spectrum_forward(self, fields):
+        x = fields.contiguous()
+        assert x.dtype == self.torch.float64 and x.numel() == 18 * self.nvox and x.device == self.device
+        n2, n1, n0 = self.shape
+        out = self.torch.empty((18, n2, n1, n0 // 2, 2), dtype=self.torch.float64, device=self.device)
+        check(lib.mp_spectrum_forward(self.handle, _ptr(x), _ptr(out)))
+        return self.torch.view_as_complex(out)
+
+    def radial_return(self, phase, e, g, e_n, g_n, t_n, m_n, p_n, q_n):
+        """Alg. 1 on n independent points; tensors on the plan's device, float64
+        (9, n) / (n,), phase uint8 (n,).  Returns (t, m, p, q)."""
+        T = self.torch
+        n = phase.numel()
+        ins = [x.contiguous() for x in (e, g, e_n, g_n, t_n, m_n, p_n, q_n)]
+        for x in ins:
+            assert x.dtype == T.float64 and x.device == self.device
+        ph = phase.contiguous()
+        assert ph.dtype == T.uint8 and ph.device == self.device
+        t = T.empty((9, n), dtype=T.float64, device=self.device)
+        m = T.empty_like(t)
+        p = T.empty(n, dtype=T.float64, device=self.device)
+        q = T.empty_like(p)
+        check(lib.mp_radial_return(self.handle, n, _ptr(ph), *[_ptr(x) for x in ins],
+                                   _ptr(t), _ptr(m), _ptr(p), _ptr(q)))
+        return t, m, p, q
+
+    KERNELS = ("y_fwd", "z_fwd", "green", "z_inv", "y_inv", "x_pass", "err_reduce")
+
+    def profile(self, enable=True):
+        check(lib.mp_profile(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel: (total ms, launches)} accumulated since profile(True)."""
+        ms = (C.c_double * 7)()
+        n = (C.c_int64 * 7)()
+        check(lib.mp_profile_read(self.handle, 7, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(self.KERNELS)}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.mp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+mp_version = lambda: lib.mp_version().decode()

@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI (no GPU needed): every entry point declared
+in include/mp.h is exported by the built library, and problem validation
+(workspace sizing runs no device code) rejects what it must."""
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "mp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mp_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2409_10774_amd import mp
+    names = declared()
+    assert "mp_plan_create" in names and "mp_solve_load_path" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", mp.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\b(mp_[a-z_]+)\b", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(mp.lib, n)
+
+
+def base_problem(**kw):
+    from paper_2409_10774_amd import mp, workloads as W
+    wl = W.single_sphere_16()
+    phases = kw.pop("phases", wl.phases)
+    pm = kw.pop("phase_map", wl.phase_map)
+    return mp.make_problem(pm, phases, **kw)
+
+
+def test_workspace_size_scales_with_grid():
+    from paper_2409_10774_amd import mp
+    n = mp.mp_plan_workspace_size(base_problem())
+    # 18 spectra + 4 x 18 real fields + 4 scalar fields, FP64, 16^3 voxels
+    assert n >= (18 + 4 * 18 + 4) * 8 * 16 ** 3
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(tol=0.0), "tol"),
+    (dict(max_iter=0), "max_iter"),
+    (dict(precision="mixed"), "MP_FP64"),
+    (dict(h=-1.0), "h must"),
+])
+def test_rejects_bad_problem(change, msg):
+    from paper_2409_10774_amd import mp
+    with pytest.raises(mp.MPError) as ei:
+        mp.mp_plan_workspace_size(base_problem(**change))
+    assert ei.value.status == mp.MP_E_INVALID and msg in str(ei.value)
+
+
+def bad_phase(**kw):
+    from paper_2409_10774_amd import workloads as W
+    p = W.matrix_phase()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw", [dict(kappa=0.0), dict(mu=-1.0), dict(beta=5.0, gamma=4.0),
+                                dict(alpha=0.1), dict(tY=0.0), dict(a1=0.0), dict(lam=math.nan),
+                                dict(tH=-0.1)])
+def test_rejects_bad_phase(kw):
+    from paper_2409_10774_amd import mp, workloads as W
+    wl = W.single_sphere_16()
+    with pytest.raises(mp.MPError) as ei:
+        mp.mp_plan_workspace_size(base_problem(phases=[bad_phase(**kw), wl.phases[1]]))
+    assert ei.value.status == mp.MP_E_INVALID
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 10), (16, 14, 16), (5, 16, 16), (16, 16, 512), (2, 4, 4), (16, 16, 20)])
+def test_rejects_unsupported_grid(shape):
+    from paper_2409_10774_amd import mp, workloads as W
+    wl = W.single_sphere_16()
+    with pytest.raises(mp.MPError):
+        mp.mp_plan_workspace_size(base_problem(phase_map=np.zeros(shape, np.uint8)))
+
+
+def test_accepts_beta_equal_gamma_and_elastic_alpha():
+    from paper_2409_10774_amd import mp
+    p = bad_phase(alpha=0.3, tY=math.inf, mY=math.inf)    # alpha allowed when micro-elastic
+    assert mp.mp_plan_workspace_size(base_problem(phases=[p, p])) > 0

@@ -183,13 +183,23 @@ __device__ __forceinline__ void fft_inplace(cx<T>* buf, int N, int nb, int ps, i
 // ---------------------------------------------------------------------------
 // Alg. 1: micropolar radial return at one voxel.
 // ---------------------------------------------------------------------------
-struct PhaseC {
-  double lam, mu, kap, alp, bet, gam;
-  double tY, tH, mY, mH, a1, b1;
-  double a2;      // a1 mu / kappa
-  double b2;      // b1 (gamma + beta) / (gamma - beta); 0 when gamma == beta
-  double b2gmb;   // b2 (gamma - beta); b1 (gamma + beta) when gamma == beta
+// Constants of one phase, split by level so a lane loads only its half.
+struct MacroC {
+  double lam, mu, kap;   // Eq. 6 moduli of A
+  double tY, tH;         // Eq. 15 yield stress and hardening
+  double a1, a2;         // Eq. 14 weights, a2 = a1 mu / kappa (Alg. 1)
   double pad;
+};
+struct MicroC {
+  double alp, bet, gam;  // Eq. 6 moduli of B
+  double mY, mH;         // Eq. 18 yield stress and hardening
+  double b1;             // Eq. 17 weight
+  double b2;             // b1 (gamma + beta) / (gamma - beta); 0 when gamma == beta
+  double b2gmb;          // b2 (gamma - beta); b1 (gamma + beta) when gamma == beta
+};
+struct PhaseC {
+  MacroC t;
+  MicroC m;
 };
 
 // t_kl = lam tr(e) d_kl + (mu + kappa) e_kl + (mu - kappa) e_lk      (Eq. 6)
@@ -214,21 +224,16 @@ __device__ __forceinline__ void apply_B(T alp, T bet, T gam, const T* g, T* m) {
       m[3 * k + l] = bet * g[3 * k + l] + gam * g[3 * l + k] + (k == l ? alp * tr : T(0));
 }
 
-// Trial stresses from the history base bt = t_n - A e_n, bm = m_n - B g_n
-// (Eq. 30: t_trial = t_n + A (e - e_n) = bt + A e), then the macro and
-// micro returns with the closed-form p, q of Eq. 32.
+// Macro level of Alg. 1 at one voxel: trial stress from the history base
+// bt = t_n - A e_n (Eq. 30: t_trial = t_n + A (e - e_n) = bt + A e), Eq. 14
+// equivalent stress, closed-form p of Eq. 32, radial scaling of the
+// deviatoric sym / skew parts.
 template <class T>
-__device__ __forceinline__ void return_map(const PhaseC& c, const T* e, const T* g, const T* bt,
-                                           const T* bm, double pn, double qn, T* t, T* m,
-                                           double& p, double& q) {
+__device__ __forceinline__ void macro_return(const MacroC& c, const T* e, const T* bt, double pn,
+                                             T* t, double& p) {
   apply_A<T>(T(c.lam), T(c.mu), T(c.kap), e, t);
-  apply_B<T>(T(c.alp), T(c.bet), T(c.gam), g, m);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    t[i] += bt[i];
-    m[i] += bm[i];
-  }
-  // macro level: deviatoric sym / skew parts, Eq. 14
+  for (int i = 0; i < 9; ++i) t[i] += bt[i];
   const T vol = (t[0] + t[4] + t[8]) / T(3);
   T ss[9], sk[9];
   T n_sym = 0, n_skw = 0;
@@ -258,7 +263,16 @@ __device__ __forceinline__ void return_map(const PhaseC& c, const T* e, const T*
       for (int l = 0; l < 3; ++l)
         t[3 * k + l] = (k == l ? vol : T(0)) + fs * ss[3 * k + l] + fk * sk[3 * k + l];
   }
-  // micro level: full couple stress, Eq. 17
+}
+
+// Micro level of Alg. 1: trial couple stress bm + B g, Eq. 17 on the full
+// couple stress, closed-form q of Eq. 32, radial scaling of sym / skew parts.
+template <class T>
+__device__ __forceinline__ void micro_return(const MicroC& c, const T* g, const T* bm, double qn,
+                                             T* m, double& q) {
+  apply_B<T>(T(c.alp), T(c.bet), T(c.gam), g, m);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) m[i] += bm[i];
   T ms[9], mk[9];
   T m_sym = 0, m_skw = 0;
 #pragma unroll
@@ -285,6 +299,15 @@ __device__ __forceinline__ void return_map(const PhaseC& c, const T* e, const T*
   }
 }
 
+// Alg. 1 at one voxel: the two levels are independent.
+template <class T>
+__device__ __forceinline__ void return_map(const PhaseC& c, const T* e, const T* g, const T* bt,
+                                           const T* bm, double pn, double qn, T* t, T* m,
+                                           double& p, double& q) {
+  macro_return<T>(c.t, e, bt, pn, t, p);
+  micro_return<T>(c.m, g, bm, qn, m, q);
+}
+
 // t_eq and m_eq of a final state (Eqs. 14, 17), FP64.
 template <class T>
 __device__ __forceinline__ void equivalent_stresses(const PhaseC& c, const T* t, const T* m,
@@ -304,8 +327,8 @@ __device__ __forceinline__ void equivalent_stresses(const PhaseC& c, const T* t,
       m_sym += a * a;
       m_skw += b * b;
     }
-  teq = sqrt(c.a1 * n_sym + c.a2 * n_skw);
-  meq = sqrt(c.b1 * m_sym + c.b2 * m_skw);
+  teq = sqrt(c.t.a1 * n_sym + c.t.a2 * n_skw);
+  meq = sqrt(c.m.b1 * m_sym + c.m.b2 * m_skw);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,9 +20,13 @@
 
 namespace mp {
 
-constexpr int kMaxPts = 16;      // FFT points a thread holds in one stage
-constexpr int kNPart = 48;       // per-block partials of the error measure
+constexpr int kMaxPts = 8;       // FFT points a thread holds in one stage
+constexpr int kNPart = 30;       // per-block partials of the error measure (2 levels x 15)
 constexpr int kNAvg = 40;        // per-block partials of the step averages
+
+struct ErrMacro {
+  double v[18];   // prescribed E then Gamma of the step
+};
 
 struct Ctl {
   int done;       // 0 running, 1 converged / fixed count reached, 2 max_iter, 3 diverged
@@ -75,17 +79,51 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // x pass: rows of n0 voxels, all 18 components.  LDS holds 9 packed complex
 // pencils per row: pencil q = field 2q + i field 2q+1 (two real transforms
-// in one complex transform).
+// in one complex transform).  Two lanes per voxel: lane level 0 runs the
+// macro level of Alg. 1 (e -> t, tau), level 1 the micro level (gamma -> m,
+// mu); the levels are independent, which halves each lane's live state.
+// Each lane prefetches its old strain, history base and p_n / q_n before
+// the transforms so the loads overlap them.
+constexpr int kLev = 15;   // per-level partials: see k_xpass
 template <class T, int MODE>
 __global__ void __launch_bounds__(512) k_xpass(XArgs<T> a) {
   if (a.ctl && a.ctl->done) return;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  __shared__ double red[8][kNPart];
+  T* ldr = reinterpret_cast<T*>(smem_raw);   // scalar view: field c of voxel v at 2 (q n0 ...) + (c & 1)
+  __shared__ double red[8][2][kLev];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n0 = a.n0, nh = a.nh, rows = a.rows;
+  const int vpb = rows * n0;
   const long row0 = (long)blockIdx.x * rows;
   const int npk = 9 * rows;
+  // lanes [0, vpad) run the macro level, [vpad, 2 vpad) the micro level;
+  // vpad is a multiple of 64, so the level is uniform over each wavefront
+  const int vpad = nthr >> 1;
+  const int lvl = __builtin_amdgcn_readfirstlane(tid >= vpad ? 1 : 0);
+  const int v = tid - lvl * vpad;
+  const bool own = v < vpb;
+  const int vr = own ? v / n0 : 0, vx = own ? v % n0 : 0;
+  // 32-bit voxel offset into wave-uniform component bases (the grid holds
+  // at most 2^24 voxels)
+  const int gi = int((row0 + vr) * n0 + vx);
+  const long nv = a.nvox;
+  T* const Elv = a.E + (long)lvl * 9 * nv;
+  const T* const Blv = a.base + (long)lvl * 9 * nv;
+
+  // prefetch this lane's history (ITER, INIT)
+  T eo[9], bb[9];
+  double hn = 0.0;
+  int ph = 0;
+  if ((MODE == X_ITER || MODE == X_INIT) && own) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      eo[c] = Elv[c * nv + gi];
+      bb[c] = Blv[c * nv + gi];
+    }
+    hn = a.pq[lvl * nv + gi];
+    ph = a.phase[gi];
+  }
 
   if (MODE == X_ITER || MODE == X_INV_ONLY) {
     // half spectra -> packed full spectra Z = A + i B, Z(n0 - k) = conj A + i conj B
@@ -102,113 +140,130 @@ __global__ void __launch_bounds__(512) k_xpass(XArgs<T> a) {
         pen[nh] = cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    fft_inplace<T, true, kMaxPts>(lds, n0, npk, 1, n0, false, a.sched, a.tw, tid, nthr);
+    fft_inplace<T, true, 8>(lds, n0, npk, 1, n0, false, a.sched, a.tw, tid, nthr);
   }
 
-  double acc[kNPart];
-  if (MODE == X_ITER) {
-#pragma unroll
-    for (int j = 0; j < kNPart; ++j) acc[j] = 0.0;
-  }
+  // LDS scalar slot of field c (0..17) of this lane's voxel
+  auto slot = [&](int c) { return 2 * ((vr * 9 + (c >> 1)) * n0 + vx) + (c & 1); };
 
   if (MODE == X_INV_ONLY) {
-    for (int v = tid; v < rows * n0; v += nthr) {
-      const int r = v / n0, x = v % n0;
-      const long gi = (row0 + r) * n0 + x;
+    if (own)
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        const cx<T> z = lds[(r * 9 + q) * n0 + x];
-        a.fout[(2 * q) * a.nvox + gi] = z.re;
-        a.fout[(2 * q + 1) * a.nvox + gi] = z.im;
-      }
-    }
+      for (int c = 0; c < 9; ++c) a.fout[(lvl * 9 + c) * nv + gi] = ldr[slot(lvl * 9 + c)];
     return;
   }
 
-  // pointwise part
-  for (int v = tid; v < rows * n0; v += nthr) {
-    const int r = v / n0, x = v % n0;
-    const long gi = (row0 + r) * n0 + x;
-    T f[18];
-    if (MODE == X_FWD_ONLY) {
+  // per-level partials of the error measure: |da|, |db| (max), |da|, |db| (sum),
+  // |a|^2, |b|^2, b (sum), with (a, b) = (e, t) on the macro level and
+  // (gamma, m) on the micro level.  Reduced over the wavefront as soon as
+  // they exist (fixed butterfly order), then over the waves in order.
+  const int lane = tid & 63, wv = tid >> 6, nw = (nthr + 63) >> 6;
+  auto wave_put = [&](int j, double x) {
 #pragma unroll
-      for (int c = 0; c < 18; ++c) f[c] = a.fin[c * a.nvox + gi];
-    } else {
-      T e[18];
-      if (MODE == X_ITER) {
+    for (int L = 0; L < 2; ++L) {
+      const double y = (lvl == L && own) ? x : 0.0;
+      const double z = (j < 2) ? wave_max(y) : wave_sum(y);
+      if (lane == 0) red[wv][L][j] = z;
+    }
+  };
+
+  {
+    T e[9];
+    if (own) {
+      if (MODE == X_FWD_ONLY) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          const cx<T> z = lds[(r * 9 + q) * n0 + x];
-          e[2 * q] = z.re + T(a.mac[2 * q]);
-          e[2 * q + 1] = z.im + T(a.mac[2 * q + 1]);
-        }
+        for (int c = 0; c < 9; ++c) e[c] = a.fin[(lvl * 9 + c) * nv + gi];
+      } else if (MODE == X_ITER) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) e[c] = ldr[slot(lvl * 9 + c)] + T(a.mac[lvl * 9 + c]);
       } else {  // X_INIT: first iterate of the step (Alg. 2)
 #pragma unroll
-        for (int c = 0; c < 18; ++c) {
-          const T cur = a.E[c * a.nvox + gi];
-          const T old = a.Eprev[c * a.nvox + gi];
-          e[c] = a.first ? T(a.mac[c]) : T(cur + T(a.r) * (cur - old));
-          a.Eprev[c * a.nvox + gi] = cur;
-        }
-      }
-      const PhaseC pc = a.params[a.phase[gi]];
-      T bt[9], bm[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        bt[c] = a.base[c * a.nvox + gi];
-        bm[c] = a.base[(9 + c) * a.nvox + gi];
-      }
-      const double pn = a.pq[gi], qn = a.pq[a.nvox + gi];
-      T t[9], m[9];
-      double p, q;
-      return_map<T>(pc, e, e + 9, bt, bm, pn, qn, t, m, p, q);
-      if (MODE == X_ITER) {
-        T eo[18];
-#pragma unroll
-        for (int c = 0; c < 18; ++c) eo[c] = a.E[c * a.nvox + gi];
-        T to[9], mo[9];
-        double po, qo;
-        return_map<T>(pc, eo, eo + 9, bt, bm, pn, qn, to, mo, po, qo);
-        double d0 = 0, d1 = 0, d2 = 0, d3 = 0, s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll
         for (int c = 0; c < 9; ++c) {
-          const double de = double(e[c]) - double(eo[c]);
-          const double dg = double(e[9 + c]) - double(eo[9 + c]);
-          const double dt = double(t[c]) - double(to[c]);
-          const double dm = double(m[c]) - double(mo[c]);
-          d0 += de * de; d1 += dt * dt; d2 += dg * dg; d3 += dm * dm;
-          s0 += double(e[c]) * double(e[c]);
-          s1 += double(t[c]) * double(t[c]);
-          s2 += double(e[9 + c]) * double(e[9 + c]);
-          s3 += double(m[c]) * double(m[c]);
-          acc[12 + c] += double(e[c]);
-          acc[21 + c] += double(t[c]);
-          acc[30 + c] += double(e[9 + c]);
-          acc[39 + c] += double(m[c]);
+          const long at = (lvl * 9 + c) * nv + gi;
+          const T old = a.Eprev[at];
+          e[c] = a.first ? T(a.mac[lvl * 9 + c]) : T(eo[c] + T(a.r) * (eo[c] - old));
+          a.Eprev[at] = eo[c];
         }
-        d0 = sqrt(d0); d1 = sqrt(d1); d2 = sqrt(d2); d3 = sqrt(d3);
-        acc[0] = fmax(acc[0], d0); acc[1] = fmax(acc[1], d1);
-        acc[2] = fmax(acc[2], d2); acc[3] = fmax(acc[3], d3);
-        acc[4] += d0; acc[5] += d1; acc[6] += d2; acc[7] += d3;
-        acc[8] += s0; acc[9] += s1; acc[10] += s2; acc[11] += s3;
-      }
-#pragma unroll
-      for (int c = 0; c < 18; ++c) a.E[c * a.nvox + gi] = e[c];
-      // polarization (Eq. 34): tau = t - A0 e, mu = m - B0 gamma
-      T a0e[9], b0g[9];
-      apply_A<T>(T(a.ref.lam), T(a.ref.mu), T(a.ref.kap), e, a0e);
-      apply_B<T>(T(a.ref.alp), T(a.ref.bet), T(a.ref.gam), e + 9, b0g);
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        f[c] = t[c] - a0e[c];
-        f[9 + c] = m[c] - b0g[c];
       }
     }
+    if (MODE == X_FWD_ONLY) {
+      if (own)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) lds[(r * 9 + q) * n0 + x] = cx<T>{f[2 * q], f[2 * q + 1]};
+        for (int c = 0; c < 9; ++c) ldr[slot(lvl * 9 + c)] = e[c];
+    } else {
+      // this lane's half of the phase record
+      MacroC ct;
+      MicroC cm;
+      if (lvl == 0)
+        ct = a.params[ph].t;
+      else
+        cm = a.params[ph].m;
+      T t[9];
+      double pnew;
+      if (own) {
+        if (lvl == 0)
+          macro_return<T>(ct, e, bb, hn, t, pnew);
+        else
+          micro_return<T>(cm, e, bb, hn, t, pnew);
+        // polarization (Eq. 34): tau = t - A0 e ; mu = m - B0 gamma
+        T r0[9];
+        if (lvl == 0)
+          apply_A<T>(T(a.ref.lam), T(a.ref.mu), T(a.ref.kap), e, r0);
+        else
+          apply_B<T>(T(a.ref.alp), T(a.ref.bet), T(a.ref.gam), e, r0);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          ldr[slot(lvl * 9 + c)] = t[c] - r0[c];
+          Elv[c * nv + gi] = e[c];
+        }
+      }
+      if (MODE == X_ITER) {
+        double da = 0, sa = 0, sb = 0;
+        if (own)
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            const double x = double(e[c]) - double(eo[c]);
+            da += x * x;
+            sa += double(e[c]) * double(e[c]);
+            sb += double(t[c]) * double(t[c]);
+          }
+#pragma unroll
+        for (int c = 0; c < 9; ++c) wave_put(6 + c, own ? double(t[c]) : 0.0);
+        wave_put(4, sa);
+        wave_put(5, sb);
+        da = sqrt(da);
+        wave_put(0, da);
+        wave_put(2, da);
+        // the old iterate's stresses, recomputed from the old strain (Alg. 1)
+        double db = 0;
+        if (own) {
+          T to[9];
+          double pold;
+          if (lvl == 0)
+            macro_return<T>(ct, eo, bb, hn, to, pold);
+          else
+            micro_return<T>(cm, eo, bb, hn, to, pold);
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            const double y = double(t[c]) - double(to[c]);
+            db += y * y;
+          }
+        }
+        db = sqrt(db);
+        wave_put(1, db);
+        wave_put(3, db);
+        __syncthreads();
+        if (tid < 2 * kLev) {
+          const int L = tid / kLev, j = tid % kLev;
+          double y = red[0][L][j];
+          for (int w = 1; w < nw; ++w) y = (j < 2) ? fmax(y, red[w][L][j]) : y + red[w][L][j];
+          a.partials[(long)tid * gridDim.x + blockIdx.x] = y;
+        }
+      }
+    }
   }
   __syncthreads();
-  fft_inplace<T, false, kMaxPts>(lds, n0, npk, 1, n0, false, a.sched, a.tw, tid, nthr);
+  fft_inplace<T, false, 8>(lds, n0, npk, 1, n0, false, a.sched, a.tw, tid, nthr);
   // unpack: A = (Z(k) + conj Z(-k)) / 2, B = (Z(k) - conj Z(-k)) / (2 i)
   for (int w = tid; w < npk * nh; w += nthr) {
     const int kx = w % nh, q = (w / nh) % 9, r = w / (nh * 9);
@@ -220,21 +275,73 @@ __global__ void __launch_bounds__(512) k_xpass(XArgs<T> a) {
     a.S[(2 * q + 1) * a.nspec + off] = cx<T>{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
   }
 
-  if (MODE == X_ITER) {
-    // block partials in a fixed order: wavefront butterflies, then waves in order
-    const int lane = tid & 63, wv = tid >> 6, nw = nthr >> 6;
-#pragma unroll
-    for (int j = 0; j < kNPart; ++j) {
-      const double v = (j < 4) ? wave_max(acc[j]) : wave_sum(acc[j]);
-      if (lane == 0) red[wv][j] = v;
-    }
-    __syncthreads();
-    if (tid < kNPart) {
-      double v = red[0][tid];
-      for (int w = 1; w < nw; ++w) v = (tid < 4) ? fmax(v, red[w][tid]) : v + red[w][tid];
-      a.partials[(long)blockIdx.x * kNPart + tid] = v;
-    }
+}
+
+// error measure, stage 1: block j reduces partial row j over the x-pass blocks
+__global__ void __launch_bounds__(256) k_err_rows(const double* partials, int nblk, double* tot,
+                                                  const Ctl* ctl) {
+  if (ctl->done) return;
+  __shared__ double red[4];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const bool mx = (j % kLev) < 2;
+  const double* row = partials + (long)j * nblk;
+  double v0 = 0.0, v1 = 0.0;
+  int b = tid;
+  for (; b + 256 < nblk; b += 512) {
+    const double x = row[b], y = row[b + 256];
+    v0 = mx ? fmax(v0, x) : v0 + x;
+    v1 = mx ? fmax(v1, y) : v1 + y;
   }
+  if (b < nblk) v0 = mx ? fmax(v0, row[b]) : v0 + row[b];
+  double v = mx ? fmax(v0, v1) : v0 + v1;
+  v = mx ? wave_max(v) : wave_sum(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0)
+    tot[j] = mx ? fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))
+                : ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+// error measure, stage 2 (Eqs. 36-38).  <e> = E and <gamma> = Gamma hold
+// exactly (the Green operator leaves no k = 0 fluctuation), so the averages
+// of the strain-like fields are the prescribed ones.
+__global__ void k_err_final(const double* tot, long nvox, Ctl* ctl, ErrMacro mac) {
+  if (ctl->done || threadIdx.x != 0) return;
+  const double inv = 1.0 / double(nvox);
+  double err = 0.0;
+  for (int f = 0; f < 4; ++f) {   // e, t, gamma, m
+    const int L = f / 2, b = f % 2;
+    const double* P = tot + L * kLev;
+    const double num = ctl->norm == 0 ? P[b] : P[2 + b] * inv;
+    double ea = 0.0;
+    if (num != 0.0) {
+      double mn = 0.0;
+      for (int c = 0; c < 9; ++c) {
+        const double mc = b == 0 ? mac.v[L * 9 + c] : P[6 + c] * inv;
+        mn += mc * mc;
+      }
+      double den = sqrt(mn);
+      const double rms = sqrt(P[4 + b] * inv);
+      if (den <= 1e-6 * rms) den = rms;
+      ea = num / den;
+    }
+    ctl->err_parts[f] = ea;
+    err = (ea > err || ea != ea) ? ea : err;
+  }
+  ctl->err = err;
+  const int it = ctl->iters + 1;
+  ctl->iters = it;
+  int done = 0;
+  if (ctl->fixed > 0) {
+    if (it >= ctl->fixed) done = 1;
+  } else if (!(err <= 1e4)) {
+    done = 3;
+  } else if (err <= ctl->tol) {
+    done = 1;
+  } else if (it >= ctl->max_iter) {
+    done = 2;
+  }
+  ctl->done = done;
 }
 
 // y or z pass over the half spectra: tile of L points x TX consecutive kx.
@@ -314,66 +421,6 @@ __global__ void __launch_bounds__(256) k_green(GreenArgs<T> a) {
   }
 }
 
-// error measure (Eqs. 36-38) from the x-pass partials; one block
-__global__ void __launch_bounds__(256) k_err_reduce(const double* partials, int nblk, long nvox,
-                                                    Ctl* ctl) {
-  if (ctl->done) return;
-  __shared__ double red[4][kNPart];
-  __shared__ double tot[kNPart];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int j = 0; j < kNPart; ++j) {
-    double v = (j < 4) ? 0.0 : 0.0;
-    for (int b = tid; b < nblk; b += 256) {
-      const double x = partials[(long)b * kNPart + j];
-      v = (j < 4) ? fmax(v, x) : v + x;
-    }
-    v = (j < 4) ? wave_max(v) : wave_sum(v);
-    if (lane == 0) red[wv][j] = v;
-  }
-  __syncthreads();
-  if (tid < kNPart) {
-    double v = red[0][tid];
-    for (int w = 1; w < 4; ++w) v = (tid < 4) ? fmax(v, red[w][tid]) : v + red[w][tid];
-    tot[tid] = v;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    const double inv = 1.0 / double(nvox);
-    double err = 0.0;
-    for (int f = 0; f < 4; ++f) {   // e, t, gamma, m
-      const double num = ctl->norm == 0 ? tot[f] : tot[4 + f] * inv;
-      double ea = 0.0;
-      if (num != 0.0) {
-        double mn = 0.0;
-        for (int c = 0; c < 9; ++c) {
-          const double mc = tot[12 + 9 * f + c] * inv;
-          mn += mc * mc;
-        }
-        double den = sqrt(mn);
-        const double rms = sqrt(tot[8 + f] * inv);
-        if (den <= 1e-6 * rms) den = rms;
-        ea = num / den;
-      }
-      ctl->err_parts[f] = ea;
-      err = (ea > err || ea != ea) ? ea : err;
-    }
-    ctl->err = err;
-    const int it = ctl->iters + 1;
-    ctl->iters = it;
-    int done = 0;
-    if (ctl->fixed > 0) {
-      if (it >= ctl->fixed) done = 1;
-    } else if (!(err <= 1e4)) {
-      done = 3;
-    } else if (err <= ctl->tol) {
-      done = 1;
-    } else if (it >= ctl->max_iter) {
-      done = 2;
-    }
-    ctl->done = done;
-  }
-}
-
 __global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm) {
   ctl->done = 0;
   ctl->iters = 0;
@@ -420,8 +467,8 @@ __global__ void __launch_bounds__(256) k_commit(CommitArgs<T> a) {
     double p, q;
     return_map<T>(pc, e, e + 9, bt, bm, a.pq[gi], a.pq[a.nvox + gi], t, m, p, q);
     T ae[9], bg[9];
-    apply_A<T>(T(pc.lam), T(pc.mu), T(pc.kap), e, ae);
-    apply_B<T>(T(pc.alp), T(pc.bet), T(pc.gam), e + 9, bg);
+    apply_A<T>(T(pc.t.lam), T(pc.t.mu), T(pc.t.kap), e, ae);
+    apply_B<T>(T(pc.m.alp), T(pc.m.bet), T(pc.m.gam), e + 9, bg);
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       a.base[c * a.nvox + gi] = t[c] - ae[c];
@@ -490,8 +537,8 @@ __global__ void __launch_bounds__(256) k_rrm_points(long n, const uint8_t* phase
     env[c] = en[c * n + i];
     env[9 + c] = gn[c * n + i];
   }
-  apply_A<T>(T(pc.lam), T(pc.mu), T(pc.kap), env, ae);
-  apply_B<T>(T(pc.alp), T(pc.bet), T(pc.gam), env + 9, bg);
+  apply_A<T>(T(pc.t.lam), T(pc.t.mu), T(pc.t.kap), env, ae);
+  apply_B<T>(T(pc.m.alp), T(pc.m.bet), T(pc.m.gam), env + 9, bg);
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
     bt[c] = tn[c * n + i] - ae[c];

@@ -59,7 +59,7 @@ bool fits(int N, int nb, int nthr, const std::vector<int>& radices) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t S, E, Eprev, base, pq, out_tm, out_pq, phase, params, tw, partials, ctl, resp, total;
+  size_t S, E, Eprev, base, pq, out_tm, out_pq, phase, params, tw, partials, ctl, tot, resp, total;
 };
 
 struct Geometry {
@@ -80,7 +80,7 @@ struct mp_plan_s {
   hipStream_t stream;
   unsigned char* ws;
   cx<double>* S;
-  double *E, *Eprev, *base, *pq, *out_tm, *out_pq, *partials, *resp;
+  double *E, *Eprev, *base, *pq, *out_tm, *out_pq, *partials, *tot, *resp;
   uint8_t* phase;
   PhaseC* params;
   cx<double>* tw0;
@@ -155,14 +155,14 @@ mp_status validate(const mp_problem* p, Geometry* g) {
   radix_schedule(G.n0, &G.s0, &r0);
   radix_schedule(G.n1, &G.s1, &r1);
   radix_schedule(G.n2, &G.s2, &r2);
-  // x pass: rows per block (a divisor of n1 n2) and threads
+  // x pass: rows per block (a divisor of n1 n2), two lanes per voxel
   const long nrows = long(G.n1) * G.n2;
-  int rows = std::max(1, 256 / G.n0);
+  int rows = std::max(1, 128 / G.n0);
   while (rows > 1 && nrows % rows) --rows;
   G.rows = rows;
-  G.xthreads = 256;
-  if (!fits(G.n0, 9 * rows, 256, r0)) G.xthreads = 512;
-  if (!fits(G.n0, 9 * rows, G.xthreads, r0)) return fail(MP_E_INVALID, "x pass does not fit");
+  G.xthreads = 2 * ((rows * G.n0 + 63) / 64 * 64);
+  if (G.xthreads > 512 || !fits(G.n0, 9 * rows, G.xthreads, r0))
+    return fail(MP_E_INVALID, "x pass does not fit");
   G.xblocks = int(nrows / rows);
   // y / z passes: tile width TX | nh
   auto pick_tx = [&](int L, const std::vector<int>& rad) {
@@ -194,6 +194,7 @@ Layout layout(const Geometry& g) {
   L.tw = take(size_t(g.n0 + g.n1 + g.n2) * sizeof(cx<double>));
   L.partials = take(size_t(std::max(g.xblocks * kNPart, g.commit_blocks * kNAvg)) * sizeof(double));
   L.ctl = take(sizeof(Ctl));
+  L.tot = take(32 * sizeof(double));
   L.resp = take(64 * sizeof(double));
   L.total = o;
   return L;
@@ -201,15 +202,17 @@ Layout layout(const Geometry& g) {
 
 PhaseC derive(const mp_phase& c) {
   PhaseC d{};
-  d.lam = c.lambda; d.mu = c.mu; d.kap = c.kappa; d.alp = c.alpha; d.bet = c.beta; d.gam = c.gamma;
-  d.tY = c.tY; d.tH = c.tH; d.mY = c.mY; d.mH = c.mH; d.a1 = c.a1; d.b1 = c.b1;
-  d.a2 = c.a1 * c.mu / c.kappa;
+  d.t.lam = c.lambda; d.t.mu = c.mu; d.t.kap = c.kappa;
+  d.t.tY = c.tY; d.t.tH = c.tH; d.t.a1 = c.a1;
+  d.t.a2 = c.a1 * c.mu / c.kappa;
+  d.m.alp = c.alpha; d.m.bet = c.beta; d.m.gam = c.gamma;
+  d.m.mY = c.mY; d.m.mH = c.mH; d.m.b1 = c.b1;
   if (c.gamma != c.beta) {
-    d.b2 = c.b1 * (c.gamma + c.beta) / (c.gamma - c.beta);
-    d.b2gmb = d.b2 * (c.gamma - c.beta);
+    d.m.b2 = c.b1 * (c.gamma + c.beta) / (c.gamma - c.beta);
+    d.m.b2gmb = d.m.b2 * (c.gamma - c.beta);
   } else {
-    d.b2 = 0.0;
-    d.b2gmb = c.b1 * (c.gamma + c.beta);
+    d.m.b2 = 0.0;
+    d.m.b2gmb = c.b1 * (c.gamma + c.beta);
   }
   return d;
 }
@@ -311,6 +314,7 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   P->tw2 = P->tw1 + g.n1;
   P->partials = reinterpret_cast<double*>(w + L.partials);
   P->ctl = reinterpret_cast<Ctl*>(w + L.ctl);
+  P->tot = reinterpret_cast<double*>(w + L.tot);
   P->resp = reinterpret_cast<double*>(w + L.resp);
   P->tol = prob->tol;
   P->max_iter = prob->max_iter;
@@ -445,6 +449,8 @@ mp_status mp_solve_load_path(mp_plan P, int32_t n_steps, const double* times, co
     hipLaunchKernelGGL((k_xpass<double, X_INIT>), dim3(g.xblocks), dim3(g.xthreads), xshared(g),
                        P->stream, xa);
     xa.ctl = P->ctl;
+    ErrMacro em;
+    for (int c = 0; c < 18; ++c) em.v[c] = xa.mac[c];
     int batch = 2;
     long queued = 0;
     for (;;) {
@@ -465,8 +471,9 @@ mp_status mp_solve_load_path(mp_plan P, int32_t n_steps, const double* times, co
         hipLaunchKernelGGL((k_xpass<double, X_ITER>), dim3(g.xblocks), dim3(g.xthreads), xshared(g),
                            P->stream, xa);
         if (ev) HIP_TRY(hipEventRecord(ev[6], P->stream));
-        hipLaunchKernelGGL(k_err_reduce, dim3(1), dim3(256), 0, P->stream, P->partials, g.xblocks,
-                           g.nvox, P->ctl);
+        hipLaunchKernelGGL(k_err_rows, dim3(kNPart), dim3(256), 0, P->stream, P->partials, g.xblocks,
+                           P->tot, P->ctl);
+        hipLaunchKernelGGL(k_err_final, dim3(1), dim3(64), 0, P->stream, P->tot, g.nvox, P->ctl, em);
         if (ev) HIP_TRY(hipEventRecord(ev[7], P->stream));
       }
       HIP_TRY(hipGetLastError());

@@ -26,10 +26,11 @@ HBM_PEAK_GBS = 8000.0
 #   x pass : read 18 half spectra (18 w), e/gamma old (18 w), history base
 #            (18 w), p_n, q_n (2 x 8 B), phase id (1 B); write e/gamma (18 w)
 #            and 18 half spectra (18 w)
-#   y, z passes and the Green operator: read + write 18 half spectra (36 w)
+#   y passes, fused z pass (z forward + Green operator + z inverse):
+#            read + write 18 half spectra (36 w)
 BYTES_PER_VOXEL = {
     "x_pass": 90 * 8 + 16 + 1,
-    "y_fwd": 36 * 8, "z_fwd": 36 * 8, "green": 36 * 8, "z_inv": 36 * 8, "y_inv": 36 * 8,
+    "y_fwd": 36 * 8, "z_green": 36 * 8, "y_inv": 36 * 8,
     "err_reduce": 0,
 }
 BYTES_PER_VOXEL_ITER = sum(BYTES_PER_VOXEL.values())

@@ -15,8 +15,8 @@
  *
  * Conventions shared by every entry point
  *   - Grid n[0] x n[1] x n[2] voxels of size h, x fastest: voxel (x, y, z) has
- *     linear index (z * n[1] + y) * n[0] + x.  Every n[i] must be even, in
- *     [4, 256], and a product of 2s and 3s.
+ *     linear index (z * n[1] + y) * n[0] + x.  Every n[i] must be one of
+ *     4 6 8 12 16 24 32 48 64 96 128 192 256.
  *   - Tensor V_kl is component 3 * k + l (k = row).  t_kl acts on the face of
  *     normal k (Eq. 2); e_kl = u_l,k + eps_lkm phi_m, gamma_kl = phi_k,l (Eq. 1);
  *     m_kl = B_lkmn gamma_mn (Eq. 5).
@@ -136,10 +136,11 @@ mp_status mp_plan_steps(mp_plan plan, int32_t* steps);
  * (no averages added).  Uses the plan's transforms and reference medium. */
 mp_status mp_green_apply(mp_plan plan, const void* dev_in, void* dev_out);
 
-/* Forward transform of 18 real fields (device, 18*n doubles) to their half
- * spectra: dev_out receives 18 * n[2] * n[1] * (n[0]/2) complex doubles
- * (interleaved re, im), layout [c][kz][ky][kx], kx = 0 .. n[0]/2 - 1 (the
- * x-Nyquist bin is not kept), unnormalised forward DFT. */
+/* Forward transform of 18 real fields (device, 18*n doubles, SoA) to their
+ * half spectra: dev_out receives n[2] * n[1] * (n[0]/2) * 18 complex doubles
+ * (interleaved re, im), component-interleaved layout [kz][ky][kx][c],
+ * kx = 0 .. n[0]/2 - 1 (the x-Nyquist bin is not kept), unnormalised
+ * forward DFT.  This is the solver's own spectral layout. */
 mp_status mp_spectrum_forward(mp_plan plan, const void* dev_in, void* dev_out);
 
 /* Radial return (Alg. 1) at n_vox independent points on the device, FP64.
@@ -156,10 +157,10 @@ mp_status mp_radial_return(mp_plan plan, int64_t n_vox, const void* phase,
  * the plan records hipEvents on its stream between the kernels of every
  * iteration that runs and accumulates their durations (counters reset on
  * every call).  mp_profile_read fills ms_total[j] (milliseconds) and
- * launches[j] for j < min(n, 7), kernel j in iteration order: 0 y forward,
- * 1 z forward, 2 Green operator, 3 z inverse, 4 y inverse, 5 x pass (inverse
+ * launches[j] for j < min(n, 5), kernel j in iteration order: 0 y forward,
+ * 1 z forward + Green operator + z inverse, 2 y inverse, 3 x pass (inverse
  * x transform, return maps, error partials, polarization, forward x
- * transform), 6 error reduction.  Adds event records between kernels. */
+ * transform), 4 error reduction.  Adds event records between kernels. */
 mp_status mp_profile(mp_plan plan, int32_t enable);
 mp_status mp_profile_read(mp_plan plan, int32_t n, double* ms_total, int64_t* launches);
 

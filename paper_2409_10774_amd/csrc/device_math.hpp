@@ -1,10 +1,11 @@
 // Device building blocks of the micropolar FFT solver (gfx950).
 //
 //   cx<T>            interleaved complex value (re, im), 2*sizeof(T) aligned
-//   fft_inplace      self-sorting mixed-radix Stockham FFT of a batch of
-//                    pencils held in LDS (radices 2, 3, 4, 8); each stage
-//                    gathers its butterflies into registers, barriers, then
-//                    scatters, so one LDS buffer suffices
+//   fft_ct           self-sorting mixed-radix Stockham FFT of a batch of
+//                    pencils held in LDS (radices 8, 4, 2, 3), all sizes
+//                    compile-time; each stage gathers its butterflies into
+//                    registers, barriers, then scatters, so one LDS buffer
+//                    suffices
 //   PhaseC           per-phase constants with the derived a2, b2 of Alg. 1
 //   return_map       micropolar radial return of Alg. 1 at one voxel
 //   green_apply      reference-medium Green operator at one frequency
@@ -108,75 +109,73 @@ struct Dft<T, 3, INV> {
 };
 
 // ---------------------------------------------------------------------------
-// Stockham stage, in place in LDS.
-//   pencil b, point i lives at buf[b * bs + i * ps]; N points per pencil,
-//   nb pencils.  p = product of the radices already applied.  Butterfly w
-//   reads points i + r N/R, twiddles them by exp(-+2 pi i r k/(pR)),
-//   k = i mod p, and writes points (i - k) R + k + s p.
-//   MB = butterflies a thread can hold; the host guarantees
-//   ceil(nb N / R / nthr) <= MB.
+// Self-sorting mixed-radix Stockham FFT, in place in LDS, every size and
+// stride a compile-time constant (index arithmetic folds to shifts and
+// multiplies).
+//   pencil b, point i lives at buf[b * BS + i * PS]; N points per pencil,
+//   NB pencils, NTHR threads.  P = product of the radices already applied.
+//   Butterfly w reads points i + r N/R, twiddles them by
+//   exp(-+2 pi i r k / (P R)), k = i mod P, runs an R-point DFT and writes
+//   points (i - k) R + k + s P.  Every thread gathers all its butterflies
+//   into registers, the block barriers, then scatters, so one buffer is
+//   enough.  Radices: 8 while it divides, then 4, 2, 3.
+//   tw: N-entry table exp(-2 pi i m / N).  Unnormalised in both directions.
 // ---------------------------------------------------------------------------
-template <class T, int R, bool INV, int MB>
-__device__ __forceinline__ void stage_inplace(cx<T>* buf, int N, int p, int nb, int ps, int bs,
-                                              bool bfast, const cx<T>* __restrict__ tw,
-                                              int tid, int nthr) {
-  const int nbf = N / R;
-  const int total = nbf * nb;
-  const int tws = N / (p * R);
+template <class T, int R, bool INV, int N, int P, int NB, int PS, int BS, bool BFAST, int NTHR>
+__device__ __forceinline__ void stage_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+  constexpr int NBF = N / R;
+  constexpr int TOTAL = NBF * NB;
+  constexpr int MB = (TOTAL + NTHR - 1) / NTHR;
+  constexpr int TWS = N / (P * R);
   cx<T> u[MB][R];
 #pragma unroll
   for (int j = 0; j < MB; ++j) {
-    const int w = tid + j * nthr;
-    if (w < total) {
-      int i, b;
-      if (bfast) { b = w % nb; i = w / nb; } else { i = w % nbf; b = w / nbf; }
-      const cx<T>* src = buf + b * bs + i * ps;
+    const int w = tid + j * NTHR;
+    if (TOTAL % NTHR == 0 || w < TOTAL) {
+      const int b = BFAST ? w % NB : w / NBF;
+      const int i = BFAST ? w / NB : w % NBF;
+      const cx<T>* src = buf + b * BS + i * PS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) u[j][r] = src[r * nbf * ps];
+      for (int r = 0; r < R; ++r) u[j][r] = src[r * NBF * PS];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < MB; ++j) {
-    const int w = tid + j * nthr;
-    if (w < total) {
-      int i, b;
-      if (bfast) { b = w % nb; i = w / nb; } else { i = w % nbf; b = w / nbf; }
-      const int k = i % p;
+    const int w = tid + j * NTHR;
+    if (TOTAL % NTHR == 0 || w < TOTAL) {
+      const int b = BFAST ? w % NB : w / NBF;
+      const int i = BFAST ? w / NB : w % NBF;
+      const int k = i % P;
+      if (P > 1) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cx<T> t = tw[r * k * tws];
-        if (INV) t.im = -t.im;
-        u[j][r] = cmul(u[j][r], t);
+        for (int r = 1; r < R; ++r) {
+          cx<T> t = tw[r * k * TWS];
+          if (INV) t.im = -t.im;
+          u[j][r] = cmul(u[j][r], t);
+        }
       }
       Dft<T, R, INV>::run(u[j]);
-      cx<T>* dst = buf + b * bs + ((i - k) * R + k) * ps;
+      cx<T>* dst = buf + b * BS + ((i - k) * R + k) * PS;
 #pragma unroll
-      for (int s = 0; s < R; ++s) dst[s * p * ps] = u[j][s];
+      for (int s = 0; s < R; ++s) dst[s * P * PS] = u[j][s];
     }
   }
   __syncthreads();
 }
 
-// Radix schedule: 4 bits per stage, first stage in the low bits, 0 ends.
-// tw: N-entry table exp(-2 pi i m / N).  Unnormalised in both directions.
-template <class T, bool INV, int MAXP>
-__device__ __forceinline__ void fft_inplace(cx<T>* buf, int N, int nb, int ps, int bs, bool bfast,
-                                            uint32_t sched, const cx<T>* __restrict__ tw,
-                                            int tid, int nthr) {
-  int p = 1;
-  for (int st = 0; st < 8; ++st) {
-    const int R = (sched >> (4 * st)) & 15;
-    if (R == 0) break;
-    if (R == 8)
-      stage_inplace<T, 8, INV, MAXP / 8>(buf, N, p, nb, ps, bs, bfast, tw, tid, nthr);
-    else if (R == 4)
-      stage_inplace<T, 4, INV, MAXP / 4>(buf, N, p, nb, ps, bs, bfast, tw, tid, nthr);
-    else if (R == 2)
-      stage_inplace<T, 2, INV, MAXP / 2>(buf, N, p, nb, ps, bs, bfast, tw, tid, nthr);
-    else
-      stage_inplace<T, 3, INV, MAXP / 3>(buf, N, p, nb, ps, bs, bfast, tw, tid, nthr);
-    p *= R;
+template <int REM>
+struct NextRadix {
+  static constexpr int value = REM % 8 == 0 ? 8 : REM % 4 == 0 ? 4 : REM % 2 == 0 ? 2 : 3;
+};
+
+template <class T, bool INV, int N, int P, int NB, int PS, int BS, bool BFAST, int NTHR>
+__device__ __forceinline__ void fft_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+  if constexpr (P < N) {
+    constexpr int R = NextRadix<N / P>::value;
+    static_assert((N / P) % R == 0, "size must be a product of 2s and 3s");
+    stage_ct<T, R, INV, N, P, NB, PS, BS, BFAST, NTHR>(buf, tw, tid);
+    fft_ct<T, INV, N, P * R, NB, PS, BS, BFAST, NTHR>(buf, tw, tid);
   }
 }
 

@@ -1,28 +1,31 @@
 // Kernels of one fixed-point iteration of the micropolar basic scheme (Alg. 2)
 // and of the step control around it.
 //
-// Field layout in HBM (SoA, x fastest, voxel index (z n1 + y) n0 + x):
-//   S      18 half spectra, [c][kz][ky][kx], kx < n0/2 (x-Nyquist dropped:
-//          the Green operator zeroes it), complex T
-//   E      current strain e (c = 0..8) and curvature gamma (c = 9..17), T
+// Layout in HBM (x fastest, voxel index (z n1 + y) n0 + x):
+//   S      half spectra of the 18 components, component-interleaved:
+//          [kz][ky][kx][c], kx < n0/2 (the x-Nyquist bin is dropped: the
+//          Green operator zeroes it), complex T.  A spectral row (kz, ky) is
+//          one contiguous run of n0/2 * 18 values; a y or z tile of TX
+//          consecutive kx is a contiguous run of TX * 18 values per point.
+//   E      current strain e (c = 0..8) and curvature gamma (c = 9..17), SoA, T
 //   Eprev  the same fields one committed step earlier (extrapolation)
 //   base   history base t_n - A e_n (0..8), m_n - B gamma_n (9..17), T
 //   pq     p_n, q_n of the last committed step, FP64
 //
-// Per iteration: k_xpass<ITER> (x inverse, +E/Gamma, Alg. 1 twice for the
-// error measure, polarization, x forward) -> k_axis (y fwd) -> k_axis
-// (z fwd) -> k_green -> k_axis (z inv) -> k_axis (y inv) -> k_err_reduce.
-// Every iteration kernel returns at once when the step's control block says
-// the loop is finished, so batches of iterations can be queued ahead.
+// One loop iteration: k_axis<Y_FWD> -> k_axis<Z_GREEN> (z forward, Green
+// operator, z inverse) -> k_axis<Y_INV> -> k_xpass<ITER> (x inverse, + E /
+// Gamma, Alg. 1, error partials, polarization, x forward) -> k_err_rows ->
+// k_err_final.  Every loop kernel returns at once when the step's control
+// block says the loop is finished, so iterations can be queued ahead.
 #pragma once
 
 #include "device_math.hpp"
 
 namespace mp {
 
-constexpr int kMaxPts = 8;       // FFT points a thread holds in one stage
-constexpr int kNPart = 30;       // per-block partials of the error measure (2 levels x 15)
-constexpr int kNAvg = 40;        // per-block partials of the step averages
+constexpr int kLev = 15;          // per-level error partials
+constexpr int kNPart = 2 * kLev;  // per-block error partials
+constexpr int kNAvg = 40;         // per-block partials of the step averages
 
 struct ErrMacro {
   double v[18];   // prescribed E then Gamma of the step
@@ -41,14 +44,14 @@ struct Ctl {
 };
 
 enum XMode { X_ITER = 0, X_INIT = 1, X_FWD_ONLY = 2, X_INV_ONLY = 3 };
+enum AMode { Y_FWD = 0, Y_INV = 1, Z_GREEN = 2, Z_FWD = 3 };
 
 template <class T>
 struct XArgs {
-  int n0, n1, n2, nh, rows;
-  uint32_t sched;
-  const cx<T>* tw;
+  long nrows;       // n1 * n2
+  const cx<T>* tw;  // n0-entry twiddles
   cx<T>* S;
-  long nspec, nvox;
+  long nvox;
   T* E;
   T* Eprev;
   const T* base;
@@ -77,44 +80,53 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// x pass: rows of n0 voxels, all 18 components.  LDS holds 9 packed complex
+// x-pass launch shape for a row length N0: ROWS rows per block (the last
+// block may be ragged), two lanes per voxel (one per Alg. 1 level), each
+// level padded to whole wavefronts.
+template <int N0>
+struct XShape {
+  static constexpr int ROWS = N0 >= 128 ? 1 : 128 / N0;
+  static constexpr int VPB = ROWS * N0;
+  static constexpr int VPAD = (VPB + 63) / 64 * 64;
+  static constexpr int NTHR = 2 * VPAD;
+  static constexpr int NH = N0 / 2;
+};
+
+// x pass: rows of N0 voxels, all 18 components.  LDS holds 9 packed complex
 // pencils per row: pencil q = field 2q + i field 2q+1 (two real transforms
-// in one complex transform).  Two lanes per voxel: lane level 0 runs the
-// macro level of Alg. 1 (e -> t, tau), level 1 the micro level (gamma -> m,
-// mu); the levels are independent, which halves each lane's live state.
-// Each lane prefetches its old strain, history base and p_n / q_n before
-// the transforms so the loads overlap them.
-constexpr int kLev = 15;   // per-level partials: see k_xpass
-template <class T, int MODE>
-__global__ void __launch_bounds__(512) k_xpass(XArgs<T> a) {
+// in one complex transform).  Lanes [0, VPAD) run the macro level of Alg. 1
+// (e -> t, tau), lanes [VPAD, 2 VPAD) the micro level (gamma -> m, mu): the
+// levels are independent, which halves each lane's live state, and the level
+// is uniform over each wavefront.  Each lane prefetches its old strain,
+// history base and p_n / q_n before the transforms so the loads overlap them.
+template <class T, int MODE, int N0>
+__global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
+  using X = XShape<N0>;
+  constexpr int ROWS = X::ROWS, VPB = X::VPB, VPAD = X::VPAD, NTHR = X::NTHR, NH = X::NH;
+  constexpr int NPK = 9 * ROWS;
   if (a.ctl && a.ctl->done) return;
-  extern __shared__ unsigned char smem_raw[];
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  T* ldr = reinterpret_cast<T*>(smem_raw);   // scalar view: field c of voxel v at 2 (q n0 ...) + (c & 1)
-  __shared__ double red[8][2][kLev];
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int n0 = a.n0, nh = a.nh, rows = a.rows;
-  const int vpb = rows * n0;
-  const long row0 = (long)blockIdx.x * rows;
-  const int npk = 9 * rows;
-  // lanes [0, vpad) run the macro level, [vpad, 2 vpad) the micro level;
-  // vpad is a multiple of 64, so the level is uniform over each wavefront
-  const int vpad = nthr >> 1;
-  const int lvl = __builtin_amdgcn_readfirstlane(tid >= vpad ? 1 : 0);
-  const int v = tid - lvl * vpad;
-  const bool own = v < vpb;
-  const int vr = own ? v / n0 : 0, vx = own ? v % n0 : 0;
-  // 32-bit voxel offset into wave-uniform component bases (the grid holds
-  // at most 2^24 voxels)
-  const int gi = int((row0 + vr) * n0 + vx);
+  __shared__ cx<T> lds[NPK * N0];
+  __shared__ double red[NTHR / 64][kLev];
+  T* ldr = reinterpret_cast<T*>(lds);
+  const int tid = threadIdx.x;
+  const long row0 = (long)blockIdx.x * ROWS;
+  const int lvl = __builtin_amdgcn_readfirstlane(tid >= VPAD ? 1 : 0);
+  const int v = tid - lvl * VPAD;
+  const int vr = v < VPB ? v / N0 : 0, vx = v < VPB ? v % N0 : 0;
+  const bool own = v < VPB && row0 + vr < a.nrows;
+  // 32-bit voxel offset into wave-uniform component bases (at most 2^24 voxels)
+  const int gi = own ? int((row0 + vr) * N0 + vx) : 0;
   const long nv = a.nvox;
   T* const Elv = a.E + (long)lvl * 9 * nv;
   const T* const Blv = a.base + (long)lvl * 9 * nv;
+  const int rows_here = int(a.nrows - row0 < ROWS ? a.nrows - row0 : ROWS);
 
   // prefetch this lane's history (ITER, INIT)
   T eo[9], bb[9];
   double hn = 0.0;
   int ph = 0;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) eo[c] = bb[c] = T(0);
   if ((MODE == X_ITER || MODE == X_INIT) && own) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
@@ -127,24 +139,25 @@ __global__ void __launch_bounds__(512) k_xpass(XArgs<T> a) {
 
   if (MODE == X_ITER || MODE == X_INV_ONLY) {
     // half spectra -> packed full spectra Z = A + i B, Z(n0 - k) = conj A + i conj B
-    for (int w = tid; w < npk * nh; w += nthr) {
-      const int kx = w % nh, q = (w / nh) % 9, r = w / (nh * 9);
-      const long off = (row0 + r) * nh + kx;
-      const cx<T> A = a.S[(2 * q) * a.nspec + off];
-      const cx<T> B = a.S[(2 * q + 1) * a.nspec + off];
-      cx<T>* pen = lds + (r * 9 + q) * n0;
+    for (int w = tid; w < rows_here * NH * 9; w += NTHR) {
+      const int r = w / (NH * 9), rem = w % (NH * 9);
+      const int kx = rem / 9, q = rem % 9;
+      const cx<T>* srow = a.S + (row0 + r) * (NH * 18) + kx * 18 + 2 * q;
+      const cx<T> A = srow[0];
+      const cx<T> B = srow[1];
+      cx<T>* pen = lds + (r * 9 + q) * N0;
       pen[kx] = cx<T>{A.re - B.im, A.im + B.re};
       if (kx > 0)
-        pen[n0 - kx] = cx<T>{A.re + B.im, B.re - A.im};
+        pen[N0 - kx] = cx<T>{A.re + B.im, B.re - A.im};
       else
-        pen[nh] = cx<T>{T(0), T(0)};
+        pen[NH] = cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    fft_inplace<T, true, 8>(lds, n0, npk, 1, n0, false, a.sched, a.tw, tid, nthr);
+    fft_ct<T, true, N0, 1, NPK, 1, N0, false, NTHR>(lds, a.tw, tid);
   }
 
   // LDS scalar slot of field c (0..17) of this lane's voxel
-  auto slot = [&](int c) { return 2 * ((vr * 9 + (c >> 1)) * n0 + vx) + (c & 1); };
+  auto slot = [&](int c) { return 2 * ((vr * 9 + (c >> 1)) * N0 + vx) + (c & 1); };
 
   if (MODE == X_INV_ONLY) {
     if (own)
@@ -157,18 +170,17 @@ __global__ void __launch_bounds__(512) k_xpass(XArgs<T> a) {
   // |a|^2, |b|^2, b (sum), with (a, b) = (e, t) on the macro level and
   // (gamma, m) on the micro level.  Reduced over the wavefront as soon as
   // they exist (fixed butterfly order), then over the waves in order.
-  const int lane = tid & 63, wv = tid >> 6, nw = (nthr + 63) >> 6;
+  const int lane = tid & 63, wv = tid >> 6;
   auto wave_put = [&](int j, double x) {
-#pragma unroll
-    for (int L = 0; L < 2; ++L) {
-      const double y = (lvl == L && own) ? x : 0.0;
-      const double z = (j < 2) ? wave_max(y) : wave_sum(y);
-      if (lane == 0) red[wv][L][j] = z;
-    }
+    const double y = own ? x : 0.0;
+    const double z = (j < 2) ? wave_max(y) : wave_sum(y);
+    if (lane == 0) red[wv][j] = z;
   };
 
   {
     T e[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) e[c] = T(0);
     if (own) {
       if (MODE == X_FWD_ONLY) {
 #pragma unroll
@@ -199,6 +211,8 @@ __global__ void __launch_bounds__(512) k_xpass(XArgs<T> a) {
       else
         cm = a.params[ph].m;
       T t[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) t[c] = T(0);
       double pnew;
       if (own) {
         if (lvl == 0)
@@ -219,16 +233,15 @@ __global__ void __launch_bounds__(512) k_xpass(XArgs<T> a) {
       }
       if (MODE == X_ITER) {
         double da = 0, sa = 0, sb = 0;
-        if (own)
 #pragma unroll
-          for (int c = 0; c < 9; ++c) {
-            const double x = double(e[c]) - double(eo[c]);
-            da += x * x;
-            sa += double(e[c]) * double(e[c]);
-            sb += double(t[c]) * double(t[c]);
-          }
+        for (int c = 0; c < 9; ++c) {
+          const double x = double(e[c]) - double(eo[c]);
+          da += x * x;
+          sa += double(e[c]) * double(e[c]);
+          sb += double(t[c]) * double(t[c]);
+        }
 #pragma unroll
-        for (int c = 0; c < 9; ++c) wave_put(6 + c, own ? double(t[c]) : 0.0);
+        for (int c = 0; c < 9; ++c) wave_put(6 + c, double(t[c]));
         wave_put(4, sa);
         wave_put(5, sb);
         da = sqrt(da);
@@ -253,28 +266,114 @@ __global__ void __launch_bounds__(512) k_xpass(XArgs<T> a) {
         wave_put(1, db);
         wave_put(3, db);
         __syncthreads();
-        if (tid < 2 * kLev) {
+        if (tid < kNPart) {
           const int L = tid / kLev, j = tid % kLev;
-          double y = red[0][L][j];
-          for (int w = 1; w < nw; ++w) y = (j < 2) ? fmax(y, red[w][L][j]) : y + red[w][L][j];
+          // waves [0, VPAD/64) hold level 0, the rest level 1
+          const int w0 = L * (VPAD / 64), w1 = w0 + VPAD / 64;
+          double y = red[w0][j];
+          for (int w = w0 + 1; w < w1; ++w) y = (j < 2) ? fmax(y, red[w][j]) : y + red[w][j];
           a.partials[(long)tid * gridDim.x + blockIdx.x] = y;
         }
       }
     }
   }
   __syncthreads();
-  fft_inplace<T, false, 8>(lds, n0, npk, 1, n0, false, a.sched, a.tw, tid, nthr);
+  fft_ct<T, false, N0, 1, NPK, 1, N0, false, NTHR>(lds, a.tw, tid);
   // unpack: A = (Z(k) + conj Z(-k)) / 2, B = (Z(k) - conj Z(-k)) / (2 i)
-  for (int w = tid; w < npk * nh; w += nthr) {
-    const int kx = w % nh, q = (w / nh) % 9, r = w / (nh * 9);
-    const cx<T>* pen = lds + (r * 9 + q) * n0;
+  for (int w = tid; w < rows_here * NH * 9; w += NTHR) {
+    const int r = w / (NH * 9), rem = w % (NH * 9);
+    const int kx = rem / 9, q = rem % 9;
+    const cx<T>* pen = lds + (r * 9 + q) * N0;
     const cx<T> zk = pen[kx];
-    const cx<T> zm = pen[kx == 0 ? 0 : n0 - kx];
-    const long off = (row0 + r) * nh + kx;
-    a.S[(2 * q) * a.nspec + off] = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
-    a.S[(2 * q + 1) * a.nspec + off] = cx<T>{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
+    const cx<T> zm = pen[kx == 0 ? 0 : N0 - kx];
+    cx<T>* srow = a.S + (row0 + r) * (NH * 18) + kx * 18 + 2 * q;
+    srow[0] = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
+    srow[1] = cx<T>{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
   }
+}
 
+// ---------------------------------------------------------------------------
+// y and z passes over the interleaved half spectra.  A block owns TX
+// consecutive kx at one kz (y pass) or one ky (z pass): L points x TX*18
+// pencils, each point a contiguous run of TX*18 complex values.  Z_GREEN
+// runs the forward z transform, the Green operator at every frequency of the
+// tile (all 18 components are in LDS) and the inverse z transform, so the
+// spectrum makes one HBM round trip for the three steps.
+// ---------------------------------------------------------------------------
+template <class T>
+struct AxisArgs {
+  cx<T>* S;
+  long ostride;    // stride (complex) of blockIdx.y: kz for y, ky for z
+  long pstride;    // stride (complex) between points of the transformed axis
+  const cx<T>* tw;
+  const Ctl* ctl;
+  // Z_GREEN only
+  int n0, n1, n2;
+  double h, scale;
+  RefC ref;
+};
+
+template <int L, int TX>
+struct AShape {
+  static constexpr int NB = TX * 18;
+  static constexpr int PTS = L * NB;
+  static constexpr int NTHR = PTS > 2304 ? 512 : 256;
+};
+
+template <class T, int MODE, int L, int TX>
+__global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_axis(AxisArgs<T> a) {
+  using A = AShape<L, TX>;
+  constexpr int NB = A::NB, PTS = A::PTS, NTHR = A::NTHR;
+  if (a.ctl && a.ctl->done) return;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  cx<T>* g = a.S + (long)blockIdx.y * a.ostride + (long)blockIdx.x * NB;
+  for (int w = tid; w < PTS; w += NTHR) {
+    const int i = w / NB, b = w % NB;
+    lds[w] = g[i * a.pstride + b];
+  }
+  __syncthreads();
+  constexpr bool INV = MODE == Y_INV;
+  fft_ct<T, INV, L, 1, NB, NB, 1, true, NTHR>(lds, a.tw, tid);
+  if (MODE == Z_GREEN) {
+    // Green operator at the L * TX frequencies of the tile
+    for (int f = tid; f < L * TX; f += NTHR) {
+      const int kz = f / TX, xl = f % TX;
+      const int kx = blockIdx.x * TX + xl, ky = blockIdx.y;
+      cx<T>* p = lds + kz * NB + xl * 18;
+      const bool zero = (kx == 0 && ky == 0 && kz == 0) || (2 * ky == a.n1) || (2 * kz == a.n2);
+      if (zero) {
+#pragma unroll
+        for (int c = 0; c < 18; ++c) p[c] = cx<T>{T(0), T(0)};
+      } else {
+        cx<T> tau[9], mu[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          tau[c] = p[c];
+          mu[c] = p[9 + c];
+        }
+        const double tp = 6.283185307179586476925286766559;
+        const int my = (2 * ky < a.n1) ? ky : ky - a.n1;
+        const int mz = (2 * kz < a.n2) ? kz : kz - a.n2;
+        const T x1 = T(tp * kx / (a.n0 * a.h));
+        const T x2 = T(tp * my / (a.n1 * a.h));
+        const T x3 = T(tp * mz / (a.n2 * a.h));
+        green_apply<T>(a.ref, x1, x2, x3, T(a.scale), tau, mu);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          p[c] = tau[c];
+          p[9 + c] = mu[c];
+        }
+      }
+    }
+    __syncthreads();
+    fft_ct<T, true, L, 1, NB, NB, 1, true, NTHR>(lds, a.tw, tid);
+  }
+  for (int w = tid; w < PTS; w += NTHR) {
+    const int i = w / NB, b = w % NB;
+    g[i * a.pstride + b] = lds[w];
+  }
 }
 
 // error measure, stage 1: block j reduces partial row j over the x-pass blocks
@@ -342,83 +441,6 @@ __global__ void k_err_final(const double* tot, long nvox, Ctl* ctl, ErrMacro mac
     done = 2;
   }
   ctl->done = done;
-}
-
-// y or z pass over the half spectra: tile of L points x TX consecutive kx.
-template <class T>
-struct AxisArgs {
-  cx<T>* S;
-  long nspec;
-  long ostride;    // stride of blockIdx.y
-  long pstride;    // stride between points of the transformed axis
-  int L, TX;
-  uint32_t sched;
-  const cx<T>* tw;
-  const Ctl* ctl;
-};
-
-template <class T, bool INV>
-__global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
-  if (a.ctl && a.ctl->done) return;
-  extern __shared__ unsigned char smem_raw[];
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int L = a.L, TX = a.TX;
-  cx<T>* g = a.S + (long)blockIdx.z * a.nspec + (long)blockIdx.y * a.ostride + (long)blockIdx.x * TX;
-  for (int w = tid; w < L * TX; w += nthr) {
-    const int i = w / TX, b = w % TX;
-    lds[i * TX + b] = g[i * a.pstride + b];
-  }
-  __syncthreads();
-  fft_inplace<T, INV, kMaxPts>(lds, L, TX, TX, 1, true, a.sched, a.tw, tid, nthr);
-  for (int w = tid; w < L * TX; w += nthr) {
-    const int i = w / TX, b = w % TX;
-    g[i * a.pstride + b] = lds[i * TX + b];
-  }
-}
-
-template <class T>
-struct GreenArgs {
-  cx<T>* S;
-  long nspec;
-  int n0, n1, n2, nh;
-  double h, scale;
-  RefC ref;
-  const Ctl* ctl;
-};
-
-template <class T>
-__global__ void __launch_bounds__(256) k_green(GreenArgs<T> a) {
-  if (a.ctl && a.ctl->done) return;
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= a.nspec) return;
-  const int kx = int(idx % a.nh);
-  const int ky = int((idx / a.nh) % a.n1);
-  const int kz = int(idx / ((long)a.nh * a.n1));
-  cx<T> tau[9], mu[9];
-  const bool zero = (kx == 0 && ky == 0 && kz == 0) || (2 * ky == a.n1) || (2 * kz == a.n2);
-  if (zero) {
-#pragma unroll
-    for (int c = 0; c < 18; ++c) a.S[c * a.nspec + idx] = cx<T>{T(0), T(0)};
-    return;
-  }
-#pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    tau[c] = a.S[c * a.nspec + idx];
-    mu[c] = a.S[(9 + c) * a.nspec + idx];
-  }
-  const double tp = 6.283185307179586476925286766559;
-  const int my = (2 * ky < a.n1) ? ky : ky - a.n1;
-  const int mz = (2 * kz < a.n2) ? kz : kz - a.n2;
-  const T x1 = T(tp * kx / (a.n0 * a.h));
-  const T x2 = T(tp * my / (a.n1 * a.h));
-  const T x3 = T(tp * mz / (a.n2 * a.h));
-  green_apply<T>(a.ref, x1, x2, x3, T(a.scale), tau, mu);
-#pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    a.S[c * a.nspec + idx] = tau[c];
-    a.S[(9 + c) * a.nspec + idx] = mu[c];
-  }
 }
 
 __global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm) {

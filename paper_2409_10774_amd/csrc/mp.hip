@@ -30,30 +30,84 @@ mp_status fail(mp_status s, const std::string& msg) {
       return fail(MP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
   } while (0)
 
-// radix schedule (8s first, then 4, 2, 3): 4 bits per stage
-bool radix_schedule(int n, uint32_t* sched, std::vector<int>* radices) {
-  std::vector<int> r;
-  int m = n;
-  while (m % 8 == 0) { r.push_back(8); m /= 8; }
-  while (m % 4 == 0) { r.push_back(4); m /= 4; }
-  while (m % 2 == 0) { r.push_back(2); m /= 2; }
-  while (m % 3 == 0) { r.push_back(3); m /= 3; }
-  if (m != 1 || r.size() > 8) return false;
-  uint32_t s = 0;
-  for (size_t i = 0; i < r.size(); ++i) s |= uint32_t(r[i]) << (4 * i);
-  *sched = s;
-  if (radices) *radices = r;
-  return true;
+// ---------------------------------------------------------------------------
+// compile-time sizes: every axis length must be one of these
+// ---------------------------------------------------------------------------
+#define MP_SIZES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+
+bool supported(int n) {
+  switch (n) {
+#define MP_CASE(N) case N:
+    MP_SIZES(MP_CASE)
+#undef MP_CASE
+    return true;
+    default: return false;
+  }
 }
 
-// every stage must fit kMaxPts points per thread
-bool fits(int N, int nb, int nthr, const std::vector<int>& radices) {
-  for (int R : radices) {
-    const long total = long(N / R) * nb;
-    const long per = (total + nthr - 1) / nthr;
-    if (per * R > kMaxPts) return false;
+// widest y / z tile: TX * L <= 256 frequencies (a power of two)
+constexpr int tx_wide(int L) {
+  int t = 1;
+  while (2 * t * L <= 256) t *= 2;
+  return t;
+}
+
+int x_rows(int n0) { return n0 >= 128 ? 1 : 128 / n0; }
+
+template <class T, int MODE>
+void launch_x(int n0, int blocks, hipStream_t s, const XArgs<T>& a) {
+  switch (n0) {
+#define MP_CASE(N)                                                                           \
+  case N:                                                                                    \
+    hipLaunchKernelGGL((k_xpass<T, MODE, N>), dim3(blocks), dim3(XShape<N>::NTHR), 0, s, a); \
+    break;
+    MP_SIZES(MP_CASE)
+#undef MP_CASE
   }
-  return true;
+}
+
+template <class T, int MODE, int L, int TX>
+void launch_axis_tx(dim3 grid, hipStream_t s, const AxisArgs<T>& a) {
+  const size_t shm = size_t(AShape<L, TX>::PTS) * sizeof(cx<T>);
+  hipLaunchKernelGGL((k_axis<T, MODE, L, TX>), grid, dim3(AShape<L, TX>::NTHR), shm, s, a);
+}
+
+template <class T, int MODE>
+void launch_axis(int L, int tx, dim3 grid, hipStream_t s, const AxisArgs<T>& a) {
+  switch (L) {
+#define MP_CASE(N)                                        \
+  case N:                                                 \
+    if (tx == 1)                                          \
+      launch_axis_tx<T, MODE, N, 1>(grid, s, a);          \
+    else                                                  \
+      launch_axis_tx<T, MODE, N, tx_wide(N)>(grid, s, a); \
+    break;
+    MP_SIZES(MP_CASE)
+#undef MP_CASE
+  }
+}
+
+// let every axis kernel use more than 64 KB of LDS (up to 160 KB on gfx950)
+template <class T, int MODE, int L, int TX>
+hipError_t allow_lds_tx() {
+  const size_t shm = size_t(AShape<L, TX>::PTS) * sizeof(cx<T>);
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_axis<T, MODE, L, TX>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+}
+
+template <class T, int MODE>
+hipError_t allow_lds(int L) {
+  hipError_t e = hipSuccess;
+  switch (L) {
+#define MP_CASE(N)                                                   \
+  case N:                                                            \
+    if ((e = allow_lds_tx<T, MODE, N, 1>()) != hipSuccess) return e; \
+    e = allow_lds_tx<T, MODE, N, tx_wide(N)>();                      \
+    break;
+    MP_SIZES(MP_CASE)
+#undef MP_CASE
+  }
+  return e;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -64,28 +118,31 @@ struct Layout {
 
 struct Geometry {
   int n0, n1, n2, nh;
-  long nvox, nspec;
-  int rows, xthreads, xblocks;
-  int txy, txz;
-  uint32_t s0, s1, s2;
+  long nvox, nspec, nrows;
+  int xblocks, txy, txz;
   int commit_blocks;
 };
+
+constexpr int kProfEv = 6;     // boundaries around the 5 loop kernels of one iteration
 
 }  // namespace
 
 struct mp_plan_s {
   Geometry g;
   Layout L;
+  int precision;
   double h;
   hipStream_t stream;
   unsigned char* ws;
-  cx<double>* S;
-  double *E, *Eprev, *base, *pq, *out_tm, *out_pq, *partials, *tot, *resp;
+  void* S;        // cx<T>
+  void* E;        // T
+  void* Eprev;    // T
+  void* base;     // T
+  void* out_tm;   // T
+  double *pq, *out_pq, *partials, *tot, *resp;
   uint8_t* phase;
   PhaseC* params;
-  cx<double>* tw0;
-  cx<double>* tw1;
-  cx<double>* tw2;
+  void* tw0;      // cx<T>, n0 + n1 + n2 entries
   Ctl* ctl;
   Ctl* ctl_host;
   RefC ref;
@@ -97,7 +154,7 @@ struct mp_plan_s {
   std::vector<std::vector<double>> resp_hist;
   // optional per-kernel timing of loop iterations (hipEvents on the plan's stream)
   bool prof;
-  std::vector<hipEvent_t> ev;    // kProfEv events per queued iteration
+  std::vector<hipEvent_t> ev;
   double prof_ms[8];
   long prof_n[8];
 };
@@ -106,13 +163,10 @@ namespace {
 
 mp_status validate(const mp_problem* p, Geometry* g) {
   if (!p) return fail(MP_E_INVALID, "problem is NULL");
-  for (int i = 0; i < 3; ++i) {
-    const int n = p->n[i];
-    uint32_t s;
-    if (n < 4 || n > 256 || (n & 1) || !radix_schedule(n, &s, nullptr))
-      return fail(MP_E_INVALID, "grid size n[" + std::to_string(i) + "] = " + std::to_string(n) +
-                                    " unsupported (even, 4..256, 2^a 3^b)");
-  }
+  for (int i = 0; i < 3; ++i)
+    if (!supported(p->n[i]))
+      return fail(MP_E_INVALID, "grid size n[" + std::to_string(i) + "] = " + std::to_string(p->n[i]) +
+                                    " unsupported (4 6 8 12 16 24 32 48 64 96 128 192 256)");
   if (!(p->h > 0.0) || !std::isfinite(p->h)) return fail(MP_E_INVALID, "h must be > 0");
   if (p->n_phases < 1 || p->n_phases > 256) return fail(MP_E_INVALID, "n_phases out of 1..256");
   if (!p->phase || !p->phases) return fail(MP_E_INVALID, "phase map / table is NULL");
@@ -151,47 +205,30 @@ mp_status validate(const mp_problem* p, Geometry* g) {
   G.n0 = p->n[0]; G.n1 = p->n[1]; G.n2 = p->n[2]; G.nh = G.n0 / 2;
   G.nvox = nvox;
   G.nspec = long(G.n2) * G.n1 * G.nh;
-  std::vector<int> r0, r1, r2;
-  radix_schedule(G.n0, &G.s0, &r0);
-  radix_schedule(G.n1, &G.s1, &r1);
-  radix_schedule(G.n2, &G.s2, &r2);
-  // x pass: rows per block (a divisor of n1 n2), two lanes per voxel
-  const long nrows = long(G.n1) * G.n2;
-  int rows = std::max(1, 128 / G.n0);
-  while (rows > 1 && nrows % rows) --rows;
-  G.rows = rows;
-  G.xthreads = 2 * ((rows * G.n0 + 63) / 64 * 64);
-  if (G.xthreads > 512 || !fits(G.n0, 9 * rows, G.xthreads, r0))
-    return fail(MP_E_INVALID, "x pass does not fit");
-  G.xblocks = int(nrows / rows);
-  // y / z passes: tile width TX | nh
-  auto pick_tx = [&](int L, const std::vector<int>& rad) {
-    for (int tx = 16; tx >= 1; tx >>= 1)
-      if (G.nh % tx == 0 && fits(L, tx, 256, rad)) return tx;
-    return 0;
-  };
-  G.txy = pick_tx(G.n1, r1);
-  G.txz = pick_tx(G.n2, r2);
-  if (!G.txy || !G.txz) return fail(MP_E_INVALID, "y/z pass does not fit");
+  G.nrows = long(G.n1) * G.n2;
+  const int rows = x_rows(G.n0);
+  G.xblocks = int((G.nrows + rows - 1) / rows);
+  G.txy = (G.nh % tx_wide(G.n1) == 0) ? tx_wide(G.n1) : 1;
+  G.txz = (G.nh % tx_wide(G.n2) == 0) ? tx_wide(G.n2) : 1;
   G.commit_blocks = int((nvox + 255) / 256);
   *g = G;
   return MP_OK;
 }
 
-Layout layout(const Geometry& g) {
+Layout layout(const Geometry& g, size_t w /* bytes per bulk word */) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
-  L.S = take(18 * g.nspec * sizeof(cx<double>));
-  L.E = take(18 * g.nvox * sizeof(double));
-  L.Eprev = take(18 * g.nvox * sizeof(double));
-  L.base = take(18 * g.nvox * sizeof(double));
+  L.S = take(18 * g.nspec * 2 * w);
+  L.E = take(18 * g.nvox * w);
+  L.Eprev = take(18 * g.nvox * w);
+  L.base = take(18 * g.nvox * w);
   L.pq = take(2 * g.nvox * sizeof(double));
-  L.out_tm = take(18 * g.nvox * sizeof(double));
+  L.out_tm = take(18 * g.nvox * w);
   L.out_pq = take(2 * g.nvox * sizeof(double));
   L.phase = take(g.nvox);
   L.params = take(256 * sizeof(PhaseC));
-  L.tw = take(size_t(g.n0 + g.n1 + g.n2) * sizeof(cx<double>));
+  L.tw = take(size_t(g.n0 + g.n1 + g.n2) * 2 * w);
   L.partials = take(size_t(std::max(g.xblocks * kNPart, g.commit_blocks * kNAvg)) * sizeof(double));
   L.ctl = take(sizeof(Ctl));
   L.tot = take(32 * sizeof(double));
@@ -217,67 +254,208 @@ PhaseC derive(const mp_phase& c) {
   return d;
 }
 
-void twiddles(int n, std::vector<cx<double>>* out) {
+template <class T>
+void twiddles(int n, std::vector<cx<T>>* out) {
   for (int m = 0; m < n; ++m) {
-    // exp(-2 pi i m / n), argument reduced to the first half-turn for accuracy
+    // exp(-2 pi i m / n), evaluated in long double
     const long double a = -2.0L * 3.14159265358979323846264338327950288L * m / n;
-    out->push_back(cx<double>{double(cosl(a)), double(sinl(a))});
+    out->push_back(cx<T>{T(cosl(a)), T(sinl(a))});
   }
 }
 
-constexpr int kProfEv = 8;     // boundaries around the 7 kernels of one iteration
+// ---------------------------------------------------------------------------
+// typed launch helpers
+// ---------------------------------------------------------------------------
+template <class T>
+struct Eng {
+  static cx<T>* S(mp_plan P) { return static_cast<cx<T>*>(P->S); }
+  static const cx<T>* tw(mp_plan P, int axis) {
+    const cx<T>* t = static_cast<const cx<T>*>(P->tw0);
+    return axis == 0 ? t : axis == 1 ? t + P->g.n0 : t + P->g.n0 + P->g.n1;
+  }
 
-// enqueue the spectral part: y fwd, z fwd, Green, z inv, y inv
-// (ev: optional array of 6 events recorded before each kernel and after the last)
-void enqueue_spectral(mp_plan P, const Ctl* ctl, hipEvent_t* ev = nullptr) {
+  static AxisArgs<T> yargs(mp_plan P, cx<T>* S, const Ctl* ctl) {
+    const Geometry& g = P->g;
+    AxisArgs<T> a{};
+    a.S = S;
+    a.ostride = long(g.n1) * g.nh * 18;   // one kz plane
+    a.pstride = long(g.nh) * 18;          // next ky
+    a.tw = tw(P, 1);
+    a.ctl = ctl;
+    return a;
+  }
+  static AxisArgs<T> zargs(mp_plan P, cx<T>* S, const Ctl* ctl) {
+    const Geometry& g = P->g;
+    AxisArgs<T> a{};
+    a.S = S;
+    a.ostride = long(g.nh) * 18;          // next ky
+    a.pstride = long(g.n1) * g.nh * 18;   // next kz
+    a.tw = tw(P, 2);
+    a.ctl = ctl;
+    a.n0 = g.n0; a.n1 = g.n1; a.n2 = g.n2;
+    a.h = P->h;
+    a.scale = 1.0 / double(g.nvox);
+    a.ref = P->ref;
+    return a;
+  }
+  static dim3 ygrid(const Geometry& g) { return dim3(g.nh / g.txy, g.n2); }
+  static dim3 zgrid(const Geometry& g) { return dim3(g.nh / g.txz, g.n1); }
+
+  // y fwd, z fwd + Green + z inv, y inv (ev: optional events before each
+  // kernel and after the last)
+  static void spectral(mp_plan P, cx<T>* S, const Ctl* ctl, hipEvent_t* ev) {
+    const Geometry& g = P->g;
+    auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], P->stream); };
+    const AxisArgs<T> ay = yargs(P, S, ctl), az = zargs(P, S, ctl);
+    mark(0);
+    launch_axis<T, Y_FWD>(g.n1, g.txy, ygrid(g), P->stream, ay);
+    mark(1);
+    launch_axis<T, Z_GREEN>(g.n2, g.txz, zgrid(g), P->stream, az);
+    mark(2);
+    launch_axis<T, Y_INV>(g.n1, g.txy, ygrid(g), P->stream, ay);
+    mark(3);
+  }
+
+  static XArgs<T> xargs(mp_plan P) {
+    const Geometry& g = P->g;
+    XArgs<T> a{};
+    a.nrows = g.nrows;
+    a.tw = tw(P, 0);
+    a.S = S(P);
+    a.nvox = g.nvox;
+    a.E = static_cast<T*>(P->E);
+    a.Eprev = static_cast<T*>(P->Eprev);
+    a.base = static_cast<const T*>(P->base);
+    a.pq = P->pq;
+    a.phase = P->phase;
+    a.params = P->params;
+    a.partials = P->partials;
+    a.ctl = P->ctl;
+    a.ref = P->ref;
+    return a;
+  }
+
+  static hipError_t prepare() {
+    hipError_t e;
+    const int sizes[] = {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+    for (int L : sizes) {
+      if ((e = allow_lds<T, Y_FWD>(L)) != hipSuccess) return e;
+      if ((e = allow_lds<T, Y_INV>(L)) != hipSuccess) return e;
+      if ((e = allow_lds<T, Z_GREEN>(L)) != hipSuccess) return e;
+      if ((e = allow_lds<T, Z_FWD>(L)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+
+  static mp_status solve(mp_plan P, int32_t n_steps, const double* times, const double* E,
+                         const double* Gam, int32_t* iters);
+};
+
+template <class T>
+mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const double* E,
+                        const double* Gam, int32_t* iters) {
   const Geometry& g = P->g;
-  AxisArgs<double> ay{P->S, g.nspec, long(g.n1) * g.nh, g.nh, g.n1, g.txy, g.s1, P->tw1, ctl};
-  AxisArgs<double> az{P->S, g.nspec, g.nh, long(g.n1) * g.nh, g.n2, g.txz, g.s2, P->tw2, ctl};
-  dim3 gy(g.nh / g.txy, g.n2, 18), gz(g.nh / g.txz, g.n1, 18);
-  const size_t shy = size_t(g.n1) * g.txy * sizeof(cx<double>);
-  const size_t shz = size_t(g.n2) * g.txz * sizeof(cx<double>);
-  auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], P->stream); };
-  mark(0);
-  hipLaunchKernelGGL((k_axis<double, false>), gy, dim3(256), shy, P->stream, ay);
-  mark(1);
-  hipLaunchKernelGGL((k_axis<double, false>), gz, dim3(256), shz, P->stream, az);
-  mark(2);
-  GreenArgs<double> ga{P->S, g.nspec, g.n0, g.n1, g.n2, g.nh, P->h,
-                       1.0 / double(g.nvox), P->ref, ctl};
-  hipLaunchKernelGGL((k_green<double>), dim3(unsigned((g.nspec + 255) / 256)), dim3(256), 0,
-                     P->stream, ga);
-  mark(3);
-  hipLaunchKernelGGL((k_axis<double, true>), gz, dim3(256), shz, P->stream, az);
-  mark(4);
-  hipLaunchKernelGGL((k_axis<double, true>), gy, dim3(256), shy, P->stream, ay);
-  mark(5);
+  if (P->steps == 0) P->t_prev = P->t_cur = times[0];
+  for (int s = 1; s <= n_steps; ++s) {
+    XArgs<T> xa = xargs(P);
+    for (int c = 0; c < 9; ++c) {
+      xa.mac[c] = E[(s - 1) * 9 + c];
+      xa.mac[9 + c] = Gam[(s - 1) * 9 + c];
+    }
+    xa.first = P->steps == 0;
+    // Alg. 2 linear extrapolation ratio (t_n - t_{n-1}) / (t_{n-1} - t_{n-2})
+    xa.r = P->steps == 0 ? 0.0 : (times[s] - P->t_cur) / (P->t_cur - P->t_prev);
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(1), 0, P->stream, P->ctl, P->fixed, P->max_iter,
+                       P->tol, P->norm);
+    P->ctl_host->iters = 0;
+    P->ctl_host->done = 0;
+    // first iterate (extrapolated or uniform), its return map and polarization
+    xa.ctl = nullptr;
+    launch_x<T, X_INIT>(g.n0, g.xblocks, P->stream, xa);
+    xa.ctl = P->ctl;
+    ErrMacro em;
+    for (int c = 0; c < 18; ++c) em.v[c] = xa.mac[c];
+    int batch = 2;
+    long queued = 0;
+    for (;;) {
+      // the control block ends every step within max_iter (or the fixed count)
+      // iterations; a loop that runs far past that means a broken device state
+      if (queued > long(std::max(P->max_iter, P->fixed)) + 256)
+        return fail(MP_E_DEVICE, "iteration control did not finish the step");
+      queued += batch;
+      const int it0 = P->ctl_host->iters;
+      if (P->prof && P->ev.size() < size_t(batch) * kProfEv) {
+        const size_t old = P->ev.size();
+        P->ev.resize(size_t(batch) * kProfEv);
+        for (size_t i = old; i < P->ev.size(); ++i) HIP_TRY(hipEventCreate(&P->ev[i]));
+      }
+      for (int k = 0; k < batch; ++k) {
+        hipEvent_t* ev = P->prof ? &P->ev[size_t(k) * kProfEv] : nullptr;
+        spectral(P, S(P), P->ctl, ev);
+        launch_x<T, X_ITER>(g.n0, g.xblocks, P->stream, xa);
+        if (ev) HIP_TRY(hipEventRecord(ev[4], P->stream));
+        hipLaunchKernelGGL(k_err_rows, dim3(kNPart), dim3(256), 0, P->stream, P->partials, g.xblocks,
+                           P->tot, P->ctl);
+        hipLaunchKernelGGL(k_err_final, dim3(1), dim3(64), 0, P->stream, P->tot, g.nvox, P->ctl, em);
+        if (ev) HIP_TRY(hipEventRecord(ev[5], P->stream));
+      }
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P->stream));
+      HIP_TRY(hipStreamSynchronize(P->stream));
+      if (P->prof) {
+        // only iterations that really ran (later ones returned at once)
+        const int ran = std::min(batch, P->ctl_host->iters - it0);
+        for (int k = 0; k < ran; ++k)
+          for (int j = 0; j < kProfEv - 1; ++j) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, P->ev[size_t(k) * kProfEv + j],
+                                        P->ev[size_t(k) * kProfEv + j + 1]));
+            P->prof_ms[j] += ms;
+            P->prof_n[j] += 1;
+          }
+      }
+      if (P->ctl_host->done) break;
+      batch = std::min(batch * 2, 64);
+    }
+    const Ctl c = *P->ctl_host;
+    // commit
+    CommitArgs<T> ca{g.nvox, static_cast<const T*>(P->E), static_cast<T*>(P->base), P->pq,
+                     static_cast<T*>(P->out_tm), P->out_pq, P->phase, P->params, P->partials};
+    hipLaunchKernelGGL((k_commit<T>), dim3(g.commit_blocks), dim3(256), 0, P->stream, ca);
+    hipLaunchKernelGGL(k_avg_reduce, dim3(1), dim3(256), 0, P->stream, P->partials, g.commit_blocks,
+                       g.nvox, P->resp);
+    std::vector<double> r(42, 0.0);
+    HIP_TRY(hipMemcpyAsync(r.data(), P->resp, kNAvg * sizeof(double), hipMemcpyDeviceToHost,
+                           P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    r[40] = c.err;
+    r[41] = c.iters;
+    P->resp_hist.push_back(r);
+    P->steps += 1;
+    P->t_prev = P->t_cur;
+    P->t_cur = times[s];
+    if (iters) iters[s - 1] = c.iters;
+    if (c.done == 2)
+      return fail(MP_E_NOT_CONVERGED, "step " + std::to_string(P->steps) + " hit max_iter");
+    if (c.done == 3)
+      return fail(MP_E_DIVERGED, "step " + std::to_string(P->steps) + " diverged");
+  }
+  return MP_OK;
 }
-
-XArgs<double> xargs(mp_plan P) {
-  const Geometry& g = P->g;
-  XArgs<double> a{};
-  a.n0 = g.n0; a.n1 = g.n1; a.n2 = g.n2; a.nh = g.nh; a.rows = g.rows;
-  a.sched = g.s0; a.tw = P->tw0; a.S = P->S; a.nspec = g.nspec; a.nvox = g.nvox;
-  a.E = P->E; a.Eprev = P->Eprev; a.base = P->base; a.pq = P->pq; a.phase = P->phase;
-  a.params = P->params; a.partials = P->partials; a.ctl = P->ctl; a.ref = P->ref;
-  return a;
-}
-
-size_t xshared(const Geometry& g) { return size_t(9) * g.rows * g.n0 * sizeof(cx<double>); }
 
 }  // namespace
 
 extern "C" {
 
 const char* mp_last_error(void) { return g_err.c_str(); }
-const char* mp_version(void) { return "mp 0.1 gfx950"; }
+const char* mp_version(void) { return "mp 0.2 gfx950"; }
 
 mp_status mp_plan_workspace_size(const mp_problem* prob, size_t* bytes) {
   Geometry g;
   mp_status s = validate(prob, &g);
   if (s != MP_OK) return s;
   if (!bytes) return fail(MP_E_INVALID, "bytes is NULL");
-  *bytes = layout(g).total;
+  *bytes = layout(g, sizeof(double)).total;
   return MP_OK;
 }
 
@@ -287,7 +465,8 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   mp_status s = validate(prob, &g);
   if (s != MP_OK) return s;
   if (!out) return fail(MP_E_INVALID, "out is NULL");
-  Layout L = layout(g);
+  const size_t w = sizeof(double);
+  Layout L = layout(g, w);
   if (!dev_workspace || bytes < L.total)
     return fail(MP_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
   if (reinterpret_cast<uintptr_t>(dev_workspace) & 255)
@@ -296,26 +475,25 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   mp_plan P = new mp_plan_s();
   P->g = g;
   P->L = L;
+  P->precision = prob->precision;
   P->h = prob->h;
   P->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  unsigned char* w = static_cast<unsigned char*>(dev_workspace);
-  P->ws = w;
-  P->S = reinterpret_cast<cx<double>*>(w + L.S);
-  P->E = reinterpret_cast<double*>(w + L.E);
-  P->Eprev = reinterpret_cast<double*>(w + L.Eprev);
-  P->base = reinterpret_cast<double*>(w + L.base);
-  P->pq = reinterpret_cast<double*>(w + L.pq);
-  P->out_tm = reinterpret_cast<double*>(w + L.out_tm);
-  P->out_pq = reinterpret_cast<double*>(w + L.out_pq);
-  P->phase = w + L.phase;
-  P->params = reinterpret_cast<PhaseC*>(w + L.params);
-  P->tw0 = reinterpret_cast<cx<double>*>(w + L.tw);
-  P->tw1 = P->tw0 + g.n0;
-  P->tw2 = P->tw1 + g.n1;
-  P->partials = reinterpret_cast<double*>(w + L.partials);
-  P->ctl = reinterpret_cast<Ctl*>(w + L.ctl);
-  P->tot = reinterpret_cast<double*>(w + L.tot);
-  P->resp = reinterpret_cast<double*>(w + L.resp);
+  unsigned char* wsp = static_cast<unsigned char*>(dev_workspace);
+  P->ws = wsp;
+  P->S = wsp + L.S;
+  P->E = wsp + L.E;
+  P->Eprev = wsp + L.Eprev;
+  P->base = wsp + L.base;
+  P->pq = reinterpret_cast<double*>(wsp + L.pq);
+  P->out_tm = wsp + L.out_tm;
+  P->out_pq = reinterpret_cast<double*>(wsp + L.out_pq);
+  P->phase = wsp + L.phase;
+  P->params = reinterpret_cast<PhaseC*>(wsp + L.params);
+  P->tw0 = wsp + L.tw;
+  P->partials = reinterpret_cast<double*>(wsp + L.partials);
+  P->ctl = reinterpret_cast<Ctl*>(wsp + L.ctl);
+  P->tot = reinterpret_cast<double*>(wsp + L.tot);
+  P->resp = reinterpret_cast<double*>(wsp + L.resp);
   P->tol = prob->tol;
   P->max_iter = prob->max_iter;
   P->norm = prob->err_norm;
@@ -367,8 +545,9 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
     g_err = std::string(#call) + ": " + hipGetErrorString(e);                            \
     return cleanup(MP_E_DEVICE);                                                         \
   }
+  CREATE_TRY(Eng<double>::prepare());
   CREATE_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->ctl_host), sizeof(Ctl)));
-  CREATE_TRY(hipMemsetAsync(w, 0, L.total, P->stream));
+  CREATE_TRY(hipMemsetAsync(wsp, 0, L.total, P->stream));
   CREATE_TRY(hipMemcpyAsync(P->phase, prob->phase, g.nvox, hipMemcpyHostToDevice, P->stream));
   CREATE_TRY(hipMemcpyAsync(P->params, pc.data(), pc.size() * sizeof(PhaseC), hipMemcpyHostToDevice,
                             P->stream));
@@ -399,7 +578,7 @@ mp_status mp_profile(mp_plan P, int32_t enable) {
 
 mp_status mp_profile_read(mp_plan P, int32_t n, double* ms_total, int64_t* launches) {
   if (!P || !ms_total || !launches || n < 0) return fail(MP_E_INVALID, "bad argument");
-  for (int j = 0; j < n && j < 7; ++j) {
+  for (int j = 0; j < n && j < kProfEv - 1; ++j) {
     ms_total[j] = P->prof_ms[j];
     launches[j] = P->prof_n[j];
   }
@@ -429,96 +608,9 @@ mp_status mp_solve_load_path(mp_plan P, int32_t n_steps, const double* times, co
     return fail(MP_E_STATE, "times[0] must equal the time of the last committed step");
   for (int s = 1; s <= n_steps; ++s)
     if (!(times[s] > times[s - 1])) return fail(MP_E_INVALID, "times must increase");
-  if (P->steps == 0) P->t_prev = P->t_cur = times[0];
-  const Geometry& g = P->g;
-  for (int s = 1; s <= n_steps; ++s) {
-    XArgs<double> xa = xargs(P);
-    for (int c = 0; c < 9; ++c) {
-      xa.mac[c] = E[(s - 1) * 9 + c];
-      xa.mac[9 + c] = Gam[(s - 1) * 9 + c];
-    }
-    xa.first = P->steps == 0;
-    // Alg. 2 linear extrapolation ratio (t_n - t_{n-1}) / (t_{n-1} - t_{n-2})
-    xa.r = P->steps == 0 ? 0.0 : (times[s] - P->t_cur) / (P->t_cur - P->t_prev);
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(1), 0, P->stream, P->ctl, P->fixed, P->max_iter,
-                       P->tol, P->norm);
-    P->ctl_host->iters = 0;
-    P->ctl_host->done = 0;
-    // first iterate (extrapolated or uniform), its return map and polarization
-    xa.ctl = nullptr;
-    hipLaunchKernelGGL((k_xpass<double, X_INIT>), dim3(g.xblocks), dim3(g.xthreads), xshared(g),
-                       P->stream, xa);
-    xa.ctl = P->ctl;
-    ErrMacro em;
-    for (int c = 0; c < 18; ++c) em.v[c] = xa.mac[c];
-    int batch = 2;
-    long queued = 0;
-    for (;;) {
-      // the control block ends every step within max_iter (or the fixed count)
-      // iterations; a loop that runs far past that means a broken device state
-      if (queued > long(std::max(P->max_iter, P->fixed)) + 256)
-        return fail(MP_E_DEVICE, "iteration control did not finish the step");
-      queued += batch;
-      const int it0 = P->ctl_host->iters;
-      if (P->prof && P->ev.size() < size_t(batch) * kProfEv) {
-        const size_t old = P->ev.size();
-        P->ev.resize(size_t(batch) * kProfEv);
-        for (size_t i = old; i < P->ev.size(); ++i) HIP_TRY(hipEventCreate(&P->ev[i]));
-      }
-      for (int k = 0; k < batch; ++k) {
-        hipEvent_t* ev = P->prof ? &P->ev[size_t(k) * kProfEv] : nullptr;
-        enqueue_spectral(P, P->ctl, ev);
-        hipLaunchKernelGGL((k_xpass<double, X_ITER>), dim3(g.xblocks), dim3(g.xthreads), xshared(g),
-                           P->stream, xa);
-        if (ev) HIP_TRY(hipEventRecord(ev[6], P->stream));
-        hipLaunchKernelGGL(k_err_rows, dim3(kNPart), dim3(256), 0, P->stream, P->partials, g.xblocks,
-                           P->tot, P->ctl);
-        hipLaunchKernelGGL(k_err_final, dim3(1), dim3(64), 0, P->stream, P->tot, g.nvox, P->ctl, em);
-        if (ev) HIP_TRY(hipEventRecord(ev[7], P->stream));
-      }
-      HIP_TRY(hipGetLastError());
-      HIP_TRY(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P->stream));
-      HIP_TRY(hipStreamSynchronize(P->stream));
-      if (P->prof) {
-        // only iterations that really ran (later ones returned at once)
-        const int ran = std::min(batch, P->ctl_host->iters - it0);
-        for (int k = 0; k < ran; ++k)
-          for (int j = 0; j < kProfEv - 1; ++j) {
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, P->ev[size_t(k) * kProfEv + j],
-                                        P->ev[size_t(k) * kProfEv + j + 1]));
-            // kernel order: y fwd, z fwd, green, z inv, y inv, x pass, error reduce
-            P->prof_ms[j] += ms;
-            P->prof_n[j] += 1;
-          }
-      }
-      if (P->ctl_host->done) break;
-      batch = std::min(batch * 2, 64);
-    }
-    const Ctl c = *P->ctl_host;
-    // commit
-    CommitArgs<double> ca{g.nvox, P->E, P->base, P->pq, P->out_tm, P->out_pq, P->phase, P->params,
-                          P->partials};
-    hipLaunchKernelGGL((k_commit<double>), dim3(g.commit_blocks), dim3(256), 0, P->stream, ca);
-    hipLaunchKernelGGL(k_avg_reduce, dim3(1), dim3(256), 0, P->stream, P->partials, g.commit_blocks,
-                       g.nvox, P->resp);
-    std::vector<double> r(42, 0.0);
-    HIP_TRY(hipMemcpyAsync(r.data(), P->resp, kNAvg * sizeof(double), hipMemcpyDeviceToHost,
-                           P->stream));
-    HIP_TRY(hipStreamSynchronize(P->stream));
-    r[40] = c.err;
-    r[41] = c.iters;
-    P->resp_hist.push_back(r);
-    P->steps += 1;
-    P->t_prev = P->t_cur;
-    P->t_cur = times[s];
-    if (iters) iters[s - 1] = c.iters;
-    if (c.done == 2)
-      return fail(MP_E_NOT_CONVERGED, "step " + std::to_string(P->steps) + " hit max_iter");
-    if (c.done == 3)
-      return fail(MP_E_DIVERGED, "step " + std::to_string(P->steps) + " diverged");
-  }
-  return MP_OK;
+  for (int i = 0; i < 9 * n_steps; ++i)
+    if (!std::isfinite(E[i]) || !std::isfinite(Gam[i])) return fail(MP_E_INVALID, "non-finite load");
+  return Eng<double>::solve(P, n_steps, times, E, Gam, iters);
 }
 
 mp_status mp_homogenized_response(mp_plan P, int32_t step, double out[42]) {
@@ -534,10 +626,10 @@ mp_status mp_get_fields(mp_plan P, int32_t field, double* dst) {
   const double* src = nullptr;
   long count = 9 * n;
   switch (field) {
-    case MP_FIELD_E: src = P->E; break;
-    case MP_FIELD_GAMMA: src = P->E + 9 * n; break;
-    case MP_FIELD_T: src = P->out_tm; break;
-    case MP_FIELD_M: src = P->out_tm + 9 * n; break;
+    case MP_FIELD_E: src = static_cast<const double*>(P->E); break;
+    case MP_FIELD_GAMMA: src = static_cast<const double*>(P->E) + 9 * n; break;
+    case MP_FIELD_T: src = static_cast<const double*>(P->out_tm); break;
+    case MP_FIELD_M: src = static_cast<const double*>(P->out_tm) + 9 * n; break;
     case MP_FIELD_P: src = P->out_pq; count = n; break;
     case MP_FIELD_Q: src = P->out_pq + n; count = n; break;
     default: return fail(MP_E_INVALID, "unknown field");
@@ -549,20 +641,16 @@ mp_status mp_get_fields(mp_plan P, int32_t field, double* dst) {
 
 mp_status mp_spectrum_forward(mp_plan P, const void* dev_in, void* dev_out) {
   if (!P || !dev_in || !dev_out) return fail(MP_E_INVALID, "NULL argument");
+  using E8 = Eng<double>;
   const Geometry& g = P->g;
-  XArgs<double> xa = xargs(P);
+  XArgs<double> xa = E8::xargs(P);
   xa.ctl = nullptr;
   xa.fin = static_cast<const double*>(dev_in);
-  xa.S = static_cast<cx<double>*>(dev_out);
-  hipLaunchKernelGGL((k_xpass<double, X_FWD_ONLY>), dim3(g.xblocks), dim3(g.xthreads), xshared(g),
-                     P->stream, xa);
   cx<double>* S = static_cast<cx<double>*>(dev_out);
-  AxisArgs<double> ay{S, g.nspec, long(g.n1) * g.nh, g.nh, g.n1, g.txy, g.s1, P->tw1, nullptr};
-  AxisArgs<double> az{S, g.nspec, g.nh, long(g.n1) * g.nh, g.n2, g.txz, g.s2, P->tw2, nullptr};
-  hipLaunchKernelGGL((k_axis<double, false>), dim3(g.nh / g.txy, g.n2, 18), dim3(256),
-                     size_t(g.n1) * g.txy * sizeof(cx<double>), P->stream, ay);
-  hipLaunchKernelGGL((k_axis<double, false>), dim3(g.nh / g.txz, g.n1, 18), dim3(256),
-                     size_t(g.n2) * g.txz * sizeof(cx<double>), P->stream, az);
+  xa.S = S;
+  launch_x<double, X_FWD_ONLY>(g.n0, g.xblocks, P->stream, xa);
+  launch_axis<double, Y_FWD>(g.n1, g.txy, E8::ygrid(g), P->stream, E8::yargs(P, S, nullptr));
+  launch_axis<double, Z_FWD>(g.n2, g.txz, E8::zgrid(g), P->stream, E8::zargs(P, S, nullptr));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(P->stream));
   return MP_OK;
@@ -570,16 +658,15 @@ mp_status mp_spectrum_forward(mp_plan P, const void* dev_in, void* dev_out) {
 
 mp_status mp_green_apply(mp_plan P, const void* dev_in, void* dev_out) {
   if (!P || !dev_in || !dev_out) return fail(MP_E_INVALID, "NULL argument");
+  using E8 = Eng<double>;
   const Geometry& g = P->g;
-  XArgs<double> xa = xargs(P);
+  XArgs<double> xa = E8::xargs(P);
   xa.ctl = nullptr;
   xa.fin = static_cast<const double*>(dev_in);
-  hipLaunchKernelGGL((k_xpass<double, X_FWD_ONLY>), dim3(g.xblocks), dim3(g.xthreads), xshared(g),
-                     P->stream, xa);
-  enqueue_spectral(P, nullptr);
+  launch_x<double, X_FWD_ONLY>(g.n0, g.xblocks, P->stream, xa);
+  E8::spectral(P, E8::S(P), nullptr, nullptr);
   xa.fout = static_cast<double*>(dev_out);
-  hipLaunchKernelGGL((k_xpass<double, X_INV_ONLY>), dim3(g.xblocks), dim3(g.xthreads), xshared(g),
-                     P->stream, xa);
+  launch_x<double, X_INV_ONLY>(g.n0, g.xblocks, P->stream, xa);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(P->stream));
   return MP_OK;

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_lib", "libmp.so")
+# MP_LIB selects another build of the same library (e.g. an A/B variant)
+LIB_PATH = os.environ.get("MP_LIB") or os.path.join(HERE, "_lib", "libmp.so")
 
 MP_OK, MP_E_INVALID, MP_E_NOMEM, MP_E_DEVICE, MP_E_NOT_CONVERGED, MP_E_DIVERGED, MP_E_STATE = range(7)
 STATUS_NAMES = {0: "MP_OK", 1: "MP_E_INVALID", 2: "MP_E_NOMEM", 3: "MP_E_DEVICE",
@@ -201,9 +202,9 @@ class Plan:
         x = fields.contiguous()
         assert x.dtype == self.torch.float64 and x.numel() == 18 * self.nvox and x.device == self.device
         n2, n1, n0 = self.shape
-        out = self.torch.empty((18, n2, n1, n0 // 2, 2), dtype=self.torch.float64, device=self.device)
+        out = self.torch.empty((n2, n1, n0 // 2, 18, 2), dtype=self.torch.float64, device=self.device)
         check(lib.mp_spectrum_forward(self.handle, _ptr(x), _ptr(out)))
-        return self.torch.view_as_complex(out)
+        return self.torch.view_as_complex(out)   # [kz][ky][kx][c]
 
     def radial_return(self, phase, e, g, e_n, g_n, t_n, m_n, p_n, q_n):
         """Alg. 1 on n independent points; tensors on the plan's device, float64
@@ -223,16 +224,17 @@ class Plan:
                                    _ptr(t), _ptr(m), _ptr(p), _ptr(q)))
         return t, m, p, q
 
-    KERNELS = ("y_fwd", "z_fwd", "green", "z_inv", "y_inv", "x_pass", "err_reduce")
+    KERNELS = ("y_fwd", "z_green", "y_inv", "x_pass", "err_reduce")
 
     def profile(self, enable=True):
         check(lib.mp_profile(self.handle, 1 if enable else 0))
 
     def profile_read(self):
         """{kernel: (total ms, launches)} accumulated since profile(True)."""
-        ms = (C.c_double * 7)()
-        n = (C.c_int64 * 7)()
-        check(lib.mp_profile_read(self.handle, 7, ms, n))
+        k = len(self.KERNELS)
+        ms = (C.c_double * k)()
+        n = (C.c_int64 * k)()
+        check(lib.mp_profile_read(self.handle, k, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(self.KERNELS)}
 
     def close(self):

@@ -28,15 +28,28 @@ HBM_PEAK_GBS = 8000.0
 #            and 18 half spectra (18 w)
 #   y passes, fused z pass (z forward + Green operator + z inverse):
 #            read + write 18 half spectra (36 w)
-BYTES_PER_VOXEL = {
-    "x_pass": 90 * 8 + 16 + 1,
-    "y_fwd": 36 * 8, "z_green": 36 * 8, "y_inv": 36 * 8,
-    "err_reduce": 0,
+def bytes_per_voxel(w):
+    """w = bytes per bulk word (8 FP64, 4 mixed); p_n, q_n stay FP64."""
+    return {"x_pass": 90 * w + 16 + 1, "y_fwd": 36 * w, "z_green": 36 * w, "y_inv": 36 * w,
+            "err_reduce": 0}
+
+
+WORKLOADS = {
+    "spheres128_fp64": dict(
+        precision="fp64", dtype="f64",
+        desc="spheres128_fp64: 128^3 voxels, 40 random elastic spheres r~U[6,12], contrast 10, "
+             "E11->0.02 + Gamma12->0.002 over 50 steps, tol 1e-8 (Eq. 38)"),
+    "spheres256_mixed": dict(
+        precision="mixed", dtype="f32 bulk / f64 reductions",
+        desc="spheres256_mixed: 256^3 voxels, random elastic spheres r~U[5,15] to volume fraction "
+             "0.25, contrast 10, E11->0.01 over 20 steps, tol 1e-6 (Eq. 38), FP32 bulk arithmetic"),
 }
-BYTES_PER_VOXEL_ITER = sum(BYTES_PER_VOXEL.values())
 
 
 def cpu_baseline(wl, iters=2):
+    nvox = wl.phase_map.size
+    if nvox > 128 ** 3:
+        iters = 1
     """The oracle, untuned, on a bounded sample: load step 1 of the same cell
     with a fixed schedule of `iters` loop iterations (setup excluded)."""
     from threadpoolctl import threadpool_limits
@@ -46,9 +59,8 @@ def cpu_baseline(wl, iters=2):
         t0 = time.perf_counter()
         solver.solve(wl.times[:2], wl.E[:1], wl.G[:1], schedule=[iters])
         dt = time.perf_counter() - t0
-    nvox = wl.phase_map.size
     return {"value": iters * nvox / dt, "unit": "voxel-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"load step 1 of the same 128^3 cell, {iters} fixed-point iterations "
+            "sample": f"load step 1 of the same cell, {iters} fixed-point iteration(s) "
                       f"(plus the first iterate and commit), {dt:.1f} s wall, 1 thread"}
 
 
@@ -59,6 +71,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--workload", default="spheres128_fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="run every load step for exactly this many iterations (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
@@ -69,9 +84,17 @@ def main():
     from paper_2409_10774_amd import mp, workloads as W
 
     W_, K = args.warmup, args.steps
-    wl = W.random_spheres_128(n_steps=W_ + K)
+    cfg = WORKLOADS[args.workload]
+    if args.workload == "spheres128_fp64":
+        wl = W.random_spheres_128(n_steps=W_ + K)
+    else:
+        wl = W.random_spheres_256(n_steps=W_ + K)
     nvox = wl.phase_map.size
-    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol)
+    BYTES_PER_VOXEL = bytes_per_voxel(8 if cfg["precision"] == "fp64" else 4)
+    BYTES_PER_VOXEL_ITER = sum(BYTES_PER_VOXEL.values())
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision=cfg["precision"])
+    if args.fixed_iters:
+        plan.set_fixed_iterations(args.fixed_iters)
     print(f"# workload {wl.name}: {wl.info}, warmup {W_} step(s), timed {K}", file=sys.stderr,
           flush=True)
     if W_ > 0:
@@ -118,11 +141,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": cfg["dtype"],
         "data": "synthetic (seeded random-sphere microstructure)",
-        "config": {"workload": "spheres128_fp64: 128^3 voxels, 40 random elastic spheres r~U[6,12], "
-                               "contrast 10, E11->0.02 + Gamma12->0.002 over 50 steps, tol 1e-8 (Eq. 38)",
-                   "timed_load_steps": [W_ + 1, W_ + K], "iterations": iters,
+        "config": {"workload": cfg["desc"], "timed_load_steps": [W_ + 1, W_ + K],
+                   "iterations": iters, "fixed_iters": args.fixed_iters or None,
                    "parallelism": "single GPU"},
         "iteration_hbm_frac": round(BYTES_PER_VOXEL_ITER * value / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roof,

@@ -48,7 +48,8 @@ typedef enum {
   MP_E_NOMEM = 2,          /* workspace smaller than mp_plan_workspace_size */
   MP_E_DEVICE = 3,         /* a HIP call failed */
   MP_E_NOT_CONVERGED = 4,  /* max_iter reached in a step; that step is committed */
-  MP_E_DIVERGED = 5,       /* non-finite or exploding error measure; step committed */
+  MP_E_DIVERGED = 5,       /* non-finite error measure, or one grown 1e6 x above the
+                              step's smallest; step committed */
   MP_E_STATE = 6           /* call not valid in the plan's current state */
 } mp_status;
 
@@ -80,7 +81,13 @@ typedef struct {
   double tol;               /* epsilon of Alg. 2 (> 0) */
   int32_t max_iter;         /* loop cap per step (>= 1) */
   int32_t err_norm;         /* MP_ERR_LOCAL | MP_ERR_AVERAGE */
-  int32_t precision;        /* MP_FP64 (MP_MIXED is rejected by this build) */
+  int32_t precision;        /* MP_FP64, or MP_MIXED: spectra, strain, history
+                               base and the FFT / Green / Alg. 1 arithmetic in
+                               FP32; p, q, the error measure (Eqs. 36-38) and
+                               every volume average in FP64; a step also ends
+                               when the error measure stops improving for 100
+                               iterations (its FP32 rounding floor), which
+                               mp_step_error_parts reports */
 } mp_problem;
 
 typedef struct mp_plan_s* mp_plan;
@@ -117,6 +124,12 @@ mp_status mp_solve_load_path(mp_plan plan, int32_t n_steps, const double* times,
  * err iterations, all volume averages in FP64. */
 mp_status mp_homogenized_response(mp_plan plan, int32_t step, double out[42]);
 
+/* The four terms of the error measure (Eq. 36) at the end of committed step
+ * `step`: out[5] = err_e, err_t, err_gamma, err_m (Eq. 38 or Eq. 37), and
+ * 1.0 when the step ended at the rounding floor of the MP_MIXED form (no
+ * new smallest error for 100 iterations while above tol), else 0.0. */
+mp_status mp_step_error_parts(mp_plan plan, int32_t step, double out[5]);
+
 /* Copy one field of the current state (after the last committed step) to
  * host memory as FP64: MP_FIELD_E/GAMMA/T/M write 9*n doubles (SoA),
  * MP_FIELD_P/Q write n doubles.  Blocks. */
@@ -135,6 +148,8 @@ mp_status mp_plan_steps(mp_plan plan, int32_t* steps);
  * 18*n device doubles receiving the fluctuating strain then curvature
  * (no averages added).  Uses the plan's transforms and reference medium. */
 mp_status mp_green_apply(mp_plan plan, const void* dev_in, void* dev_out);
+/* (mp_green_apply, mp_spectrum_forward and mp_radial_return accept FP64
+ * plans only and return MP_E_INVALID for MP_MIXED plans.) */
 
 /* Forward transform of 18 real fields (device, 18*n doubles, SoA) to their
  * half spectra: dev_out receives n[2] * n[1] * (n[0]/2) * 18 complex doubles

@@ -32,15 +32,19 @@ struct ErrMacro {
 };
 
 struct Ctl {
-  int done;       // 0 running, 1 converged / fixed count reached, 2 max_iter, 3 diverged
+  int done;       // 0 running, 1 converged / fixed count reached, 2 max_iter, 3 diverged,
+                  // 4 stopped at the rounding floor of the low-precision form
   int iters;      // loop iterations of the current step
   int fixed;      // > 0: run exactly this many iterations
   int max_iter;
   double err;
   double tol;
   int norm;       // 0 local (Eq. 38), 1 average (Eq. 37)
-  int pad;
+  int window;     // > 0: floor stop after this many iterations without a new best err
   double err_parts[4];
+  double best;    // smallest err of the step so far
+  int best_it;    // iteration that reached it
+  int pad;
 };
 
 enum XMode { X_ITER = 0, X_INIT = 1, X_FWD_ONLY = 2, X_INV_ONLY = 3 };
@@ -74,9 +78,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+// NaN-propagating max (a non-finite field must not look converged)
+__device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  for (int o = 32; o > 0; o >>= 1) v = nmax(v, __shfl_xor(v, o, 64));
   return v;
 }
 
@@ -92,9 +98,23 @@ struct XShape {
   static constexpr int NH = N0 / 2;
 };
 
-// x pass: rows of N0 voxels, all 18 components.  LDS holds 9 packed complex
-// pencils per row: pencil q = field 2q + i field 2q+1 (two real transforms
-// in one complex transform).  Lanes [0, VPAD) run the macro level of Alg. 1
+// Real fields packed two per complex pencil for the x transforms, only like
+// with like: pencils 0-3 carry strain-like components 0-7 in pairs, pencil 4
+// component 8 alone, pencils 5-8 curvature-like components 9-16 in pairs,
+// pencil 9 component 17 alone.  (Unpacking a field from a pencil shared with
+// a much larger one would cost it relative precision.)
+constexpr int kPencils = 10;
+__device__ __forceinline__ int pencil_of(int c) {
+  return c < 8 ? (c >> 1) : c == 8 ? 4 : c < 17 ? 5 + ((c - 9) >> 1) : 9;
+}
+__device__ __forceinline__ int part_of(int c) {
+  return c < 8 ? (c & 1) : (c == 8 || c == 17) ? 0 : ((c - 9) & 1);
+}
+__device__ __forceinline__ int pencil_re(int q) { return q < 5 ? 2 * q : 2 * q - 1; }
+__device__ __forceinline__ int pencil_im(int q) { return (q == 4 || q == 9) ? -1 : pencil_re(q) + 1; }
+
+// x pass: rows of N0 voxels, all 18 components, held in LDS as 10 complex
+// pencils per row (two real transforms in one complex transform).  Lanes [0, VPAD) run the macro level of Alg. 1
 // (e -> t, tau), lanes [VPAD, 2 VPAD) the micro level (gamma -> m, mu): the
 // levels are independent, which halves each lane's live state, and the level
 // is uniform over each wavefront.  Each lane prefetches its old strain,
@@ -103,7 +123,7 @@ template <class T, int MODE, int N0>
 __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
   using X = XShape<N0>;
   constexpr int ROWS = X::ROWS, VPB = X::VPB, VPAD = X::VPAD, NTHR = X::NTHR, NH = X::NH;
-  constexpr int NPK = 9 * ROWS;
+  constexpr int NPK = kPencils * ROWS;
   if (a.ctl && a.ctl->done) return;
   __shared__ cx<T> lds[NPK * N0];
   __shared__ double red[NTHR / 64][kLev];
@@ -139,13 +159,14 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
 
   if (MODE == X_ITER || MODE == X_INV_ONLY) {
     // half spectra -> packed full spectra Z = A + i B, Z(n0 - k) = conj A + i conj B
-    for (int w = tid; w < rows_here * NH * 9; w += NTHR) {
-      const int r = w / (NH * 9), rem = w % (NH * 9);
-      const int kx = rem / 9, q = rem % 9;
-      const cx<T>* srow = a.S + (row0 + r) * (NH * 18) + kx * 18 + 2 * q;
-      const cx<T> A = srow[0];
-      const cx<T> B = srow[1];
-      cx<T>* pen = lds + (r * 9 + q) * N0;
+    for (int w = tid; w < rows_here * NH * kPencils; w += NTHR) {
+      const int r = w / (NH * kPencils), rem = w % (NH * kPencils);
+      const int kx = rem / kPencils, q = rem % kPencils;
+      const cx<T>* srow = a.S + (row0 + r) * (NH * 18) + kx * 18;
+      const int cre = pencil_re(q), cim = pencil_im(q);
+      const cx<T> A = srow[cre];
+      const cx<T> B = cim >= 0 ? srow[cim] : cx<T>{T(0), T(0)};
+      cx<T>* pen = lds + (r * kPencils + q) * N0;
       pen[kx] = cx<T>{A.re - B.im, A.im + B.re};
       if (kx > 0)
         pen[N0 - kx] = cx<T>{A.re + B.im, B.re - A.im};
@@ -157,7 +178,7 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
   }
 
   // LDS scalar slot of field c (0..17) of this lane's voxel
-  auto slot = [&](int c) { return 2 * ((vr * 9 + (c >> 1)) * N0 + vx) + (c & 1); };
+  auto slot = [&](int c) { return 2 * ((vr * kPencils + pencil_of(c)) * N0 + vx) + part_of(c); };
 
   if (MODE == X_INV_ONLY) {
     if (own)
@@ -198,6 +219,9 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
         }
       }
     }
+    // the single-field pencil of this level (4 or 9) has no imaginary field:
+    // clear it, the transform must not read stale LDS
+    if (own) ldr[2 * ((vr * kPencils + (lvl ? 9 : 4)) * N0 + vx) + 1] = T(0);
     if (MODE == X_FWD_ONLY) {
       if (own)
 #pragma unroll
@@ -271,7 +295,7 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
           // waves [0, VPAD/64) hold level 0, the rest level 1
           const int w0 = L * (VPAD / 64), w1 = w0 + VPAD / 64;
           double y = red[w0][j];
-          for (int w = w0 + 1; w < w1; ++w) y = (j < 2) ? fmax(y, red[w][j]) : y + red[w][j];
+          for (int w = w0 + 1; w < w1; ++w) y = (j < 2) ? nmax(y, red[w][j]) : y + red[w][j];
           a.partials[(long)tid * gridDim.x + blockIdx.x] = y;
         }
       }
@@ -280,15 +304,16 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
   __syncthreads();
   fft_ct<T, false, N0, 1, NPK, 1, N0, false, NTHR>(lds, a.tw, tid);
   // unpack: A = (Z(k) + conj Z(-k)) / 2, B = (Z(k) - conj Z(-k)) / (2 i)
-  for (int w = tid; w < rows_here * NH * 9; w += NTHR) {
-    const int r = w / (NH * 9), rem = w % (NH * 9);
-    const int kx = rem / 9, q = rem % 9;
-    const cx<T>* pen = lds + (r * 9 + q) * N0;
+  for (int w = tid; w < rows_here * NH * kPencils; w += NTHR) {
+    const int r = w / (NH * kPencils), rem = w % (NH * kPencils);
+    const int kx = rem / kPencils, q = rem % kPencils;
+    const cx<T>* pen = lds + (r * kPencils + q) * N0;
     const cx<T> zk = pen[kx];
     const cx<T> zm = pen[kx == 0 ? 0 : N0 - kx];
-    cx<T>* srow = a.S + (row0 + r) * (NH * 18) + kx * 18 + 2 * q;
-    srow[0] = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
-    srow[1] = cx<T>{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
+    cx<T>* srow = a.S + (row0 + r) * (NH * 18) + kx * 18;
+    const int cre = pencil_re(q), cim = pencil_im(q);
+    srow[cre] = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
+    if (cim >= 0) srow[cim] = cx<T>{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
   }
 }
 
@@ -388,16 +413,16 @@ __global__ void __launch_bounds__(256) k_err_rows(const double* partials, int nb
   int b = tid;
   for (; b + 256 < nblk; b += 512) {
     const double x = row[b], y = row[b + 256];
-    v0 = mx ? fmax(v0, x) : v0 + x;
-    v1 = mx ? fmax(v1, y) : v1 + y;
+    v0 = mx ? nmax(v0, x) : v0 + x;
+    v1 = mx ? nmax(v1, y) : v1 + y;
   }
-  if (b < nblk) v0 = mx ? fmax(v0, row[b]) : v0 + row[b];
-  double v = mx ? fmax(v0, v1) : v0 + v1;
+  if (b < nblk) v0 = mx ? nmax(v0, row[b]) : v0 + row[b];
+  double v = mx ? nmax(v0, v1) : v0 + v1;
   v = mx ? wave_max(v) : wave_sum(v);
   if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
   if (tid == 0)
-    tot[j] = mx ? fmax(fmax(red[0], red[1]), fmax(red[2], red[3]))
+    tot[j] = mx ? nmax(nmax(red[0], red[1]), nmax(red[2], red[3]))
                 : ((red[0] + red[1]) + (red[2] + red[3]));
 }
 
@@ -430,20 +455,29 @@ __global__ void k_err_final(const double* tot, long nvox, Ctl* ctl, ErrMacro mac
   ctl->err = err;
   const int it = ctl->iters + 1;
   ctl->iters = it;
+  if (err < ctl->best * (1.0 - 1e-3)) {
+    ctl->best = err;
+    ctl->best_it = it;
+  }
+  // divergence: a non-finite measure, or growth far above the step's best
+  // (a large err alone is legitimate when a field's mean is nearly zero)
+  const bool diverged = !(err <= 1e300) || (it > 5 && err > 1e6 * ctl->best);
   int done = 0;
-  if (ctl->fixed > 0) {
-    if (it >= ctl->fixed) done = 1;
-  } else if (!(err <= 1e4)) {
+  if (diverged) {
     done = 3;
+  } else if (ctl->fixed > 0) {
+    if (it >= ctl->fixed) done = 1;
   } else if (err <= ctl->tol) {
     done = 1;
   } else if (it >= ctl->max_iter) {
     done = 2;
+  } else if (ctl->window > 0 && it - ctl->best_it >= ctl->window) {
+    done = 4;
   }
   ctl->done = done;
 }
 
-__global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm) {
+__global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm, int window) {
   ctl->done = 0;
   ctl->iters = 0;
   ctl->fixed = fixed;
@@ -451,6 +485,9 @@ __global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int n
   ctl->err = 2.0 * tol;
   ctl->tol = tol;
   ctl->norm = norm;
+  ctl->window = window;
+  ctl->best = 1e300;
+  ctl->best_it = 0;
 }
 
 // commit (last line of the step loop): final return map, new history base,

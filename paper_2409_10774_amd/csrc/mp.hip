@@ -124,6 +124,7 @@ struct Geometry {
 };
 
 constexpr int kProfEv = 6;     // boundaries around the 5 loop kernels of one iteration
+constexpr int kFloorWindow = 100;
 
 }  // namespace
 
@@ -174,7 +175,7 @@ mp_status validate(const mp_problem* p, Geometry* g) {
   if (p->max_iter < 1) return fail(MP_E_INVALID, "max_iter must be >= 1");
   if (p->err_norm != MP_ERR_LOCAL && p->err_norm != MP_ERR_AVERAGE)
     return fail(MP_E_INVALID, "err_norm");
-  if (p->precision != MP_FP64) return fail(MP_E_INVALID, "only MP_FP64 is built");
+  if (p->precision != MP_FP64 && p->precision != MP_MIXED) return fail(MP_E_INVALID, "precision");
   if (p->ref_mode < 0 || p->ref_mode > 2) return fail(MP_E_INVALID, "ref_mode");
   for (int i = 0; i < p->n_phases; ++i) {
     const mp_phase& c = p->phases[i];
@@ -365,8 +366,10 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     xa.first = P->steps == 0;
     // Alg. 2 linear extrapolation ratio (t_n - t_{n-1}) / (t_{n-1} - t_{n-2})
     xa.r = P->steps == 0 ? 0.0 : (times[s] - P->t_cur) / (P->t_cur - P->t_prev);
+    // the low-precision form may stop at its rounding floor: no new best
+    // error for kFloorWindow iterations (flagged in the step record)
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(1), 0, P->stream, P->ctl, P->fixed, P->max_iter,
-                       P->tol, P->norm);
+                       P->tol, P->norm, sizeof(T) < sizeof(double) ? kFloorWindow : 0);
     P->ctl_host->iters = 0;
     P->ctl_host->done = 0;
     // first iterate (extrapolated or uniform), its return map and polarization
@@ -424,12 +427,14 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     hipLaunchKernelGGL((k_commit<T>), dim3(g.commit_blocks), dim3(256), 0, P->stream, ca);
     hipLaunchKernelGGL(k_avg_reduce, dim3(1), dim3(256), 0, P->stream, P->partials, g.commit_blocks,
                        g.nvox, P->resp);
-    std::vector<double> r(42, 0.0);
+    std::vector<double> r(47, 0.0);
     HIP_TRY(hipMemcpyAsync(r.data(), P->resp, kNAvg * sizeof(double), hipMemcpyDeviceToHost,
                            P->stream));
     HIP_TRY(hipStreamSynchronize(P->stream));
     r[40] = c.err;
     r[41] = c.iters;
+    for (int f = 0; f < 4; ++f) r[42 + f] = c.err_parts[f];
+    r[46] = c.done == 4 ? 1.0 : 0.0;
     P->resp_hist.push_back(r);
     P->steps += 1;
     P->t_prev = P->t_cur;
@@ -455,7 +460,7 @@ mp_status mp_plan_workspace_size(const mp_problem* prob, size_t* bytes) {
   mp_status s = validate(prob, &g);
   if (s != MP_OK) return s;
   if (!bytes) return fail(MP_E_INVALID, "bytes is NULL");
-  *bytes = layout(g, sizeof(double)).total;
+  *bytes = layout(g, prob->precision == MP_MIXED ? sizeof(float) : sizeof(double)).total;
   return MP_OK;
 }
 
@@ -465,7 +470,8 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   mp_status s = validate(prob, &g);
   if (s != MP_OK) return s;
   if (!out) return fail(MP_E_INVALID, "out is NULL");
-  const size_t w = sizeof(double);
+  const bool mixed = prob->precision == MP_MIXED;
+  const size_t w = mixed ? sizeof(float) : sizeof(double);
   Layout L = layout(g, w);
   if (!dev_workspace || bytes < L.total)
     return fail(MP_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
@@ -534,25 +540,39 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   std::vector<PhaseC> pc(256);
   for (int i = 0; i < prob->n_phases; ++i) pc[i] = derive(prob->phases[i]);
   std::vector<cx<double>> tw;
-  twiddles(g.n0, &tw);
-  twiddles(g.n1, &tw);
-  twiddles(g.n2, &tw);
+  std::vector<cx<float>> twf;
+  if (mixed) {
+    twiddles(g.n0, &twf);
+    twiddles(g.n1, &twf);
+    twiddles(g.n2, &twf);
+  } else {
+    twiddles(g.n0, &tw);
+    twiddles(g.n1, &tw);
+    twiddles(g.n2, &tw);
+  }
 
   auto cleanup = [&](mp_status st) { delete P; return st; };
   hipError_t e;
 #define CREATE_TRY(call)                                                                 \
-  if ((e = (call)) != hipSuccess) {                                                      \
-    g_err = std::string(#call) + ": " + hipGetErrorString(e);                            \
-    return cleanup(MP_E_DEVICE);                                                         \
-  }
-  CREATE_TRY(Eng<double>::prepare());
+  do {                                                                                   \
+    if ((e = (call)) != hipSuccess) {                                                    \
+      g_err = std::string(#call) + ": " + hipGetErrorString(e);                          \
+      return cleanup(MP_E_DEVICE);                                                       \
+    }                                                                                    \
+  } while (0)
+  CREATE_TRY(mixed ? Eng<float>::prepare() : Eng<double>::prepare());
   CREATE_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->ctl_host), sizeof(Ctl)));
   CREATE_TRY(hipMemsetAsync(wsp, 0, L.total, P->stream));
   CREATE_TRY(hipMemcpyAsync(P->phase, prob->phase, g.nvox, hipMemcpyHostToDevice, P->stream));
   CREATE_TRY(hipMemcpyAsync(P->params, pc.data(), pc.size() * sizeof(PhaseC), hipMemcpyHostToDevice,
                             P->stream));
-  CREATE_TRY(hipMemcpyAsync(P->tw0, tw.data(), tw.size() * sizeof(cx<double>), hipMemcpyHostToDevice,
-                            P->stream));
+  if (mixed) {
+    CREATE_TRY(hipMemcpyAsync(P->tw0, twf.data(), twf.size() * sizeof(cx<float>),
+                              hipMemcpyHostToDevice, P->stream));
+  } else {
+    CREATE_TRY(hipMemcpyAsync(P->tw0, tw.data(), tw.size() * sizeof(cx<double>),
+                              hipMemcpyHostToDevice, P->stream));
+  }
   CREATE_TRY(hipStreamSynchronize(P->stream));
 #undef CREATE_TRY
   *out = P;
@@ -610,6 +630,7 @@ mp_status mp_solve_load_path(mp_plan P, int32_t n_steps, const double* times, co
     if (!(times[s] > times[s - 1])) return fail(MP_E_INVALID, "times must increase");
   for (int i = 0; i < 9 * n_steps; ++i)
     if (!std::isfinite(E[i]) || !std::isfinite(Gam[i])) return fail(MP_E_INVALID, "non-finite load");
+  if (P->precision == MP_MIXED) return Eng<float>::solve(P, n_steps, times, E, Gam, iters);
   return Eng<double>::solve(P, n_steps, times, E, Gam, iters);
 }
 
@@ -620,19 +641,35 @@ mp_status mp_homogenized_response(mp_plan P, int32_t step, double out[42]) {
   return MP_OK;
 }
 
+mp_status mp_step_error_parts(mp_plan P, int32_t step, double out[5]) {
+  if (!P || !out) return fail(MP_E_INVALID, "NULL argument");
+  if (step < 1 || step > P->steps) return fail(MP_E_INVALID, "step out of range");
+  std::memcpy(out, P->resp_hist[step - 1].data() + 42, 5 * sizeof(double));
+  return MP_OK;
+}
+
 mp_status mp_get_fields(mp_plan P, int32_t field, double* dst) {
   if (!P || !dst) return fail(MP_E_INVALID, "NULL argument");
   const long n = P->g.nvox;
-  const double* src = nullptr;
+  const size_t w = P->precision == MP_MIXED ? sizeof(float) : sizeof(double);
+  const unsigned char* src = nullptr;
   long count = 9 * n;
+  bool bulk = true;   // stored in the bulk type (else FP64)
   switch (field) {
-    case MP_FIELD_E: src = static_cast<const double*>(P->E); break;
-    case MP_FIELD_GAMMA: src = static_cast<const double*>(P->E) + 9 * n; break;
-    case MP_FIELD_T: src = static_cast<const double*>(P->out_tm); break;
-    case MP_FIELD_M: src = static_cast<const double*>(P->out_tm) + 9 * n; break;
-    case MP_FIELD_P: src = P->out_pq; count = n; break;
-    case MP_FIELD_Q: src = P->out_pq + n; count = n; break;
+    case MP_FIELD_E: src = static_cast<const unsigned char*>(P->E); break;
+    case MP_FIELD_GAMMA: src = static_cast<const unsigned char*>(P->E) + 9 * n * w; break;
+    case MP_FIELD_T: src = static_cast<const unsigned char*>(P->out_tm); break;
+    case MP_FIELD_M: src = static_cast<const unsigned char*>(P->out_tm) + 9 * n * w; break;
+    case MP_FIELD_P: src = reinterpret_cast<const unsigned char*>(P->out_pq); count = n; bulk = false; break;
+    case MP_FIELD_Q: src = reinterpret_cast<const unsigned char*>(P->out_pq + n); count = n; bulk = false; break;
     default: return fail(MP_E_INVALID, "unknown field");
+  }
+  if (bulk && w == sizeof(float)) {
+    std::vector<float> tmp(count);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), src, count * sizeof(float), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    for (long i = 0; i < count; ++i) dst[i] = double(tmp[i]);
+    return MP_OK;
   }
   HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToHost, P->stream));
   HIP_TRY(hipStreamSynchronize(P->stream));
@@ -641,6 +678,7 @@ mp_status mp_get_fields(mp_plan P, int32_t field, double* dst) {
 
 mp_status mp_spectrum_forward(mp_plan P, const void* dev_in, void* dev_out) {
   if (!P || !dev_in || !dev_out) return fail(MP_E_INVALID, "NULL argument");
+  if (P->precision != MP_FP64) return fail(MP_E_INVALID, "FP64 plans only");
   using E8 = Eng<double>;
   const Geometry& g = P->g;
   XArgs<double> xa = E8::xargs(P);
@@ -658,6 +696,7 @@ mp_status mp_spectrum_forward(mp_plan P, const void* dev_in, void* dev_out) {
 
 mp_status mp_green_apply(mp_plan P, const void* dev_in, void* dev_out) {
   if (!P || !dev_in || !dev_out) return fail(MP_E_INVALID, "NULL argument");
+  if (P->precision != MP_FP64) return fail(MP_E_INVALID, "FP64 plans only");
   using E8 = Eng<double>;
   const Geometry& g = P->g;
   XArgs<double> xa = E8::xargs(P);
@@ -680,6 +719,7 @@ mp_status mp_radial_return(mp_plan P, int64_t n, const void* phase, const void* 
   if (n == 0) return MP_OK;
   if (!phase || !e || !g || !e_n || !g_n || !t_n || !m_n || !p_n || !q_n || !t || !m || !p || !q)
     return fail(MP_E_INVALID, "NULL argument");
+  if (P->precision != MP_FP64) return fail(MP_E_INVALID, "FP64 plans only");
   hipLaunchKernelGGL((k_rrm_points<double>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, P->stream,
                      long(n), static_cast<const uint8_t*>(phase), P->params,
                      static_cast<const double*>(e), static_cast<const double*>(g),

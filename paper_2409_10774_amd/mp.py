@@ -10,6 +10,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# PyTorch ships its own HIP runtime; loading it before the library makes the
+# library bind to that same runtime, so torch's device pointers and streams
+# are valid inside it (two runtimes in one process would not share devices).
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # MP_LIB selects another build of the same library (e.g. an A/B variant)
@@ -54,6 +58,7 @@ def _load():
         "mp_solve_load_path": (C.c_int, [vp, i32, dp, dp, dp, C.POINTER(i32)]),
         "mp_homogenized_response": (C.c_int, [vp, i32, dp]),
         "mp_get_fields": (C.c_int, [vp, i32, dp]),
+        "mp_step_error_parts": (C.c_int, [vp, i32, dp]),
         "mp_set_fixed_iterations": (C.c_int, [vp, i32]),
         "mp_plan_steps": (C.c_int, [vp, C.POINTER(i32)]),
         "mp_green_apply": (C.c_int, [vp, vp, vp]),
@@ -171,6 +176,12 @@ class Plan:
     def response(self, step):
         out = (C.c_double * 42)()
         check(lib.mp_homogenized_response(self.handle, int(step), out))
+        return np.array(out[:])
+
+    def error_parts(self, step):
+        """(err_e, err_t, err_gamma, err_m, floor_stop) of a committed step."""
+        out = (C.c_double * 5)()
+        check(lib.mp_step_error_parts(self.handle, int(step), out))
         return np.array(out[:])
 
     def responses(self):

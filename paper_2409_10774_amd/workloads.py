@@ -83,14 +83,24 @@ def _voxel_centres(n):
 
 
 def _paint_sphere(phase, n, c, r, value):
-    """Mark voxels whose centre lies within r of c (periodic minimum image)."""
-    x, y, z = _voxel_centres(n)
-    d2 = np.zeros(phase.shape)
-    for coord, cc, L in ((x, c[0], n[0]), (y, c[1], n[1]), (z, c[2], n[2])):
-        d = coord - cc
+    """Mark voxels whose centre lies within r of c (periodic minimum image).
+
+    Only the sphere's bounding box is visited (indices wrapped periodically).
+    """
+    idx = []
+    for ax, L in ((0, n[0]), (1, n[1]), (2, n[2])):
+        lo = int(np.floor(c[ax] - r - 0.5)) - 1
+        hi = int(np.ceil(c[ax] + r - 0.5)) + 1
+        j = np.arange(lo, hi + 1)
+        if len(j) >= L:
+            j = np.arange(L)
+        d = (np.mod(j, L) + 0.5) - c[ax]
         d -= L * np.round(d / L)
-        d2 += d * d
-    phase[d2 <= r * r] = value
+        idx.append((np.mod(j, L), d))
+    (ix, dx), (iy, dy), (iz, dz) = idx
+    d2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
+    zz, yy, xx = np.nonzero(d2 <= r * r)
+    phase[iz[zz], iy[yy], ix[xx]] = value
 
 
 def centred_sphere(n: int, vf: float) -> np.ndarray:
@@ -112,27 +122,30 @@ def random_spheres(n: int, seed: int, count: int | None, rmin: float, rmax: floa
     """
     rng = np.random.default_rng(seed)
     spheres = []
+    centres = np.zeros((0, 3))
+    radii = np.zeros(0)
     ph = np.zeros((n, n, n), np.uint8)
+    painted = 0
     tries = 0
     while tries < max_tries:
         if count is not None and len(spheres) >= count:
             break
-        if target_vf is not None and len(spheres) and (ph.mean() >= target_vf):
+        if target_vf is not None and len(spheres) and painted >= target_vf * ph.size:
             break
         tries += 1
         r = rng.uniform(rmin, rmax)
         c = rng.uniform(0.0, n, size=3)
-        ok = True
-        for (cx, cy, cz, rr) in spheres:
-            d = np.array([cx, cy, cz]) - c
+        if len(spheres):
+            d = centres - c
             d -= n * np.round(d / n)
-            if float(np.sqrt(d @ d)) < r + rr:
-                ok = False
-                break
-        if not ok:
-            continue
+            if np.any(np.sqrt((d * d).sum(axis=1)) < r + radii):
+                continue
         spheres.append((float(c[0]), float(c[1]), float(c[2]), float(r)))
+        centres = np.vstack([centres, c])
+        radii = np.append(radii, r)
+        before = int(np.count_nonzero(ph))
         _paint_sphere(ph, (n, n, n), c, r, 1)
+        painted += int(np.count_nonzero(ph)) - before if target_vf is not None else 0
     return ph, spheres
 
 

@@ -49,7 +49,6 @@ def test_workspace_size_scales_with_grid():
 @pytest.mark.parametrize("change,msg", [
     (dict(tol=0.0), "tol"),
     (dict(max_iter=0), "max_iter"),
-    (dict(precision="mixed"), "MP_FP64"),
     (dict(h=-1.0), "h must"),
 ])
 def test_rejects_bad_problem(change, msg):
@@ -90,3 +89,10 @@ def test_accepts_beta_equal_gamma_and_elastic_alpha():
     from paper_2409_10774_amd import mp
     p = bad_phase(alpha=0.3, tY=math.inf, mY=math.inf)    # alpha allowed when micro-elastic
     assert mp.mp_plan_workspace_size(base_problem(phases=[p, p])) > 0
+
+
+def test_mixed_workspace_is_about_half():
+    from paper_2409_10774_amd import mp
+    a = mp.mp_plan_workspace_size(base_problem())
+    b = mp.mp_plan_workspace_size(base_problem(precision="mixed"))
+    assert 0.45 * a < b < 0.7 * a

@@ -34,6 +34,24 @@ def bytes_per_voxel(w):
             "err_reduce": 0}
 
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by a 1 GiB copy calibration: x2.000 and x1.000), valid
+# only for the kernel sources they were taken on (SHA-1 of the two headers)
+MEASURED_TRAFFIC = {
+    "spheres128_fp64": {"kernel": "x_pass", "bytes": (941.9 + 619.7) * 1e6,
+                        "src_sha1": "7007ac635df7b0fa8fe57426dd5e000c8b2de9ee"},
+}
+
+
+def kernel_src_sha1():
+    import hashlib
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2409_10774_amd", "csrc")
+    h = hashlib.sha1()
+    for f in ("kernels.hpp", "device_math.hpp"):
+        h.update(open(os.path.join(here, f), "rb").read())
+    return h.hexdigest()
+
+
 WORKLOADS = {
     "spheres128_fp64": dict(
         precision="fp64", dtype="f64",
@@ -74,7 +92,19 @@ def main():
     ap.add_argument("--workload", default="spheres128_fp64", choices=sorted(WORKLOADS))
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="run every load step for exactly this many iterations (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
+                          "dispatches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
               "multi-GPU path.", file=sys.stderr)
@@ -126,8 +156,12 @@ def main():
         dom = max(kernels, key=lambda k: prof[k][0])
         avg = kernels[dom]["avg_ms"] * 1e-3
         achieved = BYTES_PER_VOXEL[dom] * nvox / avg / 1e9
+        mt = MEASURED_TRAFFIC.get(args.workload)
+        traffic = None
+        if mt and mt["kernel"] == dom and mt["src_sha1"] == kernel_src_sha1():
+            traffic = mt["bytes"]
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": BYTES_PER_VOXEL[dom] * nvox}
 
     line = {

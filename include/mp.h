@@ -183,6 +183,123 @@ void mp_plan_destroy(mp_plan plan);
 const char* mp_last_error(void);
 const char* mp_version(void);
 
+/* ------------------------------------------------------------------------
+ * Resident batches: many independent RVEs, of a few shape classes, solved
+ * together.  Each admitted RVE keeps its whole state in the batch's device
+ * arena and runs its own load path with Alg. 2 (own convergence, step
+ * control, extrapolation and commit) entirely on the device.  One
+ * mp_batch_run replays a captured graph of iters_per_launch loop iterations
+ * of every resident RVE (per shape class: y forward, z forward + Green
+ * operator + z inverse, y inverse, x pass; then one reduction and one
+ * control kernel for the whole batch).  An RVE solved in a batch goes
+ * through the same arithmetic, in the same order, as with mp_plan, so its
+ * results are identical to a solo solve of the same problem.
+ * ------------------------------------------------------------------------ */
+typedef struct mp_batch_s* mp_batch;
+
+typedef struct {
+  int32_t precision;         /* MP_FP64 | MP_MIXED, for every RVE of the batch */
+  int32_t n_shapes;          /* number of shape classes, 1..8 */
+  int32_t shapes[8][3];      /* n[0], n[1], n[2] of each class */
+  int32_t max_rves;          /* resident RVEs at most, 1..512 */
+  int32_t iters_per_launch;  /* loop iterations per graph launch, 1..64 */
+  int32_t autotune;          /* 1: at creation, time each class's y / z tile
+                                widths {1, wide/2, wide} at full and half
+                                occupancy and keep the fastest (cached per
+                                shape for the process); 0: the single-plan
+                                schedule */
+} mp_batch_config;
+
+enum { MP_RVE_RUNNING = 0, MP_RVE_DONE = 1 };
+
+/* Arena bytes one RVE of `prob` with n_steps load steps takes in a batch of
+ * configuration `cfg` (fields, spectra, history, phase map, constants, load
+ * path, step records).  Admission succeeds while this fits in the arena. */
+mp_status mp_batch_footprint(const mp_batch_config* cfg, const mp_problem* prob, int32_t n_steps,
+                             size_t* bytes);
+
+/* Create an empty batch on the caller's device arena (256-byte aligned,
+ * owned by the caller, must outlive the batch; about 0.6 MB of it holds the
+ * slot descriptors).  Work goes to `hip_stream`.  Tunes the schedules when
+ * cfg->autotune is set. */
+mp_status mp_batch_create(const mp_batch_config* cfg, void* dev_workspace, size_t bytes,
+                          void* hip_stream, mp_batch* out);
+
+/* Admit one RVE: validate (as mp_plan_workspace_size), place it in the arena
+ * and a free slot, upload its phase map, constants and load path (times:
+ * n_steps + 1 values from the zero state; E, Gam: [n_steps][9]).  It starts
+ * at the next mp_batch_run.  prob->precision must equal the batch's; the
+ * grid must be one of its shape classes.  MP_E_NOMEM when the arena or the
+ * slots are full (nothing changes).  *id identifies it until released. */
+mp_status mp_batch_admit(mp_batch batch, const mp_problem* prob, int32_t n_steps, const double* times,
+                         const double* E, const double* Gam, int32_t* id);
+
+/* One graph launch: iters_per_launch loop iterations (step transitions
+ * included) of every resident, unfinished RVE.  *n_active receives the
+ * number still unfinished.  Blocks. */
+mp_status mp_batch_run(mp_batch batch, int32_t* n_active);
+
+/* mp_batch_run until no RVE is unfinished (or max_launches > 0 launches). */
+mp_status mp_batch_drain(mp_batch batch, int32_t max_launches, int32_t* launches);
+
+/* State (MP_RVE_RUNNING | MP_RVE_DONE), status (MP_OK, MP_E_NOT_CONVERGED or
+ * MP_E_DIVERGED, as mp_solve_load_path would return it), committed steps and
+ * loop iterations so far of RVE `id`. */
+mp_status mp_batch_query(mp_batch batch, int32_t id, int32_t* state, int32_t* status,
+                         int32_t* steps_done, int64_t* iters_total);
+
+/* Record of committed step `step` (1-based) of RVE `id`: out[0..41] as
+ * mp_homogenized_response, out[42..46] as mp_step_error_parts. */
+mp_status mp_batch_response(mp_batch batch, int32_t id, int32_t step, double out[48]);
+
+/* One field of RVE `id` (after its last committed step), as mp_get_fields. */
+mp_status mp_batch_get_field(mp_batch batch, int32_t id, int32_t field, double* host_dst);
+
+/* Remove RVE `id` (cancelling it if unfinished) and return its arena region. */
+mp_status mp_batch_release(mp_batch batch, int32_t id);
+
+/* Schedule of shape class `cls`: out = {y-forward TX, grid, z TX, grid,
+ * y-inverse TX, grid, x-pass grid, x tiles per RVE}; ms (optional, 3 values)
+ * the autotuner's per-RVE time of each y / z pass (0 when not tuned). */
+mp_status mp_batch_schedule(mp_batch batch, int32_t cls, int32_t out[8], float ms[3]);
+
+/* Graph launches so far, arena bytes in use, resident RVEs. */
+mp_status mp_batch_stats(mp_batch batch, int64_t* graph_launches, size_t* arena_used,
+                         int32_t* resident);
+
+void mp_batch_destroy(mp_batch batch);
+
+/* ------------------------------------------------------------------------
+ * Serving: requests (an RVE and its load path) arrive over time; the reply
+ * is the solved path.  Times are seconds from the start of the call, taken
+ * from a steady clock while the requests are served in real time.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double arrival;            /* seconds after the start, non-decreasing */
+  const mp_problem* prob;
+  int32_t n_steps;
+  const double* times;       /* n_steps + 1 */
+  const double* E;           /* [n_steps][9] */
+  const double* Gam;         /* [n_steps][9] */
+} mp_request;
+
+/* Continuous batching on an empty batch: arrived requests are admitted in
+ * arrival order while their footprint fits in the free arena (a later
+ * request may pass a head that does not fit, until the head has been passed
+ * max_bypass times); resident RVEs keep their state across launches;
+ * finished ones are retired after every graph launch, which frees their
+ * region for the queue.  Requests are solved in the batch's precision.
+ * Per request: t_admit, t_done (seconds), status, loop iterations. */
+mp_status mp_serve_batched(mp_batch batch, int32_t n, const mp_request* req, int32_t max_bypass,
+                           double* t_admit, double* t_done, int32_t* status, int64_t* iters);
+
+/* The same requests served one at a time in arrival order with FP64 plans
+ * (mp_plan_create / mp_solve_load_path / mp_plan_destroy) on a workspace of
+ * `bytes`.  Per request: t_start, t_done (seconds), status, iterations. */
+mp_status mp_serve_sequential(int32_t n, const mp_request* req, void* dev_workspace, size_t bytes,
+                              void* hip_stream, double* t_start, double* t_done, int32_t* status,
+                              int64_t* iters);
+
 #ifdef __cplusplus
 }
 #endif

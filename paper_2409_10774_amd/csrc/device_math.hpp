@@ -307,12 +307,11 @@ __device__ __forceinline__ void return_map(const PhaseC& c, const T* e, const T*
   micro_return<T>(c.m, g, bm, qn, m, q);
 }
 
-// t_eq and m_eq of a final state (Eqs. 14, 17), FP64.
+// t_eq of a final state (Eq. 14), FP64
 template <class T>
-__device__ __forceinline__ void equivalent_stresses(const PhaseC& c, const T* t, const T* m,
-                                                    double& teq, double& meq) {
+__device__ __forceinline__ double macro_equivalent(const MacroC& c, const T* t) {
   const double vol = (double(t[0]) + double(t[4]) + double(t[8])) / 3.0;
-  double n_sym = 0, n_skw = 0, m_sym = 0, m_skw = 0;
+  double n_sym = 0, n_skw = 0;
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -321,13 +320,24 @@ __device__ __forceinline__ void equivalent_stresses(const PhaseC& c, const T* t,
       const double slk = double(t[3 * l + k]) - (k == l ? vol : 0.0);
       n_sym += 0.25 * (skl + slk) * (skl + slk);
       n_skw += 0.25 * (skl - slk) * (skl - slk);
+    }
+  return sqrt(c.a1 * n_sym + c.a2 * n_skw);
+}
+
+// m_eq of a final state (Eq. 17), FP64
+template <class T>
+__device__ __forceinline__ double micro_equivalent(const MicroC& c, const T* m) {
+  double m_sym = 0, m_skw = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
       const double a = 0.5 * (double(m[3 * k + l]) + double(m[3 * l + k]));
       const double b = 0.5 * (double(m[3 * k + l]) - double(m[3 * l + k]));
       m_sym += a * a;
       m_skw += b * b;
     }
-  teq = sqrt(c.t.a1 * n_sym + c.t.a2 * n_skw);
-  meq = sqrt(c.m.b1 * m_sym + c.m.b2 * m_skw);
+  return sqrt(c.b1 * m_sym + c.b2 * m_skw);
 }
 
 // ---------------------------------------------------------------------------

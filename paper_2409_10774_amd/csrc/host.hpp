@@ -1,0 +1,261 @@
+// Host-side helpers shared by the single-RVE plan and the resident batch:
+// problem validation, workspace layout, per-phase constants, twiddles,
+// reference medium and the compile-time size dispatch of the kernels.
+#pragma once
+
+#include "../../include/mp.h"
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace mp {
+
+inline thread_local std::string g_err;
+
+
+inline mp_status fail(mp_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(MP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// compile-time sizes: every axis length must be one of these
+// ---------------------------------------------------------------------------
+#define MP_SIZES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+
+inline bool supported(int n) {
+  switch (n) {
+#define MP_CASE(N) case N:
+    MP_SIZES(MP_CASE)
+#undef MP_CASE
+    return true;
+    default: return false;
+  }
+}
+
+// widest y / z tile: TX * L <= 256 frequencies (a power of two)
+constexpr int tx_wide(int L) {
+  int t = 1;
+  while (2 * t * L <= 256) t *= 2;
+  return t;
+}
+
+inline int x_rows(int n0) { return n0 >= 128 ? 1 : 128 / n0; }
+
+template <class T, int MODE>
+void launch_x(int n0, int blocks, hipStream_t s, const XArgs<T>& a, const Ctl* ctl) {
+  switch (n0) {
+#define MP_CASE(N)                                                                                \
+  case N:                                                                                         \
+    hipLaunchKernelGGL((k_xpass<T, MODE, N>), dim3(blocks), dim3(XShape<N>::NTHR), 0, s, a, ctl); \
+    break;
+    MP_SIZES(MP_CASE)
+#undef MP_CASE
+  }
+}
+
+template <class T, int MODE, int L, int TX>
+void launch_axis_tx(dim3 grid, hipStream_t s, const AxisArgs<T>& a, const Ctl* ctl) {
+  const size_t shm = size_t(AShape<L, TX>::PTS) * sizeof(cx<T>);
+  hipLaunchKernelGGL((k_axis<T, MODE, L, TX>), grid, dim3(AShape<L, TX>::NTHR), shm, s, a, ctl);
+}
+
+template <class T, int MODE>
+void launch_axis(int L, int tx, dim3 grid, hipStream_t s, const AxisArgs<T>& a, const Ctl* ctl) {
+  switch (L) {
+#define MP_CASE(N)                                             \
+  case N:                                                      \
+    if (tx == 1)                                               \
+      launch_axis_tx<T, MODE, N, 1>(grid, s, a, ctl);          \
+    else                                                       \
+      launch_axis_tx<T, MODE, N, tx_wide(N)>(grid, s, a, ctl); \
+    break;
+    MP_SIZES(MP_CASE)
+#undef MP_CASE
+  }
+}
+
+// let every axis kernel use more than 64 KB of LDS (up to 160 KB on gfx950)
+template <class T, int MODE, int L, int TX>
+hipError_t allow_lds_tx() {
+  const size_t shm = size_t(AShape<L, TX>::PTS) * sizeof(cx<T>);
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_axis<T, MODE, L, TX>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+}
+
+template <class T, int MODE>
+hipError_t allow_lds(int L) {
+  hipError_t e = hipSuccess;
+  switch (L) {
+#define MP_CASE(N)                                                   \
+  case N:                                                            \
+    if ((e = allow_lds_tx<T, MODE, N, 1>()) != hipSuccess) return e; \
+    e = allow_lds_tx<T, MODE, N, tx_wide(N)>();                      \
+    break;
+    MP_SIZES(MP_CASE)
+#undef MP_CASE
+  }
+  return e;
+}
+
+// the low-precision form may stop at its rounding floor: no new best error
+// for this many iterations (flagged in the step record)
+constexpr int kFloorWindow = 100;
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t S, E, Eprev, base, pq, out_tm, out_pq, phase, params, tw, partials, ctl, tot, total;
+};
+
+struct Geometry {
+  int n0, n1, n2, nh;
+  long nvox, nspec, nrows;
+  int xblocks, txy, txz;
+};
+
+inline mp_status validate(const mp_problem* p, Geometry* g) {
+  if (!p) return fail(MP_E_INVALID, "problem is NULL");
+  for (int i = 0; i < 3; ++i)
+    if (!supported(p->n[i]))
+      return fail(MP_E_INVALID, "grid size n[" + std::to_string(i) + "] = " + std::to_string(p->n[i]) +
+                                    " unsupported (4 6 8 12 16 24 32 48 64 96 128 192 256)");
+  if (!(p->h > 0.0) || !std::isfinite(p->h)) return fail(MP_E_INVALID, "h must be > 0");
+  if (p->n_phases < 1 || p->n_phases > 256) return fail(MP_E_INVALID, "n_phases out of 1..256");
+  if (!p->phase || !p->phases) return fail(MP_E_INVALID, "phase map / table is NULL");
+  if (!(p->tol > 0.0)) return fail(MP_E_INVALID, "tol must be > 0");
+  if (p->max_iter < 1) return fail(MP_E_INVALID, "max_iter must be >= 1");
+  if (p->err_norm != MP_ERR_LOCAL && p->err_norm != MP_ERR_AVERAGE)
+    return fail(MP_E_INVALID, "err_norm");
+  if (p->precision != MP_FP64 && p->precision != MP_MIXED) return fail(MP_E_INVALID, "precision");
+  if (p->ref_mode < 0 || p->ref_mode > 2) return fail(MP_E_INVALID, "ref_mode");
+  for (int i = 0; i < p->n_phases; ++i) {
+    const mp_phase& c = p->phases[i];
+    const std::string tag = "phase " + std::to_string(i) + ": ";
+    const double v[12] = {c.lambda, c.mu, c.kappa, c.alpha, c.beta, c.gamma,
+                          c.tY, c.tH, c.mY, c.mH, c.a1, c.b1};
+    for (int k = 0; k < 12; ++k)
+      if (std::isnan(v[k])) return fail(MP_E_INVALID, tag + "NaN constant");
+    // Eq. 7 energetic bounds (gamma - beta = 0 accepted)
+    if (!(3 * c.lambda + 2 * c.mu > 0) || !(c.mu > 0) || !(c.kappa > 0) ||
+        !(3 * c.alpha + c.beta + c.gamma > 0) || !(c.gamma + c.beta > 0) || !(c.gamma - c.beta >= 0))
+      return fail(MP_E_INVALID, tag + "energetic bounds violated");
+    if (!(c.tY > 0) || !(c.mY > 0)) return fail(MP_E_INVALID, tag + "yield stresses must be > 0");
+    if (!(c.tH >= 0) || !(c.mH >= 0) || !std::isfinite(c.tH) || !std::isfinite(c.mH))
+      return fail(MP_E_INVALID, tag + "hardening moduli must be finite and >= 0");
+    if (!(c.a1 > 0) || !(c.b1 > 0) || !std::isfinite(c.a1) || !std::isfinite(c.b1))
+      return fail(MP_E_INVALID, tag + "a1, b1 must be finite and > 0");
+    if (std::isfinite(c.mY) && c.alpha != 0.0)
+      return fail(MP_E_INVALID, tag + "micro-plastic phases need alpha = 0");
+    for (int k = 0; k < 6; ++k)
+      if (!std::isfinite(v[k])) return fail(MP_E_INVALID, tag + "moduli must be finite");
+  }
+  const long nvox = long(p->n[0]) * p->n[1] * p->n[2];
+  for (long i = 0; i < nvox; ++i)
+    if (p->phase[i] >= p->n_phases) return fail(MP_E_INVALID, "phase id out of range");
+
+  Geometry G{};
+  G.n0 = p->n[0]; G.n1 = p->n[1]; G.n2 = p->n[2]; G.nh = G.n0 / 2;
+  G.nvox = nvox;
+  G.nspec = long(G.n2) * G.n1 * G.nh;
+  G.nrows = long(G.n1) * G.n2;
+  const int rows = x_rows(G.n0);
+  G.xblocks = int((G.nrows + rows - 1) / rows);
+  G.txy = (G.nh % tx_wide(G.n1) == 0) ? tx_wide(G.n1) : 1;
+  G.txz = (G.nh % tx_wide(G.n2) == 0) ? tx_wide(G.n2) : 1;
+  *g = G;
+  return MP_OK;
+}
+
+inline Layout layout(const Geometry& g, size_t w /* bytes per bulk word */) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+  L.S = take(18 * g.nspec * 2 * w);
+  L.E = take(18 * g.nvox * w);
+  L.Eprev = take(18 * g.nvox * w);
+  L.base = take(18 * g.nvox * w);
+  L.pq = take(2 * g.nvox * sizeof(double));
+  L.out_tm = take(18 * g.nvox * w);
+  L.out_pq = take(2 * g.nvox * sizeof(double));
+  L.phase = take(g.nvox);
+  L.params = take(256 * sizeof(PhaseC));
+  L.tw = take(size_t(g.n0 + g.n1 + g.n2) * 2 * w);
+  L.partials = take(size_t(g.xblocks) * kNAvg * sizeof(double));
+  L.ctl = take(sizeof(Ctl));
+  L.tot = take(64 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+inline PhaseC derive(const mp_phase& c) {
+  PhaseC d{};
+  d.t.lam = c.lambda; d.t.mu = c.mu; d.t.kap = c.kappa;
+  d.t.tY = c.tY; d.t.tH = c.tH; d.t.a1 = c.a1;
+  d.t.a2 = c.a1 * c.mu / c.kappa;
+  d.m.alp = c.alpha; d.m.bet = c.beta; d.m.gam = c.gamma;
+  d.m.mY = c.mY; d.m.mH = c.mH; d.m.b1 = c.b1;
+  if (c.gamma != c.beta) {
+    d.m.b2 = c.b1 * (c.gamma + c.beta) / (c.gamma - c.beta);
+    d.m.b2gmb = d.m.b2 * (c.gamma - c.beta);
+  } else {
+    d.m.b2 = 0.0;
+    d.m.b2gmb = c.b1 * (c.gamma + c.beta);
+  }
+  return d;
+}
+
+template <class T>
+void twiddles(int n, std::vector<cx<T>>* out) {
+  for (int m = 0; m < n; ++m) {
+    // exp(-2 pi i m / n), evaluated in long double
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * m / n;
+    out->push_back(cx<T>{T(cosl(a)), T(sinl(a))});
+  }
+}
+
+
+// Reference medium (Alg. 2: A0 = <A>, B0 = <B>): the unweighted mean of each
+// modulus over the phases present (default), the volume average, or given.
+inline mp_status reference_medium(const mp_problem* prob, long nvox, RefC* out) {
+  double refv[6] = {0, 0, 0, 0, 0, 0};
+  if (prob->ref_mode == MP_REF_EXPLICIT) {
+    const mp_phase& r = prob->ref;
+    const double v[6] = {r.lambda, r.mu, r.kappa, r.alpha, r.beta, r.gamma};
+    std::memcpy(refv, v, sizeof v);
+  } else {
+    std::vector<long> count(prob->n_phases, 0);
+    for (long i = 0; i < nvox; ++i) count[prob->phase[i]]++;
+    double wsum = 0;
+    for (int i = 0; i < prob->n_phases; ++i) {
+      if (!count[i]) continue;
+      const double wgt = prob->ref_mode == MP_REF_VOLUME_MEAN ? double(count[i]) : 1.0;
+      const mp_phase& c = prob->phases[i];
+      const double v[6] = {c.lambda, c.mu, c.kappa, c.alpha, c.beta, c.gamma};
+      for (int k = 0; k < 6; ++k) refv[k] += wgt * v[k];
+      wsum += wgt;
+    }
+    for (int k = 0; k < 6; ++k) refv[k] /= wsum;
+  }
+  const RefC r{refv[0], refv[1], refv[2], refv[3], refv[4], refv[5]};
+  if (!(r.lam + 2 * r.mu > 0) || !(r.mu > 0) || !(r.kap > 0) || !(r.gam > 0) ||
+      !(r.alp + r.bet + r.gam > 0))
+    return fail(MP_E_INVALID, "reference medium is not positive definite");
+  *out = r;
+  return MP_OK;
+}
+
+}  // namespace mp

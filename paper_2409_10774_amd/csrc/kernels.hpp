@@ -8,15 +8,22 @@
 //          one contiguous run of n0/2 * 18 values; a y or z tile of TX
 //          consecutive kx is a contiguous run of TX * 18 values per point.
 //   E      current strain e (c = 0..8) and curvature gamma (c = 9..17), SoA, T
-//   Eprev  the same fields one committed step earlier (extrapolation)
+//   Eprev  the same fields one converged step earlier (extrapolation)
 //   base   history base t_n - A e_n (0..8), m_n - B gamma_n (9..17), T
 //   pq     p_n, q_n of the last committed step, FP64
 //
-// One loop iteration: k_axis<Y_FWD> -> k_axis<Z_GREEN> (z forward, Green
-// operator, z inverse) -> k_axis<Y_INV> -> k_xpass<ITER> (x inverse, + E /
-// Gamma, Alg. 1, error partials, polarization, x forward) -> k_err_rows ->
-// k_err_final.  Every loop kernel returns at once when the step's control
-// block says the loop is finished, so iterations can be queued ahead.
+// One loop iteration: Y_FWD -> Z_GREEN (z forward, Green operator, z
+// inverse) -> Y_INV -> x pass ITER (x inverse, + E / Gamma, Alg. 1, error
+// partials, polarization, x forward) -> error rows -> error measure.
+// Between two load steps a single x pass TRANS commits the converged step
+// (final return map, new history base, output fields, step averages) and
+// opens the next one (extrapolated first iterate, its return map and
+// polarization, x forward).
+//
+// Every pass is written as a per-tile device function.  The single-RVE
+// kernels map one tile to one block; the resident-batch kernels run the same
+// functions from a persistent grid over work lists, so a batched RVE takes
+// bit-for-bit the same arithmetic as when it is solved alone.
 #pragma once
 
 #include "device_math.hpp"
@@ -24,12 +31,9 @@
 namespace mp {
 
 constexpr int kLev = 15;          // per-level error partials
-constexpr int kNPart = 2 * kLev;  // per-block error partials
-constexpr int kNAvg = 40;         // per-block partials of the step averages
-
-struct ErrMacro {
-  double v[18];   // prescribed E then Gamma of the step
-};
+constexpr int kNPart = 2 * kLev;  // error partial rows of an ITER x pass
+constexpr int kNAvg = 40;         // step-average rows of a TRANS x pass
+constexpr int kRed = 20;          // per-wave LDS reduction slots
 
 struct Ctl {
   int done;       // 0 running, 1 converged / fixed count reached, 2 max_iter, 3 diverged,
@@ -47,7 +51,7 @@ struct Ctl {
   int pad;
 };
 
-enum XMode { X_ITER = 0, X_INIT = 1, X_FWD_ONLY = 2, X_INV_ONLY = 3 };
+enum XMode { X_ITER = 0, X_TRANS = 1, X_FWD_ONLY = 2, X_INV_ONLY = 3 };
 enum AMode { Y_FWD = 0, Y_INV = 1, Z_GREEN = 2, Z_FWD = 3 };
 
 template <class T>
@@ -58,16 +62,20 @@ struct XArgs {
   long nvox;
   T* E;
   T* Eprev;
-  const T* base;
-  const double* pq;
+  T* base;
+  double* pq;
+  T* out_tm;        // committed t (0..8), m (9..17)
+  double* out_pq;   // committed p, q
   const uint8_t* phase;
   const PhaseC* params;
-  double* partials;
-  const Ctl* ctl;
+  double* partials; // [row][tile]
   RefC ref;
-  double mac[18];   // E then Gamma of the step
+  double mac[18];   // E then Gamma of the step being opened / iterated
   double r;         // extrapolation ratio (t_n - t_{n-1}) / (t_{n-1} - t_{n-2})
-  int first;        // first step of the plan: start from the uniform mac
+  int first;        // TRANS: first step, start from the uniform mac
+  int commit;       // TRANS: commit the converged state held in E
+  int init;         // TRANS: open the next step
+  int pad;
   const T* fin;     // X_FWD_ONLY input (18 n)
   T* fout;          // X_INV_ONLY output (18 n)
 };
@@ -86,8 +94,8 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// x-pass launch shape for a row length N0: ROWS rows per block (the last
-// block may be ragged), two lanes per voxel (one per Alg. 1 level), each
+// x-pass launch shape for a row length N0: ROWS rows per tile (the last
+// tile may be ragged), two lanes per voxel (one per Alg. 1 level), each
 // level padded to whole wavefronts.
 template <int N0>
 struct XShape {
@@ -96,6 +104,7 @@ struct XShape {
   static constexpr int VPAD = (VPB + 63) / 64 * 64;
   static constexpr int NTHR = 2 * VPAD;
   static constexpr int NH = N0 / 2;
+  static constexpr int NPK = 10 * ROWS;   // complex pencils held in LDS
 };
 
 // Real fields packed two per complex pencil for the x transforms, only like
@@ -113,23 +122,30 @@ __device__ __forceinline__ int part_of(int c) {
 __device__ __forceinline__ int pencil_re(int q) { return q < 5 ? 2 * q : 2 * q - 1; }
 __device__ __forceinline__ int pencil_im(int q) { return (q == 4 || q == 9) ? -1 : pencil_re(q) + 1; }
 
-// x pass: rows of N0 voxels, all 18 components, held in LDS as 10 complex
-// pencils per row (two real transforms in one complex transform).  Lanes [0, VPAD) run the macro level of Alg. 1
-// (e -> t, tau), lanes [VPAD, 2 VPAD) the micro level (gamma -> m, mu): the
-// levels are independent, which halves each lane's live state, and the level
-// is uniform over each wavefront.  Each lane prefetches its old strain,
-// history base and p_n / q_n before the transforms so the loads overlap them.
+// Row of the step-average record written by level L, slot j < 20 of a TRANS
+// pass: <t> or <m> (0..17), <e> or <gamma> (18..35), <p> or <q> (36, 37),
+// <t_eq> or <m_eq> (38, 39).
+__device__ __forceinline__ int avg_row(int L, int j) {
+  return j < 9 ? L * 9 + j : j < 18 ? 18 + L * 9 + (j - 9) : j == 18 ? 36 + L : 38 + L;
+}
+
+// x pass over one tile of ROWS rows of N0 voxels, all 18 components, held in
+// LDS as 10 complex pencils per row (two real transforms in one complex
+// transform).  Lanes [0, VPAD) run the macro level of Alg. 1 (e -> t, tau),
+// lanes [VPAD, 2 VPAD) the micro level (gamma -> m, mu): the levels are
+// independent, which halves each lane's live state, and the level is uniform
+// over each wavefront.  Each lane prefetches its old strain, history base and
+// p_n / q_n before the transforms so the loads overlap them.
+//   lds: NPK * N0 complex;  red: NTHR / 64 rows of kRed doubles.
 template <class T, int MODE, int N0>
-__global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
+__device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int ntiles, cx<T>* lds,
+                                           double (*red)[kRed]) {
   using X = XShape<N0>;
   constexpr int ROWS = X::ROWS, VPB = X::VPB, VPAD = X::VPAD, NTHR = X::NTHR, NH = X::NH;
-  constexpr int NPK = kPencils * ROWS;
-  if (a.ctl && a.ctl->done) return;
-  __shared__ cx<T> lds[NPK * N0];
-  __shared__ double red[NTHR / 64][kLev];
+  constexpr int NPK = X::NPK;
   T* ldr = reinterpret_cast<T*>(lds);
   const int tid = threadIdx.x;
-  const long row0 = (long)blockIdx.x * ROWS;
+  const long row0 = tile * ROWS;
   const int lvl = __builtin_amdgcn_readfirstlane(tid >= VPAD ? 1 : 0);
   const int v = tid - lvl * VPAD;
   const int vr = v < VPB ? v / N0 : 0, vx = v < VPB ? v % N0 : 0;
@@ -138,16 +154,16 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
   const int gi = own ? int((row0 + vr) * N0 + vx) : 0;
   const long nv = a.nvox;
   T* const Elv = a.E + (long)lvl * 9 * nv;
-  const T* const Blv = a.base + (long)lvl * 9 * nv;
   const int rows_here = int(a.nrows - row0 < ROWS ? a.nrows - row0 : ROWS);
 
-  // prefetch this lane's history (ITER, INIT)
+  // prefetch this lane's history (ITER, TRANS)
   T eo[9], bb[9];
   double hn = 0.0;
   int ph = 0;
 #pragma unroll
   for (int c = 0; c < 9; ++c) eo[c] = bb[c] = T(0);
-  if ((MODE == X_ITER || MODE == X_INIT) && own) {
+  if ((MODE == X_ITER || MODE == X_TRANS) && own) {
+    const T* const Blv = a.base + (long)lvl * 9 * nv;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       eo[c] = Elv[c * nv + gi];
@@ -187,16 +203,71 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
     return;
   }
 
-  // per-level partials of the error measure: |da|, |db| (max), |da|, |db| (sum),
-  // |a|^2, |b|^2, b (sum), with (a, b) = (e, t) on the macro level and
-  // (gamma, m) on the micro level.  Reduced over the wavefront as soon as
-  // they exist (fixed butterfly order), then over the waves in order.
+  // Per-wave partial sums (or maxima) reduced as soon as they exist (fixed
+  // butterfly order), then over the waves of a level in order.
   const int lane = tid & 63, wv = tid >> 6;
-  auto wave_put = [&](int j, double x) {
+  auto wave_put = [&](int j, double x, bool mx) {
     const double y = own ? x : 0.0;
-    const double z = (j < 2) ? wave_max(y) : wave_sum(y);
+    const double z = mx ? wave_max(y) : wave_sum(y);
     if (lane == 0) red[wv][j] = z;
   };
+
+  // this lane's half of the phase record
+  MacroC ct;
+  MicroC cm;
+  if (MODE != X_FWD_ONLY) {
+    if (lvl == 0)
+      ct = a.params[ph].t;
+    else
+      cm = a.params[ph].m;
+  }
+
+  if (MODE == X_TRANS && a.commit) {
+    // commit (end of the step loop): final return map at the converged
+    // iterate, new history base, output fields, step-average partials
+    T tc[9];
+    double pc = 0.0, eq = 0.0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) tc[c] = T(0);
+    if (own) {
+      T r0[9];
+      if (lvl == 0) {
+        macro_return<T>(ct, eo, bb, hn, tc, pc);
+        apply_A<T>(T(ct.lam), T(ct.mu), T(ct.kap), eo, r0);
+        eq = macro_equivalent<T>(ct, tc);
+      } else {
+        micro_return<T>(cm, eo, bb, hn, tc, pc);
+        apply_B<T>(T(cm.alp), T(cm.bet), T(cm.gam), eo, r0);
+        eq = micro_equivalent<T>(cm, tc);
+      }
+      T* const Blv = a.base + (long)lvl * 9 * nv;
+      T* const Olv = a.out_tm + (long)lvl * 9 * nv;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        bb[c] = tc[c] - r0[c];
+        Blv[c * nv + gi] = bb[c];
+        Olv[c * nv + gi] = tc[c];
+      }
+      hn = pc;
+      a.pq[lvl * nv + gi] = pc;
+      a.out_pq[lvl * nv + gi] = pc;
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) wave_put(c, double(tc[c]), false);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) wave_put(9 + c, double(eo[c]), false);
+    wave_put(18, pc, false);
+    wave_put(19, eq, false);
+    __syncthreads();
+    if (tid < kNAvg) {
+      const int L = tid / 20, j = tid % 20;
+      const int w0 = L * (VPAD / 64), w1 = w0 + VPAD / 64;
+      double y = red[w0][j];
+      for (int w = w0 + 1; w < w1; ++w) y += red[w][j];
+      a.partials[(long)avg_row(L, j) * ntiles + tile] = y;
+    }
+    if (!a.init) return;   // uniform over the block
+  }
 
   {
     T e[9];
@@ -209,7 +280,7 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
       } else if (MODE == X_ITER) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) e[c] = ldr[slot(lvl * 9 + c)] + T(a.mac[lvl * 9 + c]);
-      } else {  // X_INIT: first iterate of the step (Alg. 2)
+      } else {  // X_TRANS: first iterate of the step (Alg. 2)
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
           const long at = (lvl * 9 + c) * nv + gi;
@@ -227,13 +298,6 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) ldr[slot(lvl * 9 + c)] = e[c];
     } else {
-      // this lane's half of the phase record
-      MacroC ct;
-      MicroC cm;
-      if (lvl == 0)
-        ct = a.params[ph].t;
-      else
-        cm = a.params[ph].m;
       T t[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) t[c] = T(0);
@@ -256,6 +320,9 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
         }
       }
       if (MODE == X_ITER) {
+        // error partials |da|, |db| (max), |da|, |db| (sum), |a|^2, |b|^2,
+        // b (sum) with (a, b) = (e, t) on the macro level and (gamma, m) on
+        // the micro level
         double da = 0, sa = 0, sb = 0;
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
@@ -265,12 +332,12 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
           sb += double(t[c]) * double(t[c]);
         }
 #pragma unroll
-        for (int c = 0; c < 9; ++c) wave_put(6 + c, double(t[c]));
-        wave_put(4, sa);
-        wave_put(5, sb);
+        for (int c = 0; c < 9; ++c) wave_put(6 + c, double(t[c]), false);
+        wave_put(4, sa, false);
+        wave_put(5, sb, false);
         da = sqrt(da);
-        wave_put(0, da);
-        wave_put(2, da);
+        wave_put(0, da, true);
+        wave_put(2, da, false);
         // the old iterate's stresses, recomputed from the old strain (Alg. 1)
         double db = 0;
         if (own) {
@@ -287,8 +354,8 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
           }
         }
         db = sqrt(db);
-        wave_put(1, db);
-        wave_put(3, db);
+        wave_put(1, db, true);
+        wave_put(3, db, false);
         __syncthreads();
         if (tid < kNPart) {
           const int L = tid / kLev, j = tid % kLev;
@@ -296,7 +363,7 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
           const int w0 = L * (VPAD / 64), w1 = w0 + VPAD / 64;
           double y = red[w0][j];
           for (int w = w0 + 1; w < w1; ++w) y = (j < 2) ? nmax(y, red[w][j]) : y + red[w][j];
-          a.partials[(long)tid * gridDim.x + blockIdx.x] = y;
+          a.partials[(long)tid * ntiles + tile] = y;
         }
       }
     }
@@ -317,8 +384,19 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
   }
 }
 
+// one tile per block; every kernel of the step loop returns at once when the
+// step's control block says the loop is finished
+template <class T, int MODE, int N0>
+__global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a, const Ctl* ctl) {
+  using X = XShape<N0>;
+  if (ctl && ctl->done) return;
+  __shared__ cx<T> lds[X::NPK * N0];
+  __shared__ double red[X::NTHR / 64][kRed];
+  xpass_tile<T, MODE, N0>(a, blockIdx.x, gridDim.x, lds, red);
+}
+
 // ---------------------------------------------------------------------------
-// y and z passes over the interleaved half spectra.  A block owns TX
+// y and z passes over the interleaved half spectra.  A tile is TX
 // consecutive kx at one kz (y pass) or one ky (z pass): L points x TX*18
 // pencils, each point a contiguous run of TX*18 complex values.  Z_GREEN
 // runs the forward z transform, the Green operator at every frequency of the
@@ -328,10 +406,9 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a) {
 template <class T>
 struct AxisArgs {
   cx<T>* S;
-  long ostride;    // stride (complex) of blockIdx.y: kz for y, ky for z
+  long ostride;    // stride (complex) of the tile row index: kz for y, ky for z
   long pstride;    // stride (complex) between points of the transformed axis
   const cx<T>* tw;
-  const Ctl* ctl;
   // Z_GREEN only
   int n0, n1, n2;
   double h, scale;
@@ -343,17 +420,15 @@ struct AShape {
   static constexpr int NB = TX * 18;
   static constexpr int PTS = L * NB;
   static constexpr int NTHR = PTS > 2304 ? 512 : 256;
+  static constexpr size_t LDS = size_t(PTS);   // complex values
 };
 
+// tile (bx, by): kx in [bx TX, bx TX + TX), kz = by (y pass) or ky = by (z pass)
 template <class T, int MODE, int L, int TX>
-__global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_axis(AxisArgs<T> a) {
+__device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, cx<T>* lds, int tid) {
   using A = AShape<L, TX>;
   constexpr int NB = A::NB, PTS = A::PTS, NTHR = A::NTHR;
-  if (a.ctl && a.ctl->done) return;
-  extern __shared__ unsigned char smem_raw[];
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x;
-  cx<T>* g = a.S + (long)blockIdx.y * a.ostride + (long)blockIdx.x * NB;
+  cx<T>* g = a.S + (long)by * a.ostride + (long)bx * NB;
   for (int w = tid; w < PTS; w += NTHR) {
     const int i = w / NB, b = w % NB;
     lds[w] = g[i * a.pstride + b];
@@ -365,7 +440,7 @@ __global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_axis(AxisArgs<T> a) {
     // Green operator at the L * TX frequencies of the tile
     for (int f = tid; f < L * TX; f += NTHR) {
       const int kz = f / TX, xl = f % TX;
-      const int kx = blockIdx.x * TX + xl, ky = blockIdx.y;
+      const int kx = bx * TX + xl, ky = by;
       cx<T>* p = lds + kz * NB + xl * 18;
       const bool zero = (kx == 0 && ky == 0 && kz == 0) || (2 * ky == a.n1) || (2 * kz == a.n2);
       if (zero) {
@@ -401,14 +476,22 @@ __global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_axis(AxisArgs<T> a) {
   }
 }
 
-// error measure, stage 1: block j reduces partial row j over the x-pass blocks
-__global__ void __launch_bounds__(256) k_err_rows(const double* partials, int nblk, double* tot,
-                                                  const Ctl* ctl) {
-  if (ctl->done) return;
-  __shared__ double red[4];
-  const int j = blockIdx.x, tid = threadIdx.x;
-  const bool mx = (j % kLev) < 2;
-  const double* row = partials + (long)j * nblk;
+template <class T, int MODE, int L, int TX>
+__global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_axis(AxisArgs<T> a, const Ctl* ctl) {
+  if (ctl && ctl->done) return;
+  extern __shared__ unsigned char smem_raw[];
+  axis_tile<T, MODE, L, TX>(a, blockIdx.x, blockIdx.y, reinterpret_cast<cx<T>*>(smem_raw),
+                            threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// reductions and step control
+// ---------------------------------------------------------------------------
+// Deterministic reduction of one partial row over nblk tiles by a block of
+// 256 threads (fixed order: two strided accumulators per thread, wave
+// butterflies, then the four waves).  The result is valid in thread 0.
+__device__ __forceinline__ double row_reduce(const double* row, int nblk, bool mx, double* red4) {
+  const int tid = threadIdx.x;
   double v0 = 0.0, v1 = 0.0;
   int b = tid;
   for (; b + 256 < nblk; b += 512) {
@@ -419,18 +502,20 @@ __global__ void __launch_bounds__(256) k_err_rows(const double* partials, int nb
   if (b < nblk) v0 = mx ? nmax(v0, row[b]) : v0 + row[b];
   double v = mx ? nmax(v0, v1) : v0 + v1;
   v = mx ? wave_max(v) : wave_sum(v);
-  if ((tid & 63) == 0) red[tid >> 6] = v;
+  if ((tid & 63) == 0) red4[tid >> 6] = v;
   __syncthreads();
-  if (tid == 0)
-    tot[j] = mx ? nmax(nmax(red[0], red[1]), nmax(red[2], red[3]))
-                : ((red[0] + red[1]) + (red[2] + red[3]));
+  return mx ? nmax(nmax(red4[0], red4[1]), nmax(red4[2], red4[3]))
+            : ((red4[0] + red4[1]) + (red4[2] + red4[3]));
 }
 
-// error measure, stage 2 (Eqs. 36-38).  <e> = E and <gamma> = Gamma hold
-// exactly (the Green operator leaves no k = 0 fluctuation), so the averages
-// of the strain-like fields are the prescribed ones.
-__global__ void k_err_final(const double* tot, long nvox, Ctl* ctl, ErrMacro mac) {
-  if (ctl->done || threadIdx.x != 0) return;
+// rows that hold maxima in an ITER x pass's error partials
+__device__ __forceinline__ bool err_row_is_max(int j) { return (j % kLev) < 2; }
+
+// error measure (Eqs. 36-38) from the reduced rows, and the step decision.
+// <e> = E and <gamma> = Gamma hold exactly (the Green operator leaves no
+// k = 0 fluctuation), so the averages of the strain-like fields are the
+// prescribed ones.
+__device__ __forceinline__ void err_finalize(const double* tot, long nvox, Ctl* ctl, const double* mac) {
   const double inv = 1.0 / double(nvox);
   double err = 0.0;
   for (int f = 0; f < 4; ++f) {   // e, t, gamma, m
@@ -441,7 +526,7 @@ __global__ void k_err_final(const double* tot, long nvox, Ctl* ctl, ErrMacro mac
     if (num != 0.0) {
       double mn = 0.0;
       for (int c = 0; c < 9; ++c) {
-        const double mc = b == 0 ? mac.v[L * 9 + c] : P[6 + c] * inv;
+        const double mc = b == 0 ? mac[L * 9 + c] : P[6 + c] * inv;
         mn += mc * mc;
       }
       double den = sqrt(mn);
@@ -477,7 +562,12 @@ __global__ void k_err_final(const double* tot, long nvox, Ctl* ctl, ErrMacro mac
   ctl->done = done;
 }
 
-__global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm, int window) {
+struct ErrMacro {
+  double v[18];   // prescribed E then Gamma of the step
+};
+
+__device__ __forceinline__ void ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm,
+                                          int window) {
   ctl->done = 0;
   ctl->iters = 0;
   ctl->fixed = fixed;
@@ -488,95 +578,6 @@ __global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int n
   ctl->window = window;
   ctl->best = 1e300;
   ctl->best_it = 0;
-}
-
-// commit (last line of the step loop): final return map, new history base,
-// output fields and the step averages.
-template <class T>
-struct CommitArgs {
-  long nvox;
-  const T* E;
-  T* base;
-  double* pq;
-  T* out_tm;
-  double* out_pq;
-  const uint8_t* phase;
-  const PhaseC* params;
-  double* partials;
-};
-
-template <class T>
-__global__ void __launch_bounds__(256) k_commit(CommitArgs<T> a) {
-  __shared__ double red[4][kNAvg];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const long gi = (long)blockIdx.x * blockDim.x + tid;
-  double acc[kNAvg];
-#pragma unroll
-  for (int j = 0; j < kNAvg; ++j) acc[j] = 0.0;
-  if (gi < a.nvox) {
-    T e[18], bt[9], bm[9], t[9], m[9];
-#pragma unroll
-    for (int c = 0; c < 18; ++c) e[c] = a.E[c * a.nvox + gi];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      bt[c] = a.base[c * a.nvox + gi];
-      bm[c] = a.base[(9 + c) * a.nvox + gi];
-    }
-    const PhaseC pc = a.params[a.phase[gi]];
-    double p, q;
-    return_map<T>(pc, e, e + 9, bt, bm, a.pq[gi], a.pq[a.nvox + gi], t, m, p, q);
-    T ae[9], bg[9];
-    apply_A<T>(T(pc.t.lam), T(pc.t.mu), T(pc.t.kap), e, ae);
-    apply_B<T>(T(pc.m.alp), T(pc.m.bet), T(pc.m.gam), e + 9, bg);
-#pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      a.base[c * a.nvox + gi] = t[c] - ae[c];
-      a.base[(9 + c) * a.nvox + gi] = m[c] - bg[c];
-      a.out_tm[c * a.nvox + gi] = t[c];
-      a.out_tm[(9 + c) * a.nvox + gi] = m[c];
-      acc[c] = double(t[c]);
-      acc[9 + c] = double(m[c]);
-      acc[18 + c] = double(e[c]);
-      acc[27 + c] = double(e[9 + c]);
-    }
-    a.pq[gi] = p;
-    a.pq[a.nvox + gi] = q;
-    a.out_pq[gi] = p;
-    a.out_pq[a.nvox + gi] = q;
-    double teq, meq;
-    equivalent_stresses<T>(pc, t, m, teq, meq);
-    acc[36] = p;
-    acc[37] = q;
-    acc[38] = teq;
-    acc[39] = meq;
-  }
-#pragma unroll
-  for (int j = 0; j < kNAvg; ++j) {
-    const double v = wave_sum(acc[j]);
-    if (lane == 0) red[wv][j] = v;
-  }
-  __syncthreads();
-  if (tid < kNAvg) {
-    const double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    a.partials[(long)blockIdx.x * kNAvg + tid] = v;
-  }
-}
-
-__global__ void __launch_bounds__(256) k_avg_reduce(const double* partials, int nblk, long nvox,
-                                                    double* resp) {
-  __shared__ double red[4][kNAvg];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int j = 0; j < kNAvg; ++j) {
-    double v = 0.0;
-    for (int b = tid; b < nblk; b += 256) v += partials[(long)b * kNAvg + j];
-    v = wave_sum(v);
-    if (lane == 0) red[wv][j] = v;
-  }
-  __syncthreads();
-  if (tid < kNAvg) {
-    const double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    resp[tid] = v / double(nvox);
-  }
 }
 
 // pointwise Alg. 1 on independent points (same device code as the solver)

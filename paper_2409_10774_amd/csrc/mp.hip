@@ -1,9 +1,6 @@
 // Host side of the micropolar FFT solver: plan, workspace layout, Alg. 2
 // step loop and the C ABI declared in include/mp.h.
-#include "../../include/mp.h"
-#include "kernels.hpp"
-
-#include <hip/hip_runtime.h>
+#include "host.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -14,117 +11,36 @@
 
 using namespace mp;
 
+namespace mp {
+
+// kernels of the single-RVE step loop (the batch runs the same device
+// functions from its own kernels)
+// block j reduces partial row j: error rows (avg = 0, rows 0..29) or
+// step-average rows (avg = 1, rows 0..39)
+__global__ void __launch_bounds__(256) k_rows(const double* partials, int nblk, int avg, double* tot,
+                                              const Ctl* ctl) {
+  if (ctl && ctl->done) return;
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  const double v = row_reduce(partials + (long)j * nblk, nblk, !avg && err_row_is_max(j), red);
+  if (threadIdx.x == 0) tot[j] = v;
+}
+
+__global__ void k_err_final(const double* tot, long nvox, Ctl* ctl, ErrMacro mac) {
+  if (ctl->done || threadIdx.x != 0) return;
+  err_finalize(tot, nvox, ctl, mac.v);
+}
+
+__global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm, int window) {
+  ctl_reset(ctl, fixed, max_iter, tol, norm, window);
+}
+
+}  // namespace mp
+
 namespace {
 
-thread_local std::string g_err;
-
-mp_status fail(mp_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
-}
-
-#define HIP_TRY(call)                                                                  \
-  do {                                                                                 \
-    hipError_t e_ = (call);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(MP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
-  } while (0)
-
-// ---------------------------------------------------------------------------
-// compile-time sizes: every axis length must be one of these
-// ---------------------------------------------------------------------------
-#define MP_SIZES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
-
-bool supported(int n) {
-  switch (n) {
-#define MP_CASE(N) case N:
-    MP_SIZES(MP_CASE)
-#undef MP_CASE
-    return true;
-    default: return false;
-  }
-}
-
-// widest y / z tile: TX * L <= 256 frequencies (a power of two)
-constexpr int tx_wide(int L) {
-  int t = 1;
-  while (2 * t * L <= 256) t *= 2;
-  return t;
-}
-
-int x_rows(int n0) { return n0 >= 128 ? 1 : 128 / n0; }
-
-template <class T, int MODE>
-void launch_x(int n0, int blocks, hipStream_t s, const XArgs<T>& a) {
-  switch (n0) {
-#define MP_CASE(N)                                                                           \
-  case N:                                                                                    \
-    hipLaunchKernelGGL((k_xpass<T, MODE, N>), dim3(blocks), dim3(XShape<N>::NTHR), 0, s, a); \
-    break;
-    MP_SIZES(MP_CASE)
-#undef MP_CASE
-  }
-}
-
-template <class T, int MODE, int L, int TX>
-void launch_axis_tx(dim3 grid, hipStream_t s, const AxisArgs<T>& a) {
-  const size_t shm = size_t(AShape<L, TX>::PTS) * sizeof(cx<T>);
-  hipLaunchKernelGGL((k_axis<T, MODE, L, TX>), grid, dim3(AShape<L, TX>::NTHR), shm, s, a);
-}
-
-template <class T, int MODE>
-void launch_axis(int L, int tx, dim3 grid, hipStream_t s, const AxisArgs<T>& a) {
-  switch (L) {
-#define MP_CASE(N)                                        \
-  case N:                                                 \
-    if (tx == 1)                                          \
-      launch_axis_tx<T, MODE, N, 1>(grid, s, a);          \
-    else                                                  \
-      launch_axis_tx<T, MODE, N, tx_wide(N)>(grid, s, a); \
-    break;
-    MP_SIZES(MP_CASE)
-#undef MP_CASE
-  }
-}
-
-// let every axis kernel use more than 64 KB of LDS (up to 160 KB on gfx950)
-template <class T, int MODE, int L, int TX>
-hipError_t allow_lds_tx() {
-  const size_t shm = size_t(AShape<L, TX>::PTS) * sizeof(cx<T>);
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_axis<T, MODE, L, TX>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
-}
-
-template <class T, int MODE>
-hipError_t allow_lds(int L) {
-  hipError_t e = hipSuccess;
-  switch (L) {
-#define MP_CASE(N)                                                   \
-  case N:                                                            \
-    if ((e = allow_lds_tx<T, MODE, N, 1>()) != hipSuccess) return e; \
-    e = allow_lds_tx<T, MODE, N, tx_wide(N)>();                      \
-    break;
-    MP_SIZES(MP_CASE)
-#undef MP_CASE
-  }
-  return e;
-}
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-struct Layout {
-  size_t S, E, Eprev, base, pq, out_tm, out_pq, phase, params, tw, partials, ctl, tot, resp, total;
-};
-
-struct Geometry {
-  int n0, n1, n2, nh;
-  long nvox, nspec, nrows;
-  int xblocks, txy, txz;
-  int commit_blocks;
-};
-
 constexpr int kProfEv = 6;     // boundaries around the 5 loop kernels of one iteration
-constexpr int kFloorWindow = 100;
+constexpr int kRecord = 47;    // step record: 40 averages, err, iters, 4 err parts, floor flag
 
 }  // namespace
 
@@ -140,12 +56,13 @@ struct mp_plan_s {
   void* Eprev;    // T
   void* base;     // T
   void* out_tm;   // T
-  double *pq, *out_pq, *partials, *tot, *resp;
+  double *pq, *out_pq, *partials, *tot;
   uint8_t* phase;
   PhaseC* params;
   void* tw0;      // cx<T>, n0 + n1 + n2 entries
   Ctl* ctl;
   Ctl* ctl_host;
+  double* tot_host;   // pinned, kNAvg entries
   RefC ref;
   double tol;
   int max_iter, norm, fixed;
@@ -162,108 +79,6 @@ struct mp_plan_s {
 
 namespace {
 
-mp_status validate(const mp_problem* p, Geometry* g) {
-  if (!p) return fail(MP_E_INVALID, "problem is NULL");
-  for (int i = 0; i < 3; ++i)
-    if (!supported(p->n[i]))
-      return fail(MP_E_INVALID, "grid size n[" + std::to_string(i) + "] = " + std::to_string(p->n[i]) +
-                                    " unsupported (4 6 8 12 16 24 32 48 64 96 128 192 256)");
-  if (!(p->h > 0.0) || !std::isfinite(p->h)) return fail(MP_E_INVALID, "h must be > 0");
-  if (p->n_phases < 1 || p->n_phases > 256) return fail(MP_E_INVALID, "n_phases out of 1..256");
-  if (!p->phase || !p->phases) return fail(MP_E_INVALID, "phase map / table is NULL");
-  if (!(p->tol > 0.0)) return fail(MP_E_INVALID, "tol must be > 0");
-  if (p->max_iter < 1) return fail(MP_E_INVALID, "max_iter must be >= 1");
-  if (p->err_norm != MP_ERR_LOCAL && p->err_norm != MP_ERR_AVERAGE)
-    return fail(MP_E_INVALID, "err_norm");
-  if (p->precision != MP_FP64 && p->precision != MP_MIXED) return fail(MP_E_INVALID, "precision");
-  if (p->ref_mode < 0 || p->ref_mode > 2) return fail(MP_E_INVALID, "ref_mode");
-  for (int i = 0; i < p->n_phases; ++i) {
-    const mp_phase& c = p->phases[i];
-    const std::string tag = "phase " + std::to_string(i) + ": ";
-    const double v[12] = {c.lambda, c.mu, c.kappa, c.alpha, c.beta, c.gamma,
-                          c.tY, c.tH, c.mY, c.mH, c.a1, c.b1};
-    for (int k = 0; k < 12; ++k)
-      if (std::isnan(v[k])) return fail(MP_E_INVALID, tag + "NaN constant");
-    // Eq. 7 energetic bounds (gamma - beta = 0 accepted)
-    if (!(3 * c.lambda + 2 * c.mu > 0) || !(c.mu > 0) || !(c.kappa > 0) ||
-        !(3 * c.alpha + c.beta + c.gamma > 0) || !(c.gamma + c.beta > 0) || !(c.gamma - c.beta >= 0))
-      return fail(MP_E_INVALID, tag + "energetic bounds violated");
-    if (!(c.tY > 0) || !(c.mY > 0)) return fail(MP_E_INVALID, tag + "yield stresses must be > 0");
-    if (!(c.tH >= 0) || !(c.mH >= 0) || !std::isfinite(c.tH) || !std::isfinite(c.mH))
-      return fail(MP_E_INVALID, tag + "hardening moduli must be finite and >= 0");
-    if (!(c.a1 > 0) || !(c.b1 > 0) || !std::isfinite(c.a1) || !std::isfinite(c.b1))
-      return fail(MP_E_INVALID, tag + "a1, b1 must be finite and > 0");
-    if (std::isfinite(c.mY) && c.alpha != 0.0)
-      return fail(MP_E_INVALID, tag + "micro-plastic phases need alpha = 0");
-    for (int k = 0; k < 6; ++k)
-      if (!std::isfinite(v[k])) return fail(MP_E_INVALID, tag + "moduli must be finite");
-  }
-  const long nvox = long(p->n[0]) * p->n[1] * p->n[2];
-  for (long i = 0; i < nvox; ++i)
-    if (p->phase[i] >= p->n_phases) return fail(MP_E_INVALID, "phase id out of range");
-
-  Geometry G{};
-  G.n0 = p->n[0]; G.n1 = p->n[1]; G.n2 = p->n[2]; G.nh = G.n0 / 2;
-  G.nvox = nvox;
-  G.nspec = long(G.n2) * G.n1 * G.nh;
-  G.nrows = long(G.n1) * G.n2;
-  const int rows = x_rows(G.n0);
-  G.xblocks = int((G.nrows + rows - 1) / rows);
-  G.txy = (G.nh % tx_wide(G.n1) == 0) ? tx_wide(G.n1) : 1;
-  G.txz = (G.nh % tx_wide(G.n2) == 0) ? tx_wide(G.n2) : 1;
-  G.commit_blocks = int((nvox + 255) / 256);
-  *g = G;
-  return MP_OK;
-}
-
-Layout layout(const Geometry& g, size_t w /* bytes per bulk word */) {
-  Layout L{};
-  size_t o = 0;
-  auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
-  L.S = take(18 * g.nspec * 2 * w);
-  L.E = take(18 * g.nvox * w);
-  L.Eprev = take(18 * g.nvox * w);
-  L.base = take(18 * g.nvox * w);
-  L.pq = take(2 * g.nvox * sizeof(double));
-  L.out_tm = take(18 * g.nvox * w);
-  L.out_pq = take(2 * g.nvox * sizeof(double));
-  L.phase = take(g.nvox);
-  L.params = take(256 * sizeof(PhaseC));
-  L.tw = take(size_t(g.n0 + g.n1 + g.n2) * 2 * w);
-  L.partials = take(size_t(std::max(g.xblocks * kNPart, g.commit_blocks * kNAvg)) * sizeof(double));
-  L.ctl = take(sizeof(Ctl));
-  L.tot = take(32 * sizeof(double));
-  L.resp = take(64 * sizeof(double));
-  L.total = o;
-  return L;
-}
-
-PhaseC derive(const mp_phase& c) {
-  PhaseC d{};
-  d.t.lam = c.lambda; d.t.mu = c.mu; d.t.kap = c.kappa;
-  d.t.tY = c.tY; d.t.tH = c.tH; d.t.a1 = c.a1;
-  d.t.a2 = c.a1 * c.mu / c.kappa;
-  d.m.alp = c.alpha; d.m.bet = c.beta; d.m.gam = c.gamma;
-  d.m.mY = c.mY; d.m.mH = c.mH; d.m.b1 = c.b1;
-  if (c.gamma != c.beta) {
-    d.m.b2 = c.b1 * (c.gamma + c.beta) / (c.gamma - c.beta);
-    d.m.b2gmb = d.m.b2 * (c.gamma - c.beta);
-  } else {
-    d.m.b2 = 0.0;
-    d.m.b2gmb = c.b1 * (c.gamma + c.beta);
-  }
-  return d;
-}
-
-template <class T>
-void twiddles(int n, std::vector<cx<T>>* out) {
-  for (int m = 0; m < n; ++m) {
-    // exp(-2 pi i m / n), evaluated in long double
-    const long double a = -2.0L * 3.14159265358979323846264338327950288L * m / n;
-    out->push_back(cx<T>{T(cosl(a)), T(sinl(a))});
-  }
-}
-
 // ---------------------------------------------------------------------------
 // typed launch helpers
 // ---------------------------------------------------------------------------
@@ -275,24 +90,22 @@ struct Eng {
     return axis == 0 ? t : axis == 1 ? t + P->g.n0 : t + P->g.n0 + P->g.n1;
   }
 
-  static AxisArgs<T> yargs(mp_plan P, cx<T>* S, const Ctl* ctl) {
+  static AxisArgs<T> yargs(mp_plan P, cx<T>* S) {
     const Geometry& g = P->g;
     AxisArgs<T> a{};
     a.S = S;
     a.ostride = long(g.n1) * g.nh * 18;   // one kz plane
     a.pstride = long(g.nh) * 18;          // next ky
     a.tw = tw(P, 1);
-    a.ctl = ctl;
     return a;
   }
-  static AxisArgs<T> zargs(mp_plan P, cx<T>* S, const Ctl* ctl) {
+  static AxisArgs<T> zargs(mp_plan P, cx<T>* S) {
     const Geometry& g = P->g;
     AxisArgs<T> a{};
     a.S = S;
     a.ostride = long(g.nh) * 18;          // next ky
     a.pstride = long(g.n1) * g.nh * 18;   // next kz
     a.tw = tw(P, 2);
-    a.ctl = ctl;
     a.n0 = g.n0; a.n1 = g.n1; a.n2 = g.n2;
     a.h = P->h;
     a.scale = 1.0 / double(g.nvox);
@@ -307,13 +120,13 @@ struct Eng {
   static void spectral(mp_plan P, cx<T>* S, const Ctl* ctl, hipEvent_t* ev) {
     const Geometry& g = P->g;
     auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], P->stream); };
-    const AxisArgs<T> ay = yargs(P, S, ctl), az = zargs(P, S, ctl);
+    const AxisArgs<T> ay = yargs(P, S), az = zargs(P, S);
     mark(0);
-    launch_axis<T, Y_FWD>(g.n1, g.txy, ygrid(g), P->stream, ay);
+    launch_axis<T, Y_FWD>(g.n1, g.txy, ygrid(g), P->stream, ay, ctl);
     mark(1);
-    launch_axis<T, Z_GREEN>(g.n2, g.txz, zgrid(g), P->stream, az);
+    launch_axis<T, Z_GREEN>(g.n2, g.txz, zgrid(g), P->stream, az, ctl);
     mark(2);
-    launch_axis<T, Y_INV>(g.n1, g.txy, ygrid(g), P->stream, ay);
+    launch_axis<T, Y_INV>(g.n1, g.txy, ygrid(g), P->stream, ay, ctl);
     mark(3);
   }
 
@@ -326,12 +139,13 @@ struct Eng {
     a.nvox = g.nvox;
     a.E = static_cast<T*>(P->E);
     a.Eprev = static_cast<T*>(P->Eprev);
-    a.base = static_cast<const T*>(P->base);
+    a.base = static_cast<T*>(P->base);
     a.pq = P->pq;
+    a.out_tm = static_cast<T*>(P->out_tm);
+    a.out_pq = P->out_pq;
     a.phase = P->phase;
     a.params = P->params;
     a.partials = P->partials;
-    a.ctl = P->ctl;
     a.ref = P->ref;
     return a;
   }
@@ -350,32 +164,61 @@ struct Eng {
 
   static mp_status solve(mp_plan P, int32_t n_steps, const double* times, const double* E,
                          const double* Gam, int32_t* iters);
+  static mp_status record(mp_plan P, std::vector<double>& rec);
 };
+
+// Step averages of the committed state (rows of a TRANS x pass with
+// commit set): reduce, read back, append the step record.
+template <class T>
+mp_status Eng<T>::record(mp_plan P, std::vector<double>& rec) {
+  const Geometry& g = P->g;
+  hipLaunchKernelGGL(k_rows, dim3(kNAvg), dim3(256), 0, P->stream, P->partials, g.xblocks, 1, P->tot,
+                     nullptr);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(P->tot_host, P->tot, kNAvg * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  for (int j = 0; j < kNAvg; ++j) rec[j] = P->tot_host[j] / double(g.nvox);
+  P->resp_hist.push_back(rec);
+  P->steps += 1;
+  return MP_OK;
+}
 
 template <class T>
 mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const double* E,
                         const double* Gam, int32_t* iters) {
   const Geometry& g = P->g;
   if (P->steps == 0) P->t_prev = P->t_cur = times[0];
+  XArgs<T> xa = xargs(P);
+  // the converged state of the previous step is committed by the x pass that
+  // opens the next step (or by a commit-only pass after the last one)
+  std::vector<double> rec(kRecord, 0.0);
+  bool pending = false;
+  mp_status st = MP_OK;
+  std::string msg;
   for (int s = 1; s <= n_steps; ++s) {
-    XArgs<T> xa = xargs(P);
     for (int c = 0; c < 9; ++c) {
       xa.mac[c] = E[(s - 1) * 9 + c];
       xa.mac[9 + c] = Gam[(s - 1) * 9 + c];
     }
-    xa.first = P->steps == 0;
+    xa.first = P->steps == 0 && !pending;
     // Alg. 2 linear extrapolation ratio (t_n - t_{n-1}) / (t_{n-1} - t_{n-2})
-    xa.r = P->steps == 0 ? 0.0 : (times[s] - P->t_cur) / (P->t_cur - P->t_prev);
+    xa.r = xa.first ? 0.0 : (times[s] - P->t_cur) / (P->t_cur - P->t_prev);
+    xa.commit = pending;
+    xa.init = 1;
     // the low-precision form may stop at its rounding floor: no new best
     // error for kFloorWindow iterations (flagged in the step record)
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(1), 0, P->stream, P->ctl, P->fixed, P->max_iter,
                        P->tol, P->norm, sizeof(T) < sizeof(double) ? kFloorWindow : 0);
     P->ctl_host->iters = 0;
     P->ctl_host->done = 0;
-    // first iterate (extrapolated or uniform), its return map and polarization
-    xa.ctl = nullptr;
-    launch_x<T, X_INIT>(g.n0, g.xblocks, P->stream, xa);
-    xa.ctl = P->ctl;
+    // commit of the previous step, first iterate of this one (extrapolated
+    // or uniform), its return map and polarization
+    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr);
+    if (pending) {
+      mp_status r = record(P, rec);
+      if (r != MP_OK) return r;
+      pending = false;
+    }
     ErrMacro em;
     for (int c = 0; c < 18; ++c) em.v[c] = xa.mac[c];
     int batch = 2;
@@ -395,9 +238,9 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
       for (int k = 0; k < batch; ++k) {
         hipEvent_t* ev = P->prof ? &P->ev[size_t(k) * kProfEv] : nullptr;
         spectral(P, S(P), P->ctl, ev);
-        launch_x<T, X_ITER>(g.n0, g.xblocks, P->stream, xa);
+        launch_x<T, X_ITER>(g.n0, g.xblocks, P->stream, xa, P->ctl);
         if (ev) HIP_TRY(hipEventRecord(ev[4], P->stream));
-        hipLaunchKernelGGL(k_err_rows, dim3(kNPart), dim3(256), 0, P->stream, P->partials, g.xblocks,
+        hipLaunchKernelGGL(k_rows, dim3(kNPart), dim3(256), 0, P->stream, P->partials, g.xblocks, 0,
                            P->tot, P->ctl);
         hipLaunchKernelGGL(k_err_final, dim3(1), dim3(64), 0, P->stream, P->tot, g.nvox, P->ctl, em);
         if (ev) HIP_TRY(hipEventRecord(ev[5], P->stream));
@@ -421,30 +264,30 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
       batch = std::min(batch * 2, 64);
     }
     const Ctl c = *P->ctl_host;
-    // commit
-    CommitArgs<T> ca{g.nvox, static_cast<const T*>(P->E), static_cast<T*>(P->base), P->pq,
-                     static_cast<T*>(P->out_tm), P->out_pq, P->phase, P->params, P->partials};
-    hipLaunchKernelGGL((k_commit<T>), dim3(g.commit_blocks), dim3(256), 0, P->stream, ca);
-    hipLaunchKernelGGL(k_avg_reduce, dim3(1), dim3(256), 0, P->stream, P->partials, g.commit_blocks,
-                       g.nvox, P->resp);
-    std::vector<double> r(47, 0.0);
-    HIP_TRY(hipMemcpyAsync(r.data(), P->resp, kNAvg * sizeof(double), hipMemcpyDeviceToHost,
-                           P->stream));
-    HIP_TRY(hipStreamSynchronize(P->stream));
-    r[40] = c.err;
-    r[41] = c.iters;
-    for (int f = 0; f < 4; ++f) r[42 + f] = c.err_parts[f];
-    r[46] = c.done == 4 ? 1.0 : 0.0;
-    P->resp_hist.push_back(r);
-    P->steps += 1;
+    std::fill(rec.begin(), rec.end(), 0.0);
+    rec[40] = c.err;
+    rec[41] = c.iters;
+    for (int f = 0; f < 4; ++f) rec[42 + f] = c.err_parts[f];
+    rec[46] = c.done == 4 ? 1.0 : 0.0;
+    pending = true;
     P->t_prev = P->t_cur;
     P->t_cur = times[s];
     if (iters) iters[s - 1] = c.iters;
-    if (c.done == 2)
-      return fail(MP_E_NOT_CONVERGED, "step " + std::to_string(P->steps) + " hit max_iter");
-    if (c.done == 3)
-      return fail(MP_E_DIVERGED, "step " + std::to_string(P->steps) + " diverged");
+    if (c.done == 2 || c.done == 3) {
+      st = c.done == 2 ? MP_E_NOT_CONVERGED : MP_E_DIVERGED;
+      msg = "step " + std::to_string(P->steps + 1) + (c.done == 2 ? " hit max_iter" : " diverged");
+      break;
+    }
   }
+  if (pending) {
+    // commit only: the last step of this call (or the failed one)
+    xa.commit = 1;
+    xa.init = 0;
+    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr);
+    mp_status r = record(P, rec);
+    if (r != MP_OK) return r;
+  }
+  if (st != MP_OK) return fail(st, msg);
   return MP_OK;
 }
 
@@ -499,7 +342,6 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   P->partials = reinterpret_cast<double*>(wsp + L.partials);
   P->ctl = reinterpret_cast<Ctl*>(wsp + L.ctl);
   P->tot = reinterpret_cast<double*>(wsp + L.tot);
-  P->resp = reinterpret_cast<double*>(wsp + L.resp);
   P->tol = prob->tol;
   P->max_iter = prob->max_iter;
   P->norm = prob->err_norm;
@@ -511,30 +353,12 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   P->t_prev = P->t_cur = 0.0;
 
   // reference medium (Alg. 2: A0 = <A>, B0 = <B>); phase mean by default
-  double refv[6] = {0, 0, 0, 0, 0, 0};
-  if (prob->ref_mode == MP_REF_EXPLICIT) {
-    const mp_phase& r = prob->ref;
-    const double v[6] = {r.lambda, r.mu, r.kappa, r.alpha, r.beta, r.gamma};
-    std::memcpy(refv, v, sizeof v);
-  } else {
-    std::vector<long> count(prob->n_phases, 0);
-    for (long i = 0; i < g.nvox; ++i) count[prob->phase[i]]++;
-    double wsum = 0;
-    for (int i = 0; i < prob->n_phases; ++i) {
-      if (!count[i]) continue;
-      const double wgt = prob->ref_mode == MP_REF_VOLUME_MEAN ? double(count[i]) : 1.0;
-      const mp_phase& c = prob->phases[i];
-      const double v[6] = {c.lambda, c.mu, c.kappa, c.alpha, c.beta, c.gamma};
-      for (int k = 0; k < 6; ++k) refv[k] += wgt * v[k];
-      wsum += wgt;
+  {
+    const mp_status rs = reference_medium(prob, g.nvox, &P->ref);
+    if (rs != MP_OK) {
+      delete P;
+      return rs;
     }
-    for (int k = 0; k < 6; ++k) refv[k] /= wsum;
-  }
-  P->ref = RefC{refv[0], refv[1], refv[2], refv[3], refv[4], refv[5]};
-  if (!(P->ref.lam + 2 * P->ref.mu > 0) || !(P->ref.mu > 0) || !(P->ref.kap > 0) ||
-      !(P->ref.gam > 0) || !(P->ref.alp + P->ref.bet + P->ref.gam > 0)) {
-    delete P;
-    return fail(MP_E_INVALID, "reference medium is not positive definite");
   }
 
   std::vector<PhaseC> pc(256);
@@ -551,7 +375,12 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
     twiddles(g.n2, &tw);
   }
 
-  auto cleanup = [&](mp_status st) { delete P; return st; };
+  auto cleanup = [&](mp_status st) {
+    if (P->ctl_host) (void)hipHostFree(P->ctl_host);
+    if (P->tot_host) (void)hipHostFree(P->tot_host);
+    delete P;
+    return st;
+  };
   hipError_t e;
 #define CREATE_TRY(call)                                                                 \
   do {                                                                                   \
@@ -562,6 +391,7 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   } while (0)
   CREATE_TRY(mixed ? Eng<float>::prepare() : Eng<double>::prepare());
   CREATE_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->ctl_host), sizeof(Ctl)));
+  CREATE_TRY(hipHostMalloc(reinterpret_cast<void**>(&P->tot_host), kNAvg * sizeof(double)));
   CREATE_TRY(hipMemsetAsync(wsp, 0, L.total, P->stream));
   CREATE_TRY(hipMemcpyAsync(P->phase, prob->phase, g.nvox, hipMemcpyHostToDevice, P->stream));
   CREATE_TRY(hipMemcpyAsync(P->params, pc.data(), pc.size() * sizeof(PhaseC), hipMemcpyHostToDevice,
@@ -582,6 +412,7 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
 void mp_plan_destroy(mp_plan P) {
   if (!P) return;
   if (P->ctl_host) (void)hipHostFree(P->ctl_host);
+  if (P->tot_host) (void)hipHostFree(P->tot_host);
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
   delete P;
 }
@@ -682,13 +513,12 @@ mp_status mp_spectrum_forward(mp_plan P, const void* dev_in, void* dev_out) {
   using E8 = Eng<double>;
   const Geometry& g = P->g;
   XArgs<double> xa = E8::xargs(P);
-  xa.ctl = nullptr;
   xa.fin = static_cast<const double*>(dev_in);
   cx<double>* S = static_cast<cx<double>*>(dev_out);
   xa.S = S;
-  launch_x<double, X_FWD_ONLY>(g.n0, g.xblocks, P->stream, xa);
-  launch_axis<double, Y_FWD>(g.n1, g.txy, E8::ygrid(g), P->stream, E8::yargs(P, S, nullptr));
-  launch_axis<double, Z_FWD>(g.n2, g.txz, E8::zgrid(g), P->stream, E8::zargs(P, S, nullptr));
+  launch_x<double, X_FWD_ONLY>(g.n0, g.xblocks, P->stream, xa, nullptr);
+  launch_axis<double, Y_FWD>(g.n1, g.txy, E8::ygrid(g), P->stream, E8::yargs(P, S), nullptr);
+  launch_axis<double, Z_FWD>(g.n2, g.txz, E8::zgrid(g), P->stream, E8::zargs(P, S), nullptr);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(P->stream));
   return MP_OK;
@@ -700,12 +530,11 @@ mp_status mp_green_apply(mp_plan P, const void* dev_in, void* dev_out) {
   using E8 = Eng<double>;
   const Geometry& g = P->g;
   XArgs<double> xa = E8::xargs(P);
-  xa.ctl = nullptr;
   xa.fin = static_cast<const double*>(dev_in);
-  launch_x<double, X_FWD_ONLY>(g.n0, g.xblocks, P->stream, xa);
+  launch_x<double, X_FWD_ONLY>(g.n0, g.xblocks, P->stream, xa, nullptr);
   E8::spectral(P, E8::S(P), nullptr, nullptr);
   xa.fout = static_cast<double*>(dev_out);
-  launch_x<double, X_INV_ONLY>(g.n0, g.xblocks, P->stream, xa);
+  launch_x<double, X_INV_ONLY>(g.n0, g.xblocks, P->stream, xa, nullptr);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(P->stream));
   return MP_OK;

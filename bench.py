@@ -61,6 +61,15 @@ WORKLOADS = {
         precision="mixed", dtype="f32 bulk / f64 reductions",
         desc="spheres256_mixed: 256^3 voxels, random elastic spheres r~U[5,15] to volume fraction "
              "0.25, contrast 10, E11->0.01 over 20 steps, tol 1e-6 (Eq. 38), FP32 bulk arithmetic"),
+    "batch64_mixed": dict(
+        precision="mixed", dtype="f32 bulk / f64 reductions",
+        desc="batch64_mixed: 64 resident RVEs, edge U{32,64,96,128}, 1-60 spheres r~U[n/20,n/10], "
+             "contrast U[2,20], l~U[0.5,4], tY~U[0.003,0.01], random symmetric strain to norm 0.01 "
+             "over 20 steps, tol 1e-6, one batch, graph-captured iterations"),
+    "serve_mixed": dict(
+        precision="mixed", dtype="f32 bulk / f64 reductions",
+        desc="serve_mixed: Poisson request trace, edge {32,64,128,256} with weights .4/.3/.2/.1, "
+             "10-40 steps per request, continuous batching (mixed) against sequential FP64 plans"),
 }
 
 
@@ -82,6 +91,122 @@ def cpu_baseline(wl, iters=2):
                       f"(plus the first iterate and commit), {dt:.1f} s wall, 1 thread"}
 
 
+def run_batch(args, torch, mp, W):
+    """Many-RVE batch: every RVE admitted at once, drained; against the same
+    RVEs solved one after another with FP64 plans (first --seq-rves of them)."""
+    rves = W.batch_rves(seed=3, count=args.rves)
+    shapes = sorted({w.phase_map.shape[::-1] for w in rves})
+    probe = mp.Batch(shapes, arena_bytes=64 << 20, precision="mixed", max_rves=4, autotune=False)
+    need = sum(probe.footprint(w.phase_map, w.phases, len(w.E), tol=w.tol) for w in rves)
+    probe.close()
+    print(f"# {len(rves)} RVEs, {sum(w.phase_map.size for w in rves) / 1e6:.1f} M voxels, "
+          f"arena {need / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+    B = mp.Batch(shapes, arena_bytes=need + (2 << 30), precision="mixed", max_rves=max(64, len(rves)),
+                 iters_per_launch=args.iters_per_launch, autotune=True)
+    sched = {"x".join(map(str, sh)): B.schedule(c) for c, sh in enumerate(shapes)}
+    ids = [B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol) for w in rves]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    active, launches = len(ids), 0
+    while active:
+        active = B.run()
+        launches += 1
+        if launches % 25 == 0:
+            print(f"# launches {launches}, active {active}, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    q = [B.query(i) for i in ids]
+    vox_it = sum(qq[3] * w.phase_map.size for qq, w in zip(q, rves))
+    statuses = [qq[1] for qq in q]
+    B.close()
+    seq = None
+    if args.seq_rves:
+        sub = rves[: args.seq_rves]
+        t1 = time.perf_counter()
+        its = 0
+        for w in sub:
+            plan = mp.Plan(w.phase_map, w.phases, tol=w.tol, precision="fp64")
+            it = plan.solve(w.times, w.E, w.G, raise_on_error=False)[1]
+            its += sum(it) * w.phase_map.size
+            plan.close()
+            print(f"# sequential fp64 rve {w.name}: {sum(it)} iterations", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        d1 = time.perf_counter() - t1
+        seq = {"rves": len(sub), "seconds": round(d1, 3), "rve_solves_per_s": len(sub) / d1,
+               "voxel_iterations_per_s": its / d1}
+    return {
+        "metric": "voxel-iterations/s", "value": vox_it / dt, "unit": "voxel-iterations/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 bulk / f64 reductions",
+        "data": "synthetic (seeded random-sphere RVEs)",
+        "config": {"workload": WORKLOADS["batch64_mixed"]["desc"], "rves": len(rves),
+                   "voxels": int(sum(w.phase_map.size for w in rves)),
+                   "iters_per_launch": args.iters_per_launch, "graph_launches": launches,
+                   "parallelism": "single GPU"},
+        "rve_solves_per_s": len(rves) / dt,
+        "statuses": {str(k): statuses.count(k) for k in sorted(set(statuses))},
+        "schedules": sched,
+        "sequential_fp64": seq,
+    }
+
+
+def run_serve(args, torch, mp, W):
+    """Poisson trace: closed-loop saturation of the batched server, then the
+    open-loop trace at 0.8x that rate through continuous batching (mixed) and
+    through sequential FP64 plans."""
+    n = args.requests
+    base = W.serve_trace(seed=4, n_req=n, rate=1.0)
+    wls = [w for _, w in base]
+    shapes = sorted({w.phase_map.shape[::-1] for w in wls})
+    arena = args.arena_gib << 30
+
+    def items(arrivals):
+        return [(a, w.phase_map, w.phases, w.times, w.E, w.G, dict(tol=w.tol)) for a, w in zip(arrivals, wls)]
+
+    def lat(arr, done):
+        L = np.asarray(done) - np.asarray(arr)
+        return {"p50_s": float(np.percentile(L, 50)), "p99_s": float(np.percentile(L, 99)),
+                "mean_s": float(L.mean())}
+
+    B = mp.Batch(shapes, arena_bytes=arena, precision="mixed", max_rves=256,
+                 iters_per_launch=args.iters_per_launch, autotune=True)
+    print(f"# closed loop: {n} requests at t = 0", file=sys.stderr, flush=True)
+    zero = np.zeros(n)
+    ta, td, st, it = mp.serve_batched(B, mp.Requests(items(zero), "mixed"))
+    makespan = float(td.max())
+    sat = n / makespan
+    rate = 0.8 * sat
+    gaps = np.random.default_rng(4).exponential(1.0 / rate, size=n)
+    arr = np.cumsum(gaps) - gaps[0]
+    print(f"# saturation {sat:.3f} req/s; open loop at {rate:.3f} req/s", file=sys.stderr, flush=True)
+    ta2, td2, st2, it2 = mp.serve_batched(B, mp.Requests(items(arr), "mixed"))
+    B.close()
+    del B
+    torch.cuda.empty_cache()
+    print("# sequential fp64 on the same trace", file=sys.stderr, flush=True)
+    ws = torch.empty(arena, dtype=torch.uint8, device="cuda:0")
+    ts3, td3, st3, it3 = mp.serve_sequential(mp.Requests(items(arr), "fp64"), ws)
+    vox = np.array([w.phase_map.size for w in wls])
+    return {
+        "metric": "requests/s", "value": n / float(td2.max()), "unit": "requests/s", "n_gpus": 1,
+        "steps": n, "warmup": 0, "ms_per_step": float(td2.max()) / n * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 bulk / f64 reductions",
+        "data": "synthetic (seeded Poisson trace of random-sphere RVEs)",
+        "config": {"workload": WORKLOADS["serve_mixed"]["desc"], "requests": n,
+                   "arrival_rate_per_s": rate, "iters_per_launch": args.iters_per_launch,
+                   "arena_gib": args.arena_gib, "parallelism": "single GPU"},
+        "closed_loop": {"requests_per_s": sat, "makespan_s": makespan,
+                        "voxel_iterations_per_s": float((it * vox).sum()) / makespan},
+        "batched_mixed": dict(lat(arr, td2), makespan_s=float(td2.max()),
+                              statuses=[int(v) for v in set(st2)],
+                              voxel_iterations_per_s=float((it2 * vox).sum()) / float(td2.max())),
+        "sequential_fp64": dict(lat(arr, td3), makespan_s=float(td3.max()),
+                                statuses=[int(v) for v in set(st3)],
+                                voxel_iterations_per_s=float((it3 * vox).sum()) / float(td3.max())),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +217,13 @@ def main():
     ap.add_argument("--workload", default="spheres128_fp64", choices=sorted(WORKLOADS))
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="run every load step for exactly this many iterations (profiling runs)")
+    ap.add_argument("--rves", type=int, default=64, help="batch64_mixed: RVEs in the batch")
+    ap.add_argument("--seq-rves", type=int, default=0,
+                    help="batch64_mixed: also solve the first N RVEs one by one with FP64 plans")
+    ap.add_argument("--requests", type=int, default=24, help="serve_mixed: requests in the trace")
+    ap.add_argument("--arena-gib", type=int, default=48, help="serve_mixed: device arena (GiB)")
+    ap.add_argument("--iters-per-launch", type=int, default=8,
+                    help="batch / serve: loop iterations per graph launch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -112,6 +244,11 @@ def main():
 
     import torch
     from paper_2409_10774_amd import mp, workloads as W
+
+    if args.workload in ("batch64_mixed", "serve_mixed"):
+        run = run_batch if args.workload == "batch64_mixed" else run_serve
+        print(json.dumps(run(args, torch, mp, W)), flush=True)
+        return
 
     W_, K = args.warmup, args.steps
     cfg = WORKLOADS[args.workload]

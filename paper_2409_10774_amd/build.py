@@ -17,6 +17,11 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of every code object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a * b + c is fused only within one source expression, so the rounding of
+    # every formula is fixed by the source and not by the kernel it is
+    # inlined into: the resident-batch kernels and the single-RVE kernels then
+    # compute bit-identical results
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 

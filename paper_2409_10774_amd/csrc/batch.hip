@@ -338,10 +338,14 @@ mp_status BEng<T>::setup_class(mp_batch B, ClassInfo& C) {
   reps = std::min(reps, kMaxSlots);
   // temporary region: reps spectra (zero), twiddles, descriptors, a list
   const size_t tw_bytes = align256(size_t(g.n0 + g.n1 + g.n2) * sizeof(cx<T>));
-  const size_t rv_bytes = align256(size_t(reps) * sizeof(Rve<T>));
-  const size_t need = size_t(reps) * spec_bytes + tw_bytes + rv_bytes + align256(sizeof(Lists));
-  size_t off;
-  if (!B->arena.alloc(need, &off)) return MP_OK;   // no room: keep the defaults
+  size_t rv_bytes, need, off;
+  for (;;) {   // as many replicas as the free arena allows (none: keep the defaults)
+    rv_bytes = align256(size_t(reps) * sizeof(Rve<T>));
+    need = size_t(reps) * spec_bytes + tw_bytes + rv_bytes + align256(sizeof(Lists));
+    if (B->arena.alloc(need, &off)) break;
+    if (reps == 1) return MP_OK;
+    reps /= 2;
+  }
   unsigned char* base = B->ws + off;
   auto cleanup = [&]() { B->arena.release(off, need); };
   std::vector<cx<T>> tw;

@@ -40,6 +40,20 @@ class mp_problem(C.Structure):
                 ("err_norm", C.c_int32), ("precision", C.c_int32)]
 
 
+class mp_batch_config(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("n_shapes", C.c_int32), ("shapes", (C.c_int32 * 3) * 8),
+                ("max_rves", C.c_int32), ("iters_per_launch", C.c_int32), ("autotune", C.c_int32)]
+
+
+class mp_request(C.Structure):
+    _fields_ = [("arrival", C.c_double), ("prob", C.POINTER(mp_problem)), ("n_steps", C.c_int32),
+                ("times", C.POINTER(C.c_double)), ("E", C.POINTER(C.c_double)),
+                ("Gam", C.POINTER(C.c_double))]
+
+
+MP_RVE_RUNNING, MP_RVE_DONE = 0, 1
+
+
 class MPError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -67,6 +81,24 @@ def _load():
         "mp_profile": (C.c_int, [vp, i32]),
         "mp_profile_read": (C.c_int, [vp, i32, dp, C.POINTER(C.c_int64)]),
         "mp_plan_destroy": (None, [vp]),
+        "mp_batch_footprint": (C.c_int, [C.POINTER(mp_batch_config), C.POINTER(mp_problem), i32,
+                                         C.POINTER(C.c_size_t)]),
+        "mp_batch_create": (C.c_int, [C.POINTER(mp_batch_config), vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "mp_batch_admit": (C.c_int, [vp, C.POINTER(mp_problem), i32, dp, dp, dp, C.POINTER(i32)]),
+        "mp_batch_run": (C.c_int, [vp, C.POINTER(i32)]),
+        "mp_batch_drain": (C.c_int, [vp, i32, C.POINTER(i32)]),
+        "mp_batch_query": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                     C.POINTER(i64)]),
+        "mp_batch_response": (C.c_int, [vp, i32, i32, dp]),
+        "mp_batch_get_field": (C.c_int, [vp, i32, i32, dp]),
+        "mp_batch_release": (C.c_int, [vp, i32]),
+        "mp_batch_schedule": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]),
+        "mp_batch_stats": (C.c_int, [vp, C.POINTER(i64), C.POINTER(C.c_size_t), C.POINTER(i32)]),
+        "mp_batch_destroy": (None, [vp]),
+        "mp_serve_batched": (C.c_int, [vp, i32, C.POINTER(mp_request), i32, dp, dp, C.POINTER(i32),
+                                       C.POINTER(i64)]),
+        "mp_serve_sequential": (C.c_int, [i32, C.POINTER(mp_request), vp, C.c_size_t, vp, dp, dp,
+                                          C.POINTER(i32), C.POINTER(i64)]),
         "mp_last_error": (C.c_char_p, []),
         "mp_version": (C.c_char_p, []),
     }
@@ -258,6 +290,181 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _path(times, E, G):
+    times = np.ascontiguousarray(times, dtype=np.float64)
+    S = len(times) - 1
+    E = np.ascontiguousarray(np.asarray(E, np.float64).reshape(S, 9))
+    G = np.ascontiguousarray(np.asarray(G, np.float64).reshape(S, 9))
+    return S, times, E, G
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def batch_config(shapes, precision="mixed", max_rves=64, iters_per_launch=8, autotune=True):
+    cfg = mp_batch_config()
+    cfg.precision = {"fp64": MP_FP64, "mixed": MP_MIXED}[precision]
+    cfg.n_shapes = len(shapes)
+    for i, s in enumerate(shapes):
+        for j in range(3):
+            cfg.shapes[i][j] = int(s[j])
+    cfg.max_rves = int(max_rves)
+    cfg.iters_per_launch = int(iters_per_launch)
+    cfg.autotune = 1 if autotune else 0
+    return cfg
+
+
+class Batch:
+    """A resident batch of RVEs on one GPU (mp_batch_*): owns a torch arena."""
+
+    def __init__(self, shapes, arena_bytes, precision="mixed", max_rves=64, iters_per_launch=8,
+                 autotune=True, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.precision = precision
+        self.cfg = batch_config(shapes, precision, max_rves, iters_per_launch, autotune)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        check(lib.mp_batch_create(C.byref(self.cfg), _ptr(self.arena), int(arena_bytes),
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+        self._shape = {}
+
+    def footprint(self, phase_map, phases, n_steps, **kw):
+        prob = make_problem(phase_map, phases, precision=self.precision, **kw)
+        n = C.c_size_t()
+        check(lib.mp_batch_footprint(C.byref(self.cfg), C.byref(prob), int(n_steps), C.byref(n)))
+        return n.value
+
+    def admit(self, phase_map, phases, times, E, G, raise_on_error=True, **kw):
+        """Admit one RVE with its load path; returns its id (or a status when
+        raise_on_error is False and admission fails)."""
+        prob = make_problem(phase_map, phases, precision=self.precision, **kw)
+        S, times, E, G = _path(times, E, G)
+        i = C.c_int32()
+        st = lib.mp_batch_admit(self.handle, C.byref(prob), S, _dp(times), _dp(E), _dp(G), C.byref(i))
+        if st != MP_OK:
+            if raise_on_error:
+                check(st)
+            return None, st
+        self._shape[i.value] = prob._keep[0].shape
+        return (i.value, MP_OK) if not raise_on_error else i.value
+
+    def run(self):
+        a = C.c_int32()
+        check(lib.mp_batch_run(self.handle, C.byref(a)))
+        return a.value
+
+    def drain(self, max_launches=0):
+        n = C.c_int32()
+        check(lib.mp_batch_drain(self.handle, int(max_launches), C.byref(n)))
+        return n.value
+
+    def query(self, rid):
+        """(state, status, steps_done, iterations)"""
+        st, sc, sd = C.c_int32(), C.c_int32(), C.c_int32()
+        it = C.c_int64()
+        check(lib.mp_batch_query(self.handle, int(rid), C.byref(st), C.byref(sc), C.byref(sd),
+                                 C.byref(it)))
+        return st.value, sc.value, sd.value, it.value
+
+    def record(self, rid, step):
+        out = (C.c_double * 48)()
+        check(lib.mp_batch_response(self.handle, int(rid), int(step), out))
+        return np.array(out[:])
+
+    def responses(self, rid):
+        """[steps, 47]: response (42) then error parts and floor flag (5)"""
+        n = self.query(rid)[2]
+        return np.array([self.record(rid, s)[:47] for s in range(1, n + 1)])
+
+    def field(self, rid, name):
+        shape = self._shape[rid]
+        nvox = int(np.prod(shape))
+        count = 9 * nvox if name in ("e", "g", "t", "m") else nvox
+        out = np.empty(count, np.float64)
+        check(lib.mp_batch_get_field(self.handle, int(rid), FIELDS[name], _dp(out)))
+        return out.reshape(shape) if count == nvox else out.reshape((9,) + shape)
+
+    def release(self, rid):
+        check(lib.mp_batch_release(self.handle, int(rid)))
+        self._shape.pop(rid, None)
+
+    def schedule(self, cls):
+        out = (C.c_int32 * 8)()
+        ms = (C.c_float * 3)()
+        check(lib.mp_batch_schedule(self.handle, int(cls), out, ms))
+        o = list(out)
+        return {"y_fwd": {"tx": o[0], "grid": o[1], "ms": ms[0]},
+                "z_green": {"tx": o[2], "grid": o[3], "ms": ms[1]},
+                "y_inv": {"tx": o[4], "grid": o[5], "ms": ms[2]},
+                "x_grid": o[6], "x_tiles": o[7]}
+
+    def stats(self):
+        g, r = C.c_int64(), C.c_int32()
+        u = C.c_size_t()
+        check(lib.mp_batch_stats(self.handle, C.byref(g), C.byref(u), C.byref(r)))
+        return {"graph_launches": g.value, "arena_used": u.value, "resident": r.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.mp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Requests:
+    """Marshalled request trace: items (arrival, phase_map, phases, times, E, G, kw)."""
+
+    def __init__(self, items, precision="mixed"):
+        self.arr = (mp_request * max(1, len(items)))()
+        self._keep = []
+        for i, (arrival, pm, phases, times, E, G, kw) in enumerate(items):
+            prob = make_problem(pm, phases, precision=precision, **kw)
+            S, times, E, G = _path(times, E, G)
+            self._keep.append((prob, times, E, G))
+            r = self.arr[i]
+            r.arrival = float(arrival)
+            r.prob = C.pointer(prob)
+            r.n_steps = S
+            r.times, r.E, r.Gam = _dp(times), _dp(E), _dp(G)
+        self.n = len(items)
+
+
+def _serve_out(n):
+    return (C.c_double * max(1, n))(), (C.c_double * max(1, n))(), (C.c_int32 * max(1, n))(), \
+        (C.c_int64 * max(1, n))()
+
+
+def serve_batched(batch, reqs, max_bypass=16):
+    """Continuous batching of a request trace on an empty Batch; returns per
+    request (t_admit, t_done, status, iterations) as numpy arrays."""
+    a, d, st, it = _serve_out(reqs.n)
+    check(lib.mp_serve_batched(batch.handle, reqs.n, reqs.arr, int(max_bypass), a, d, st, it))
+    n = reqs.n
+    return np.array(a[:n]), np.array(d[:n]), np.array(st[:n]), np.array(it[:n])
+
+
+def serve_sequential(reqs, workspace, stream=None):
+    """The trace served one request at a time with FP64 plans on `workspace`
+    (a torch uint8 device tensor)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(workspace.device)
+    a, d, st, it = _serve_out(reqs.n)
+    check(lib.mp_serve_sequential(reqs.n, reqs.arr, _ptr(workspace), workspace.numel(),
+                                  C.c_void_p(s.cuda_stream), a, d, st, it))
+    n = reqs.n
+    return np.array(a[:n]), np.array(d[:n]), np.array(st[:n]), np.array(it[:n])
 
 
 mp_version = lambda: lib.mp_version().decode()

@@ -265,6 +265,31 @@ def random_rve(seed: int, n: int, n_steps: int = 20) -> Workload:
                     info={"spheres": len(sp), "contrast": contrast, "l": length, "tY": tY})
 
 
+def batch_rves(seed: int = 3, count: int = 64, sizes=(32, 64, 96, 128), n_steps: int = 20):
+    """The many-RVE batch: `count` RVEs, edge drawn uniformly from `sizes`,
+    each a random_rve of its own seed (mixed precision, tol 1e-6)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.asarray(sizes), size=count)
+    seeds = rng.integers(0, 2**31, size=count)
+    return [random_rve(int(sd), int(n), n_steps) for sd, n in zip(seeds, ns)]
+
+
+def serve_trace(seed: int = 4, n_req: int = 200, rate: float = 1.0,
+                sizes=(32, 64, 128, 256), weights=(0.4, 0.3, 0.2, 0.1), steps=(10, 40)):
+    """Poisson request trace: arrival times (s) with mean rate `rate` per
+    second, and per request a random_rve of edge drawn from `sizes` with
+    `weights` and a load path of U{steps[0]..steps[1]} steps.  Returns
+    [(arrival, Workload)]."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n_req)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    ns = rng.choice(np.asarray(sizes), size=n_req, p=np.asarray(weights) / np.sum(weights))
+    st = rng.integers(steps[0], steps[1] + 1, size=n_req)
+    seeds = rng.integers(0, 2**31, size=n_req)
+    return [(float(a), random_rve(int(sd), int(n), int(k)))
+            for a, n, k, sd in zip(arrivals, ns, st, seeds)]
+
+
 def mnms_cube4():
     """4^3 cube used for manufactured solutions: inner centred 2^3 block is
     phase 0, the outer layer phase 1 (constants of the paper's code check)."""

@@ -204,10 +204,10 @@ typedef struct {
   int32_t max_rves;          /* resident RVEs at most, 1..512 */
   int32_t iters_per_launch;  /* loop iterations per graph launch, 1..64 */
   int32_t autotune;          /* 1: at creation, time each class's y / z tile
-                                widths {1, wide/2, wide} at full and half
-                                occupancy and keep the fastest (cached per
-                                shape for the process); 0: the single-plan
-                                schedule */
+                                widths {1, wide/2, wide} with the full
+                                persistent grid and a quarter of it and keep
+                                the fastest (cached per shape for the
+                                process); 0: the single-plan tile widths */
 } mp_batch_config;
 
 enum { MP_RVE_RUNNING = 0, MP_RVE_DONE = 1 };
@@ -254,6 +254,11 @@ mp_status mp_batch_response(mp_batch batch, int32_t id, int32_t step, double out
 
 /* One field of RVE `id` (after its last committed step), as mp_get_fields. */
 mp_status mp_batch_get_field(mp_batch batch, int32_t id, int32_t field, double* host_dst);
+
+/* Test hook, as mp_set_fixed_iterations for RVE `id`: with n_fixed > 0
+ * every step of it runs exactly n_fixed loop iterations (0 restores the
+ * tolerance test); applies from its current step on.  Call between launches. */
+mp_status mp_batch_set_fixed_iterations(mp_batch batch, int32_t id, int32_t n_fixed);
 
 /* Remove RVE `id` (cancelling it if unfinished) and return its arena region. */
 mp_status mp_batch_release(mp_batch batch, int32_t id);

@@ -166,12 +166,12 @@ bool axis_kernel(int L, int tx, const void** fn, int* nthr, size_t* shm) {
   return false;
 }
 
-template <class T>
+template <class T, int MODE>
 bool x_kernel(int n0, const void** fn, int* nthr) {
   switch (n0) {
 #define MP_CASE(N)                                                 \
   case N:                                                          \
-    *fn = reinterpret_cast<const void*>(&k_batch_x<T, N>);         \
+    *fn = reinterpret_cast<const void*>(&k_batch_x<T, MODE, N>);   \
     *nthr = XShape<N>::NTHR;                                       \
     return true;
     MP_SIZES(MP_CASE)
@@ -206,11 +206,13 @@ struct BEng {
     return launch(fn, grid, nthr, shm, s, args);
   }
 
-  static hipError_t xpass(mp_batch B, int c, hipStream_t s) {
+  static hipError_t xpass(mp_batch B, int c, int mode, hipStream_t s) {
     const ClassInfo& C = B->cls[c];
     const void* fn;
     int nthr;
-    if (!x_kernel<T>(C.n[0], &fn, &nthr)) return hipErrorInvalidValue;
+    if (!(mode == X_ITER ? x_kernel<T, X_ITER>(C.n[0], &fn, &nthr)
+                         : x_kernel<T, X_TRANS>(C.n[0], &fn, &nthr)))
+      return hipErrorInvalidValue;
     const Rve<T>* rvp = rv(B);
     const Lists* lsp = B->ls;
     int cls = c, tiles = C.g.xblocks;
@@ -232,19 +234,24 @@ struct BEng {
         if ((e = axis(B, c, p, rv(B), B->ls, B->cls[c].pass[p].tx, B->cls[c].pass[p].grid, s)) !=
             hipSuccess)
           return e;
-    for (int c = 0; c < int(B->cls.size()); ++c)
-      if ((e = xpass(B, c, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_batch_rows<T>), dim3(4 * B->cus), dim3(256), 0, s, rv(B), B->ls,
+    for (int c = 0; c < int(B->cls.size()); ++c) {
+      if ((e = xpass(B, c, X_ITER, s)) != hipSuccess) return e;
+      if ((e = xpass(B, c, X_TRANS, s)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_batch_rows<T>), dim3(8 * B->cus), dim3(256), 0, s, rv(B), B->ls,
                        int(B->cls.size()));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return ctl(B, 1, s);
   }
 
+  // Grid of a pass: 8 times the blocks the CUs have wave slots for (32
+  // waves per CU).  Blocks stride over the work items; extra blocks find no
+  // item and exit.  The grid does not depend on an occupancy estimate.
   static hipError_t occupancy(const void* fn, int nthr, size_t shm, int cus, int* grid) {
-    int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nthr, shm);
-    if (e != hipSuccess) return e;
-    *grid = std::max(1, nb) * cus;
+    (void)fn;
+    (void)shm;
+    const int waves = (nthr + 63) / 64;
+    *grid = 8 * cus * std::max(1, 32 / waves);
     return hipSuccess;
   }
 
@@ -306,15 +313,15 @@ mp_status default_sched(mp_batch B, ClassInfo& C) {
   }
   const void* fn;
   int nthr;
-  if (!x_kernel<T>(C.n[0], &fn, &nthr)) return fail(MP_E_INVALID, "no x kernel");
+  if (!x_kernel<T, X_ITER>(C.n[0], &fn, &nthr)) return fail(MP_E_INVALID, "no x kernel");
   HIP_TRY(BEng<T>::occupancy(fn, nthr, 0, B->cus, &C.xgrid));
   return MP_OK;
 }
 
 // Autotuner: for each y / z pass of a class, time every tile width in
 // {1, wide / 2, wide} (wide = the largest with TX * L <= 256 dividing n0/2)
-// at full and half occupancy on replicas of the class's spectrum (enough
-// replicas for about 2^23 voxels), keep the fastest.  Results are cached
+// with the full persistent grid and a quarter of it, on replicas of the
+// class's spectrum (enough replicas for about 2^23 voxels), keep the fastest.  Results are cached
 // per (precision, shape) for the process.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, std::array<PassSched, 3>> g_tune_cache;
@@ -411,15 +418,19 @@ mp_status BEng<T>::setup_class(mp_batch B, ClassInfo& C) {
         int full;
         HIP_TRY(occupancy(fn, nthr, shm, B->cus, &full));
         for (int half = 0; half < 2; ++half) {
-          const int grid = half ? std::max(B->cus, full / 2) : full;
+          const int grid = half ? std::max(B->cus, full / 4) : full;
           if (half && grid == full) continue;
           HIP_TRY(axis(B, ci, p, trv, tls, tx, grid, B->stream));   // warm-up
-          HIP_TRY(hipEventRecord(ev[0], B->stream));
-          for (int rep = 0; rep < 3; ++rep) HIP_TRY(axis(B, ci, p, trv, tls, tx, grid, B->stream));
-          HIP_TRY(hipEventRecord(ev[1], B->stream));
-          HIP_TRY(hipEventSynchronize(ev[1]));
           float ms = 0.f;
-          HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+          for (int rep = 0; rep < 3; ++rep) {
+            HIP_TRY(hipEventRecord(ev[0], B->stream));
+            HIP_TRY(axis(B, ci, p, trv, tls, tx, grid, B->stream));
+            HIP_TRY(hipEventRecord(ev[1], B->stream));
+            HIP_TRY(hipEventSynchronize(ev[1]));
+            float one = 0.f;
+            HIP_TRY(hipEventElapsedTime(&one, ev[0], ev[1]));
+            ms += one;
+          }
           ms /= 3.f;
           if (ms < best_ms) {
             best_ms = ms;
@@ -748,7 +759,7 @@ mp_status mp_batch_run(mp_batch B, int32_t* n_active) {
   mp_status st = capture(B);
   if (st != MP_OK) return st;
   HIP_TRY(hipGraphLaunch(B->exec, B->stream));
-  HIP_TRY(hipMemcpyAsync(B->ls_host, B->ls, offsetof(Lists, x), hipMemcpyDeviceToHost, B->stream));
+  HIP_TRY(hipMemcpyAsync(B->ls_host, B->ls, offsetof(Lists, s), hipMemcpyDeviceToHost, B->stream));
   HIP_TRY(hipStreamSynchronize(B->stream));
   B->graph_launches += 1;
   if (n_active) *n_active = B->ls_host->active;
@@ -829,6 +840,25 @@ mp_status mp_batch_get_field(mp_batch B, int32_t id, int32_t field, double* dst)
     return MP_OK;
   }
   HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  return MP_OK;
+}
+
+mp_status mp_batch_set_fixed_iterations(mp_batch B, int32_t id, int32_t n_fixed) {
+  RveHost* H;
+  mp_status st = find(B, id, &H);
+  if (st != MP_OK) return st;
+  if (n_fixed < 0) return fail(MP_E_INVALID, "n_fixed < 0");
+  // the descriptor's count (copied into the loop control at every step start)
+  // and the running step's own
+  const bool f32 = B->w == sizeof(float);
+  const size_t base = size_t(H->slot) * (f32 ? sizeof(Rve<float>) : sizeof(Rve<double>));
+  const size_t at_r = base + (f32 ? offsetof(Rve<float>, fixed) : offsetof(Rve<double>, fixed));
+  const size_t at_c = base + (f32 ? offsetof(Rve<float>, ctl) : offsetof(Rve<double>, ctl)) +
+                      offsetof(Ctl, fixed);
+  unsigned char* d = static_cast<unsigned char*>(B->rv);
+  HIP_TRY(hipMemcpyAsync(d + at_r, &n_fixed, sizeof n_fixed, hipMemcpyHostToDevice, B->stream));
+  HIP_TRY(hipMemcpyAsync(d + at_c, &n_fixed, sizeof n_fixed, hipMemcpyHostToDevice, B->stream));
   HIP_TRY(hipStreamSynchronize(B->stream));
   return MP_OK;
 }

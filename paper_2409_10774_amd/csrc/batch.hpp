@@ -51,74 +51,105 @@ struct Rve {
 };
 
 struct Lists {
-  int nx[kMaxClasses];   // RVEs with an x pass this iteration (RUN or TRANS)
-  int ns[kMaxClasses];   // RVEs with spectral passes this iteration (RUN)
+  int ns[kMaxClasses];   // RVEs iterating this iteration (RUN): spectral + ITER x passes
+  int nt[kMaxClasses];   // RVEs between steps (TRANS): TRANS x pass
   int active;            // RVEs in RUN or TRANS
   int launches;          // control-kernel passes (loop iterations of the batch)
   int st[kMaxSlots];     // state of every slot
-  int x[kMaxClasses][kMaxSlots];
   int s[kMaxClasses][kMaxSlots];
+  int t[kMaxClasses][kMaxSlots];
 };
 
-// x pass of one shape class: ITER for RUN RVEs, TRANS for TRANS RVEs
-template <class T, int N0>
-__global__ void __launch_bounds__(XShape<N0>::NTHR) k_batch_x(const Rve<T>* rv, const Lists* ls,
-                                                              int cls, int tiles) {
+// The thread index as a fresh value on every pass of a work loop: the
+// per-thread index arithmetic of a pass then stays inside the loop instead of
+// being hoisted out of it and held in registers across every item.
+__device__ __forceinline__ int fresh_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Work distribution: block b takes work items b, b + G, b + 2G, ... of its
+// pass (G = grid size).  Every item of a pass costs the same, so a grid that
+// is an integer multiple of what the chip holds at once loses nothing to
+// imbalance; the grids are large (several times the chip's block slots), and
+// in the common case a block takes a single item.  No atomics: a shared
+// work counter serialises across the chip's L2 domains.
+// x pass of one shape class: ITER over the RUN list, or TRANS over the
+// TRANS list (separate kernels, so each keeps its own register budget)
+// The ITER pass is held to the occupancy of the single-RVE x pass (3 waves
+// per SIMD in FP64, 4 in FP32).
+template <class T, int MODE>
+constexpr int x_min_waves() { return MODE != X_ITER ? 1 : sizeof(T) == 8 ? 3 : 4; }
+
+template <class T, int MODE, int N0>
+__global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_batch_x(const Rve<T>* __restrict__ rv,
+                                                              const Lists* __restrict__ ls, int cls,
+                                                              int tiles) {
   using X = XShape<N0>;
   __shared__ cx<T> lds[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
-  const long total = long(ls->nx[cls]) * tiles;
-  for (long w = blockIdx.x; w < total; w += gridDim.x) {
-    const int slot = ls->x[cls][w / tiles];
-    const long tile = w % tiles;
-    const Rve<T>& R = rv[slot];
-    __syncthreads();   // the previous tile is done with LDS
-    if (R.state == RV_RUN)
-      xpass_tile<T, X_ITER, N0>(R.x, tile, tiles, lds, red);
-    else
-      xpass_tile<T, X_TRANS, N0>(R.x, tile, tiles, lds, red);
+  const int n = MODE == X_ITER ? ls->ns[cls] : ls->nt[cls];
+  const int* list = MODE == X_ITER ? ls->s[cls] : ls->t[cls];
+  const int total = n * tiles;
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int slot = list[w / tiles];
+    const int tile = w % tiles;
+    __syncthreads();   // the previous item is done with LDS
+    xpass_tile<T, MODE, N0>(rv[slot].x, tile, tiles, lds, red, fresh_tid());
   }
 }
 
 // y or z pass of one shape class over its RUN RVEs; tile t of an RVE is
 // (bx, by) = (t mod gx, t / gx)
 template <class T, int MODE, int L, int TX>
-__global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_batch_axis(const Rve<T>* rv, const Lists* ls,
+__global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_batch_axis(const Rve<T>* __restrict__ rv,
+                                                                      const Lists* __restrict__ ls,
                                                                       int cls, int gx, int gy) {
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int tiles = gx * gy;
-  const long total = long(ls->ns[cls]) * tiles;
-  for (long w = blockIdx.x; w < total; w += gridDim.x) {
+  const int total = ls->ns[cls] * tiles;
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int slot = ls->s[cls][w / tiles];
-    const int t = int(w % tiles);
+    const int t = w % tiles;
     __syncthreads();
     const AxisArgs<T>& a = (MODE == Y_FWD || MODE == Y_INV) ? rv[slot].y : rv[slot].z;
-    axis_tile<T, MODE, L, TX>(a, t % gx, t / gx, lds, threadIdx.x);
+    axis_tile<T, MODE, L, TX>(a, t % gx, t / gx, lds, fresh_tid());
   }
 }
 
-// Row reductions of every x pass of the iteration: error rows of RUN RVEs,
-// step-average rows of committing TRANS RVEs (same code and order as the
-// single-RVE path).
+// Row reductions of every x pass of the iteration: the kNPart error rows of
+// each RUN RVE, then the kNAvg step-average rows of each committing TRANS RVE
+// (same code and order as the single-RVE path).
 template <class T>
-__global__ void __launch_bounds__(256) k_batch_rows(Rve<T>* rv, const Lists* ls, int ncls) {
+__global__ void __launch_bounds__(256) k_batch_rows(Rve<T>* __restrict__ rv,
+                                                    const Lists* __restrict__ ls, int ncls) {
   __shared__ double red[4];
-  long total = 0;
-  for (int c = 0; c < ncls; ++c) total += long(ls->nx[c]) * kNAvg;
-  for (long w = blockIdx.x; w < total; w += gridDim.x) {
-    long u = w;
-    int c = 0;
-    while (u >= long(ls->nx[c]) * kNAvg) {
-      u -= long(ls->nx[c]) * kNAvg;
-      ++c;
+  int total = 0;
+  for (int c = 0; c < ncls; ++c) total += ls->ns[c] * kNPart + ls->nt[c] * kNAvg;
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    int u = w, c = 0, slot = 0, j = 0;
+    bool iter = true;
+    for (;; ++c) {
+      if (u < ls->ns[c] * kNPart) {
+        slot = ls->s[c][u / kNPart];
+        j = u % kNPart;
+        break;
+      }
+      u -= ls->ns[c] * kNPart;
+      if (u < ls->nt[c] * kNAvg) {
+        slot = ls->t[c][u / kNAvg];
+        j = u % kNAvg;
+        iter = false;
+        break;
+      }
+      u -= ls->nt[c] * kNAvg;
     }
-    const int slot = ls->x[c][u / kNAvg], j = int(u % kNAvg);
     Rve<T>& R = rv[slot];
-    const bool iter = R.state == RV_RUN;
-    if (iter ? j >= kNPart : !R.x.commit) continue;
+    if (!iter && !R.x.commit) continue;
     __syncthreads();
-    const double v = row_reduce(R.x.partials + (long)j * R.xblocks, R.xblocks,
+    const double v = row_reduce(glob(R.x.partials) + (long)j * R.xblocks, R.xblocks,
                                 iter && err_row_is_max(j), red);
     if (threadIdx.x == 0) R.tot[j] = v;
   }
@@ -180,18 +211,16 @@ __global__ void __launch_bounds__(kMaxSlots) k_batch_ctl(Rve<T>* rv, Lists* ls, 
   ls->st[i] = state;
   __syncthreads();
   if (i < ncls) {
-    int nx = 0, ns = 0;
+    int ns = 0, nt = 0;
     for (int k = 0; k < kMaxSlots; ++k) {
       if (cl[k] != i) continue;
-      if (st[k] == RV_RUN) {
+      if (st[k] == RV_RUN)
         ls->s[i][ns++] = k;
-        ls->x[i][nx++] = k;
-      } else if (st[k] == RV_TRANS) {
-        ls->x[i][nx++] = k;
-      }
+      else if (st[k] == RV_TRANS)
+        ls->t[i][nt++] = k;
     }
-    ls->nx[i] = nx;
     ls->ns[i] = ns;
+    ls->nt[i] = nt;
   }
   if (i == kMaxSlots - 1) {
     int a = 0;

@@ -23,6 +23,56 @@ struct __align__(2 * sizeof(T)) cx {
   T re, im;
 };
 
+// Global-memory pointers.  A pointer read out of device memory (a batch
+// descriptor) carries no address space, and accesses through it compile to
+// flat instructions, which also hold the LDS wait counter.  Every global
+// access of the passes goes through a pointer typed for the global address
+// space instead.
+#define MP_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ MP_GLOBAL T* glob(T* p) {
+  return (MP_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const MP_GLOBAL T* glob(const T* p) {
+  return (const MP_GLOBAL T*)p;
+}
+
+// complex values and constant records move through global memory as whole
+// vector words (one dwordx2 / dwordx4 access per complex value)
+template <class T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+  typedef float __attribute__((ext_vector_type(2))) type;
+};
+template <>
+struct Vec2<double> {
+  typedef double __attribute__((ext_vector_type(2))) type;
+};
+template <class T>
+__device__ __forceinline__ cx<T> gload(const MP_GLOBAL cx<T>* p) {
+  const typename Vec2<T>::type v = *(const MP_GLOBAL typename Vec2<T>::type*)p;
+  return cx<T>{v.x, v.y};
+}
+template <class T>
+__device__ __forceinline__ void gstore(MP_GLOBAL cx<T>* p, cx<T> v) {
+  typename Vec2<T>::type w;
+  w.x = v.re;
+  w.y = v.im;
+  *(MP_GLOBAL typename Vec2<T>::type*)p = w;
+}
+template <class S>
+__device__ __forceinline__ S gread(const MP_GLOBAL S* p) {
+  static_assert(sizeof(S) % 8 == 0, "record of 8-byte words");
+  S out;
+  const MP_GLOBAL unsigned long long* q = (const MP_GLOBAL unsigned long long*)p;
+  unsigned long long* o = reinterpret_cast<unsigned long long*>(&out);
+#pragma unroll
+  for (int i = 0; i < int(sizeof(S) / 8); ++i) o[i] = q[i];
+  return out;
+}
+
 template <class T>
 __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <class T>
@@ -122,7 +172,7 @@ struct Dft<T, 3, INV> {
 //   tw: N-entry table exp(-2 pi i m / N).  Unnormalised in both directions.
 // ---------------------------------------------------------------------------
 template <class T, int R, bool INV, int N, int P, int NB, int PS, int BS, bool BFAST, int NTHR>
-__device__ __forceinline__ void stage_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void stage_ct(cx<T>* buf, const MP_GLOBAL cx<T>* __restrict__ tw, int tid) {
   constexpr int NBF = N / R;
   constexpr int TOTAL = NBF * NB;
   constexpr int MB = (TOTAL + NTHR - 1) / NTHR;
@@ -150,7 +200,7 @@ __device__ __forceinline__ void stage_ct(cx<T>* buf, const cx<T>* __restrict__ t
       if (P > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cx<T> t = tw[r * k * TWS];
+          cx<T> t = gload(tw + r * k * TWS);
           if (INV) t.im = -t.im;
           u[j][r] = cmul(u[j][r], t);
         }
@@ -170,7 +220,7 @@ struct NextRadix {
 };
 
 template <class T, bool INV, int N, int P, int NB, int PS, int BS, bool BFAST, int NTHR>
-__device__ __forceinline__ void fft_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_ct(cx<T>* buf, const MP_GLOBAL cx<T>* __restrict__ tw, int tid) {
   if constexpr (P < N) {
     constexpr int R = NextRadix<N / P>::value;
     static_assert((N / P) % R == 0, "size must be a product of 2s and 3s");

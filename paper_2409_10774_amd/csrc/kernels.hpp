@@ -136,15 +136,15 @@ __device__ __forceinline__ int avg_row(int L, int j) {
 // independent, which halves each lane's live state, and the level is uniform
 // over each wavefront.  Each lane prefetches its old strain, history base and
 // p_n / q_n before the transforms so the loads overlap them.
-//   lds: NPK * N0 complex;  red: NTHR / 64 rows of kRed doubles.
+//   lds: NPK * N0 complex;  red: NTHR / 64 rows of kRed doubles;  tid: the
+//   thread index.
 template <class T, int MODE, int N0>
 __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int ntiles, cx<T>* lds,
-                                           double (*red)[kRed]) {
+                                           double (*red)[kRed], int tid) {
   using X = XShape<N0>;
   constexpr int ROWS = X::ROWS, VPB = X::VPB, VPAD = X::VPAD, NTHR = X::NTHR, NH = X::NH;
   constexpr int NPK = X::NPK;
   T* ldr = reinterpret_cast<T*>(lds);
-  const int tid = threadIdx.x;
   const long row0 = tile * ROWS;
   const int lvl = __builtin_amdgcn_readfirstlane(tid >= VPAD ? 1 : 0);
   const int v = tid - lvl * VPAD;
@@ -153,7 +153,13 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
   // 32-bit voxel offset into wave-uniform component bases (at most 2^24 voxels)
   const int gi = own ? int((row0 + vr) * N0 + vx) : 0;
   const long nv = a.nvox;
-  T* const Elv = a.E + (long)lvl * 9 * nv;
+  MP_GLOBAL cx<T>* const S = glob(a.S);
+  const MP_GLOBAL cx<T>* const tw = glob(a.tw);
+  MP_GLOBAL T* const Elv = glob(a.E) + (long)lvl * 9 * nv;
+  MP_GLOBAL T* const Eprev = glob(a.Eprev);
+  MP_GLOBAL T* const Blv = glob(a.base) + (long)lvl * 9 * nv;
+  MP_GLOBAL double* const pq = glob(a.pq);
+  MP_GLOBAL double* const partials = glob(a.partials);
   const int rows_here = int(a.nrows - row0 < ROWS ? a.nrows - row0 : ROWS);
 
   // prefetch this lane's history (ITER, TRANS)
@@ -163,14 +169,13 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
 #pragma unroll
   for (int c = 0; c < 9; ++c) eo[c] = bb[c] = T(0);
   if ((MODE == X_ITER || MODE == X_TRANS) && own) {
-    const T* const Blv = a.base + (long)lvl * 9 * nv;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       eo[c] = Elv[c * nv + gi];
       bb[c] = Blv[c * nv + gi];
     }
-    hn = a.pq[lvl * nv + gi];
-    ph = a.phase[gi];
+    hn = pq[lvl * nv + gi];
+    ph = glob(a.phase)[gi];
   }
 
   if (MODE == X_ITER || MODE == X_INV_ONLY) {
@@ -178,10 +183,11 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
     for (int w = tid; w < rows_here * NH * kPencils; w += NTHR) {
       const int r = w / (NH * kPencils), rem = w % (NH * kPencils);
       const int kx = rem / kPencils, q = rem % kPencils;
-      const cx<T>* srow = a.S + (row0 + r) * (NH * 18) + kx * 18;
+      const MP_GLOBAL cx<T>* srow = S + (row0 + r) * (NH * 18) + kx * 18;
       const int cre = pencil_re(q), cim = pencil_im(q);
-      const cx<T> A = srow[cre];
-      const cx<T> B = cim >= 0 ? srow[cim] : cx<T>{T(0), T(0)};
+      const cx<T> A = gload(srow + cre);
+      cx<T> B = {T(0), T(0)};
+      if (cim >= 0) B = gload(srow + cim);
       cx<T>* pen = lds + (r * kPencils + q) * N0;
       pen[kx] = cx<T>{A.re - B.im, A.im + B.re};
       if (kx > 0)
@@ -190,7 +196,7 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
         pen[NH] = cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    fft_ct<T, true, N0, 1, NPK, 1, N0, false, NTHR>(lds, a.tw, tid);
+    fft_ct<T, true, N0, 1, NPK, 1, N0, false, NTHR>(lds, tw, tid);
   }
 
   // LDS scalar slot of field c (0..17) of this lane's voxel
@@ -199,7 +205,7 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
   if (MODE == X_INV_ONLY) {
     if (own)
 #pragma unroll
-      for (int c = 0; c < 9; ++c) a.fout[(lvl * 9 + c) * nv + gi] = ldr[slot(lvl * 9 + c)];
+      for (int c = 0; c < 9; ++c) glob(a.fout)[(lvl * 9 + c) * nv + gi] = ldr[slot(lvl * 9 + c)];
     return;
   }
 
@@ -217,9 +223,9 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
   MicroC cm;
   if (MODE != X_FWD_ONLY) {
     if (lvl == 0)
-      ct = a.params[ph].t;
+      ct = gread(&glob(a.params)[ph].t);
     else
-      cm = a.params[ph].m;
+      cm = gread(&glob(a.params)[ph].m);
   }
 
   if (MODE == X_TRANS && a.commit) {
@@ -240,8 +246,7 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
         apply_B<T>(T(cm.alp), T(cm.bet), T(cm.gam), eo, r0);
         eq = micro_equivalent<T>(cm, tc);
       }
-      T* const Blv = a.base + (long)lvl * 9 * nv;
-      T* const Olv = a.out_tm + (long)lvl * 9 * nv;
+      MP_GLOBAL T* const Olv = glob(a.out_tm) + (long)lvl * 9 * nv;
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         bb[c] = tc[c] - r0[c];
@@ -249,8 +254,8 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
         Olv[c * nv + gi] = tc[c];
       }
       hn = pc;
-      a.pq[lvl * nv + gi] = pc;
-      a.out_pq[lvl * nv + gi] = pc;
+      pq[lvl * nv + gi] = pc;
+      glob(a.out_pq)[lvl * nv + gi] = pc;
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) wave_put(c, double(tc[c]), false);
@@ -264,7 +269,7 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
       const int w0 = L * (VPAD / 64), w1 = w0 + VPAD / 64;
       double y = red[w0][j];
       for (int w = w0 + 1; w < w1; ++w) y += red[w][j];
-      a.partials[(long)avg_row(L, j) * ntiles + tile] = y;
+      partials[(long)avg_row(L, j) * ntiles + tile] = y;
     }
     if (!a.init) return;   // uniform over the block
   }
@@ -276,7 +281,7 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
     if (own) {
       if (MODE == X_FWD_ONLY) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) e[c] = a.fin[(lvl * 9 + c) * nv + gi];
+        for (int c = 0; c < 9; ++c) e[c] = glob(a.fin)[(lvl * 9 + c) * nv + gi];
       } else if (MODE == X_ITER) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) e[c] = ldr[slot(lvl * 9 + c)] + T(a.mac[lvl * 9 + c]);
@@ -284,9 +289,9 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
           const long at = (lvl * 9 + c) * nv + gi;
-          const T old = a.Eprev[at];
+          const T old = Eprev[at];
           e[c] = a.first ? T(a.mac[lvl * 9 + c]) : T(eo[c] + T(a.r) * (eo[c] - old));
-          a.Eprev[at] = eo[c];
+          Eprev[at] = eo[c];
         }
       }
     }
@@ -363,13 +368,13 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
           const int w0 = L * (VPAD / 64), w1 = w0 + VPAD / 64;
           double y = red[w0][j];
           for (int w = w0 + 1; w < w1; ++w) y = (j < 2) ? nmax(y, red[w][j]) : y + red[w][j];
-          a.partials[(long)tid * ntiles + tile] = y;
+          partials[(long)tid * ntiles + tile] = y;
         }
       }
     }
   }
   __syncthreads();
-  fft_ct<T, false, N0, 1, NPK, 1, N0, false, NTHR>(lds, a.tw, tid);
+  fft_ct<T, false, N0, 1, NPK, 1, N0, false, NTHR>(lds, tw, tid);
   // unpack: A = (Z(k) + conj Z(-k)) / 2, B = (Z(k) - conj Z(-k)) / (2 i)
   for (int w = tid; w < rows_here * NH * kPencils; w += NTHR) {
     const int r = w / (NH * kPencils), rem = w % (NH * kPencils);
@@ -377,10 +382,10 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
     const cx<T>* pen = lds + (r * kPencils + q) * N0;
     const cx<T> zk = pen[kx];
     const cx<T> zm = pen[kx == 0 ? 0 : N0 - kx];
-    cx<T>* srow = a.S + (row0 + r) * (NH * 18) + kx * 18;
+    MP_GLOBAL cx<T>* srow = S + (row0 + r) * (NH * 18) + kx * 18;
     const int cre = pencil_re(q), cim = pencil_im(q);
-    srow[cre] = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
-    if (cim >= 0) srow[cim] = cx<T>{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
+    gstore(srow + cre, cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)});
+    if (cim >= 0) gstore(srow + cim, cx<T>{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)});
   }
 }
 
@@ -392,7 +397,7 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a, const Ct
   if (ctl && ctl->done) return;
   __shared__ cx<T> lds[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
-  xpass_tile<T, MODE, N0>(a, blockIdx.x, gridDim.x, lds, red);
+  xpass_tile<T, MODE, N0>(a, blockIdx.x, gridDim.x, lds, red, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,14 +433,15 @@ template <class T, int MODE, int L, int TX>
 __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, cx<T>* lds, int tid) {
   using A = AShape<L, TX>;
   constexpr int NB = A::NB, PTS = A::PTS, NTHR = A::NTHR;
-  cx<T>* g = a.S + (long)by * a.ostride + (long)bx * NB;
+  MP_GLOBAL cx<T>* g = glob(a.S) + (long)by * a.ostride + (long)bx * NB;
+  const MP_GLOBAL cx<T>* const tw = glob(a.tw);
   for (int w = tid; w < PTS; w += NTHR) {
     const int i = w / NB, b = w % NB;
-    lds[w] = g[i * a.pstride + b];
+    lds[w] = gload(g + i * a.pstride + b);
   }
   __syncthreads();
   constexpr bool INV = MODE == Y_INV;
-  fft_ct<T, INV, L, 1, NB, NB, 1, true, NTHR>(lds, a.tw, tid);
+  fft_ct<T, INV, L, 1, NB, NB, 1, true, NTHR>(lds, tw, tid);
   if (MODE == Z_GREEN) {
     // Green operator at the L * TX frequencies of the tile
     for (int f = tid; f < L * TX; f += NTHR) {
@@ -468,11 +474,11 @@ __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, 
       }
     }
     __syncthreads();
-    fft_ct<T, true, L, 1, NB, NB, 1, true, NTHR>(lds, a.tw, tid);
+    fft_ct<T, true, L, 1, NB, NB, 1, true, NTHR>(lds, tw, tid);
   }
   for (int w = tid; w < PTS; w += NTHR) {
     const int i = w / NB, b = w % NB;
-    g[i * a.pstride + b] = lds[w];
+    gstore(g + i * a.pstride + b, lds[w]);
   }
 }
 
@@ -490,7 +496,8 @@ __global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_axis(AxisArgs<T> a, c
 // Deterministic reduction of one partial row over nblk tiles by a block of
 // 256 threads (fixed order: two strided accumulators per thread, wave
 // butterflies, then the four waves).  The result is valid in thread 0.
-__device__ __forceinline__ double row_reduce(const double* row, int nblk, bool mx, double* red4) {
+__device__ __forceinline__ double row_reduce(const MP_GLOBAL double* row, int nblk, bool mx,
+                                             double* red4) {
   const int tid = threadIdx.x;
   double v0 = 0.0, v1 = 0.0;
   int b = tid;

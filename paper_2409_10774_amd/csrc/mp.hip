@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(256) k_rows(const double* partials, int nblk, 
   if (ctl && ctl->done) return;
   __shared__ double red[4];
   const int j = blockIdx.x;
-  const double v = row_reduce(partials + (long)j * nblk, nblk, !avg && err_row_is_max(j), red);
+  const double v = row_reduce(glob(partials) + (long)j * nblk, nblk, !avg && err_row_is_max(j), red);
   if (threadIdx.x == 0) tot[j] = v;
 }
 

@@ -92,6 +92,7 @@ def _load():
         "mp_batch_response": (C.c_int, [vp, i32, i32, dp]),
         "mp_batch_get_field": (C.c_int, [vp, i32, i32, dp]),
         "mp_batch_release": (C.c_int, [vp, i32]),
+        "mp_batch_set_fixed_iterations": (C.c_int, [vp, i32, i32]),
         "mp_batch_schedule": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]),
         "mp_batch_stats": (C.c_int, [vp, C.POINTER(i64), C.POINTER(C.c_size_t), C.POINTER(i32)]),
         "mp_batch_destroy": (None, [vp]),
@@ -390,6 +391,9 @@ class Batch:
         out = np.empty(count, np.float64)
         check(lib.mp_batch_get_field(self.handle, int(rid), FIELDS[name], _dp(out)))
         return out.reshape(shape) if count == nvox else out.reshape((9,) + shape)
+
+    def set_fixed_iterations(self, rid, n):
+        check(lib.mp_batch_set_fixed_iterations(self.handle, int(rid), int(n)))
 
     def release(self, rid):
         check(lib.mp_batch_release(self.handle, int(rid)))

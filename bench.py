@@ -173,20 +173,20 @@ def run_serve(args, torch, mp, W):
                  iters_per_launch=args.iters_per_launch, autotune=True)
     print(f"# closed loop: {n} requests at t = 0", file=sys.stderr, flush=True)
     zero = np.zeros(n)
-    ta, td, st, it = mp.serve_batched(B, mp.Requests(items(zero), "mixed"))
+    ta, td, st, it = mp.serve_batched(B, mp.Requests(items(zero), "mixed"), progress_s=20.0)
     makespan = float(td.max())
     sat = n / makespan
     rate = 0.8 * sat
     gaps = np.random.default_rng(4).exponential(1.0 / rate, size=n)
     arr = np.cumsum(gaps) - gaps[0]
     print(f"# saturation {sat:.3f} req/s; open loop at {rate:.3f} req/s", file=sys.stderr, flush=True)
-    ta2, td2, st2, it2 = mp.serve_batched(B, mp.Requests(items(arr), "mixed"))
+    ta2, td2, st2, it2 = mp.serve_batched(B, mp.Requests(items(arr), "mixed"), progress_s=20.0)
     B.close()
     del B
     torch.cuda.empty_cache()
     print("# sequential fp64 on the same trace", file=sys.stderr, flush=True)
     ws = torch.empty(arena, dtype=torch.uint8, device="cuda:0")
-    ts3, td3, st3, it3 = mp.serve_sequential(mp.Requests(items(arr), "fp64"), ws)
+    ts3, td3, st3, it3 = mp.serve_sequential(mp.Requests(items(arr), "fp64"), ws, progress_s=20.0)
     vox = np.array([w.phase_map.size for w in wls])
     return {
         "metric": "requests/s", "value": n / float(td2.max()), "unit": "requests/s", "n_gpus": 1,

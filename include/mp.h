@@ -294,16 +294,21 @@ typedef struct {
  * max_bypass times); resident RVEs keep their state across launches;
  * finished ones are retired after every graph launch, which frees their
  * region for the queue.  Requests are solved in the batch's precision.
- * Per request: t_admit, t_done (seconds), status, loop iterations. */
+ * Per request: t_admit, t_done (seconds), status, loop iterations.  With
+ * progress_s > 0 a progress line goes to stderr every progress_s seconds. */
 mp_status mp_serve_batched(mp_batch batch, int32_t n, const mp_request* req, int32_t max_bypass,
-                           double* t_admit, double* t_done, int32_t* status, int64_t* iters);
+                           double progress_s, double* t_admit, double* t_done, int32_t* status,
+                           int64_t* iters);
 
 /* The same requests served one at a time in arrival order with FP64 plans
  * (mp_plan_create / mp_solve_load_path / mp_plan_destroy) on a workspace of
- * `bytes`.  Per request: t_start, t_done (seconds), status, iterations. */
+ * `bytes`.  Per request: t_start, t_done (seconds), status, iterations.
+ * With progress_s > 0 a line goes to stderr after every request (and
+ * while waiting, at least every progress_s seconds the call returns to its
+ * clock). */
 mp_status mp_serve_sequential(int32_t n, const mp_request* req, void* dev_workspace, size_t bytes,
-                              void* hip_stream, double* t_start, double* t_done, int32_t* status,
-                              int64_t* iters);
+                              void* hip_stream, double progress_s, double* t_start, double* t_done,
+                              int32_t* status, int64_t* iters);
 
 #ifdef __cplusplus
 }

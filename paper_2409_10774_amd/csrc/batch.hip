@@ -12,6 +12,7 @@
 #include "host.hpp"
 
 #include <chrono>
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -916,7 +917,8 @@ void mp_batch_destroy(mp_batch B) {
 // serving loops
 // ---------------------------------------------------------------------------
 mp_status mp_serve_batched(mp_batch B, int32_t n, const mp_request* req, int32_t max_bypass,
-                           double* t_admit, double* t_done, int32_t* status, int64_t* iters) {
+                           double progress_s, double* t_admit, double* t_done, int32_t* status,
+                           int64_t* iters) {
   if (!B || n < 0 || (n > 0 && (!req || !t_admit || !t_done || !status || !iters)))
     return fail(MP_E_INVALID, "bad argument");
   for (int i = 1; i < n; ++i)
@@ -926,6 +928,7 @@ mp_status mp_serve_batched(mp_batch B, int32_t n, const mp_request* req, int32_t
   std::map<int32_t, int> running;         // RVE id -> request
   int next = 0, finished = 0, head_skips = 0;
   const double t0 = now_s();
+  double last_note = t0;
   for (int i = 0; i < n; ++i) {
     t_admit[i] = t_done[i] = -1.0;
     status[i] = MP_OK;
@@ -934,6 +937,12 @@ mp_status mp_serve_batched(mp_batch B, int32_t n, const mp_request* req, int32_t
   while (finished < n) {
     const double t = now_s() - t0;
     while (next < n && req[next].arrival <= t) queue.push_back(next++);
+    if (progress_s > 0 && now_s() - last_note >= progress_s) {
+      last_note = now_s();
+      std::fprintf(stderr, "# serve t=%.1f s: %d done, %d running, %d queued, %d not arrived\n", t,
+                   finished, int(running.size()), int(queue.size()), n - next);
+      std::fflush(stderr);
+    }
     // admission by footprint, arrival order; later requests may pass a head
     // that does not fit until the head has been passed max_bypass times
     for (size_t k = 0; k < queue.size();) {
@@ -962,7 +971,8 @@ mp_status mp_serve_batched(mp_batch B, int32_t n, const mp_request* req, int32_t
     }
     if (running.empty()) {
       if (next < n) {
-        const double wait = req[next].arrival - (now_s() - t0);
+        double wait = req[next].arrival - (now_s() - t0);
+        if (progress_s > 0) wait = std::min(wait, progress_s);
         if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
       } else if (!queue.empty()) {
         return fail(MP_E_NOMEM, "a request does not fit in the empty arena");
@@ -996,16 +1006,21 @@ mp_status mp_serve_batched(mp_batch B, int32_t n, const mp_request* req, int32_t
 }
 
 mp_status mp_serve_sequential(int32_t n, const mp_request* req, void* dev_workspace, size_t bytes,
-                              void* hip_stream, double* t_start, double* t_done, int32_t* status,
-                              int64_t* iters) {
+                              void* hip_stream, double progress_s, double* t_start, double* t_done,
+                              int32_t* status, int64_t* iters) {
   if (n < 0 || (n > 0 && (!req || !t_start || !t_done || !status || !iters)))
     return fail(MP_E_INVALID, "bad argument");
   for (int i = 1; i < n; ++i)
     if (req[i].arrival < req[i - 1].arrival) return fail(MP_E_INVALID, "arrivals must be sorted");
   const double t0 = now_s();
+  double last_note = t0;
   for (int i = 0; i < n; ++i) {
-    const double wait = req[i].arrival - (now_s() - t0);
-    if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+    for (;;) {   // wait for the arrival (in slices when reporting progress)
+      double wait = req[i].arrival - (now_s() - t0);
+      if (wait <= 0) break;
+      if (progress_s > 0) wait = std::min(wait, progress_s);
+      std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+    }
     t_start[i] = now_s() - t0;
     mp_problem p = *req[i].prob;
     p.precision = MP_FP64;
@@ -1015,13 +1030,28 @@ mp_status mp_serve_sequential(int32_t n, const mp_request* req, void* dev_worksp
     mp_plan P = nullptr;
     if (st == MP_OK) st = mp_plan_create(&p, dev_workspace, bytes, hip_stream, &P);
     std::vector<int32_t> it(std::max(1, req[i].n_steps), 0);
-    if (st == MP_OK) st = mp_solve_load_path(P, req[i].n_steps, req[i].times, req[i].E, req[i].Gam, it.data());
+    // one step per call (the plan continues from its committed state), so
+    // progress can be reported between steps
+    for (int k = 0; st == MP_OK && k < req[i].n_steps; ++k) {
+      st = mp_solve_load_path(P, 1, req[i].times + k, req[i].E + 9 * k, req[i].Gam + 9 * k, &it[k]);
+      if (progress_s > 0 && now_s() - last_note >= progress_s) {
+        last_note = now_s();
+        std::fprintf(stderr, "# sequential t=%.1f s: request %d of %d, step %d of %d\n", last_note - t0,
+                     i + 1, n, k + 1, req[i].n_steps);
+        std::fflush(stderr);
+      }
+    }
     if (P) mp_plan_destroy(P);
     long tot = 0;
     for (int32_t v : it) tot += v;
     iters[i] = tot;
     status[i] = st;
     t_done[i] = now_s() - t0;
+    if (progress_s > 0) {
+      std::fprintf(stderr, "# sequential t=%.1f s: request %d of %d done (%ld iterations)\n",
+                   t_done[i], i + 1, n, tot);
+      std::fflush(stderr);
+    }
     if (st == MP_E_DEVICE) return st;
   }
   return MP_OK;

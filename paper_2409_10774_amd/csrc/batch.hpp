@@ -77,11 +77,6 @@ __device__ __forceinline__ int fresh_tid() {
 // work counter serialises across the chip's L2 domains.
 // x pass of one shape class: ITER over the RUN list, or TRANS over the
 // TRANS list (separate kernels, so each keeps its own register budget)
-// The ITER pass is held to the occupancy of the single-RVE x pass (3 waves
-// per SIMD in FP64, 4 in FP32).
-template <class T, int MODE>
-constexpr int x_min_waves() { return MODE != X_ITER ? 1 : sizeof(T) == 8 ? 3 : 4; }
-
 template <class T, int MODE, int N0>
 __global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_batch_x(const Rve<T>* __restrict__ rv,
                                                               const Lists* __restrict__ ls, int cls,
@@ -89,14 +84,18 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_
   using X = XShape<N0>;
   __shared__ cx<T> lds[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
+  __shared__ cx<T> twl[N0];
   const int n = MODE == X_ITER ? ls->ns[cls] : ls->nt[cls];
   const int* list = MODE == X_ITER ? ls->s[cls] : ls->t[cls];
   const int total = n * tiles;
+  // every RVE of a class has the same twiddles: load them once per block
+  if (int(blockIdx.x) < total)
+    load_twiddles<T, N0, X::NTHR>(twl, glob(rv[list[blockIdx.x / tiles]].x.tw), threadIdx.x);
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int slot = list[w / tiles];
     const int tile = w % tiles;
     __syncthreads();   // the previous item is done with LDS
-    xpass_tile<T, MODE, N0>(rv[slot].x, tile, tiles, lds, red, fresh_tid());
+    xpass_tile<T, MODE, N0>(rv[slot].x, tile, tiles, lds, red, twl, fresh_tid());
   }
 }
 
@@ -108,14 +107,21 @@ __global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_batch_axis(const Rve<
                                                                       int cls, int gx, int gy) {
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  __shared__ cx<T> twl[L];
   const int tiles = gx * gy;
   const int total = ls->ns[cls] * tiles;
+  // every RVE of a class has the same twiddles: load them once per block
+  if (int(blockIdx.x) < total) {
+    const int s0 = ls->s[cls][blockIdx.x / tiles];
+    load_twiddles<T, L, AShape<L, TX>::NTHR>(
+        twl, glob((MODE == Y_FWD || MODE == Y_INV) ? rv[s0].y.tw : rv[s0].z.tw), threadIdx.x);
+  }
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int slot = ls->s[cls][w / tiles];
     const int t = w % tiles;
     __syncthreads();
     const AxisArgs<T>& a = (MODE == Y_FWD || MODE == Y_INV) ? rv[slot].y : rv[slot].z;
-    axis_tile<T, MODE, L, TX>(a, t % gx, t / gx, lds, fresh_tid());
+    axis_tile<T, MODE, L, TX>(a, t % gx, t / gx, lds, twl, fresh_tid());
   }
 }
 

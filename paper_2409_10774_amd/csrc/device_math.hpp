@@ -62,6 +62,13 @@ __device__ __forceinline__ void gstore(MP_GLOBAL cx<T>* p, cx<T> v) {
   w.y = v.im;
   *(MP_GLOBAL typename Vec2<T>::type*)p = w;
 }
+// copy an N-entry twiddle table from global memory into LDS (visible after
+// the caller's next barrier)
+template <class T, int N, int NTHR>
+__device__ __forceinline__ void load_twiddles(cx<T>* twl, const MP_GLOBAL cx<T>* tw, int tid) {
+  for (int i = tid; i < N; i += NTHR) twl[i] = gload(tw + i);
+}
+
 template <class S>
 __device__ __forceinline__ S gread(const MP_GLOBAL S* p) {
   static_assert(sizeof(S) % 8 == 0, "record of 8-byte words");
@@ -169,10 +176,11 @@ struct Dft<T, 3, INV> {
 //   points (i - k) R + k + s P.  Every thread gathers all its butterflies
 //   into registers, the block barriers, then scatters, so one buffer is
 //   enough.  Radices: 8 while it divides, then 4, 2, 3.
-//   tw: N-entry table exp(-2 pi i m / N).  Unnormalised in both directions.
+//   tw: N-entry table exp(-2 pi i m / N), held in LDS.  Unnormalised in both
+//   directions.
 // ---------------------------------------------------------------------------
 template <class T, int R, bool INV, int N, int P, int NB, int PS, int BS, bool BFAST, int NTHR>
-__device__ __forceinline__ void stage_ct(cx<T>* buf, const MP_GLOBAL cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void stage_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
   constexpr int NBF = N / R;
   constexpr int TOTAL = NBF * NB;
   constexpr int MB = (TOTAL + NTHR - 1) / NTHR;
@@ -200,7 +208,7 @@ __device__ __forceinline__ void stage_ct(cx<T>* buf, const MP_GLOBAL cx<T>* __re
       if (P > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cx<T> t = gload(tw + r * k * TWS);
+          cx<T> t = tw[r * k * TWS];
           if (INV) t.im = -t.im;
           u[j][r] = cmul(u[j][r], t);
         }
@@ -220,7 +228,7 @@ struct NextRadix {
 };
 
 template <class T, bool INV, int N, int P, int NB, int PS, int BS, bool BFAST, int NTHR>
-__device__ __forceinline__ void fft_ct(cx<T>* buf, const MP_GLOBAL cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_ct(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
   if constexpr (P < N) {
     constexpr int R = NextRadix<N / P>::value;
     static_assert((N / P) % R == 0, "size must be a product of 2s and 3s");

@@ -33,7 +33,7 @@ namespace mp {
 constexpr int kLev = 15;          // per-level error partials
 constexpr int kNPart = 2 * kLev;  // error partial rows of an ITER x pass
 constexpr int kNAvg = 40;         // step-average rows of a TRANS x pass
-constexpr int kRed = 20;          // per-wave LDS reduction slots
+constexpr int kRed = 32;          // per-wave LDS reduction slots
 
 struct Ctl {
   int done;       // 0 running, 1 converged / fixed count reached, 2 max_iter, 3 diverged,
@@ -88,6 +88,39 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 // NaN-propagating max (a non-finite field must not look converged)
 __device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// Deterministic reduce-scatter of K values (K a power of two, 2..16) over a
+// 64-lane wavefront.  At each exchange (lane distance 32, 16, ...) a lane
+// keeps one half of its remaining values and adds in its partner's copies of
+// that half; the one value left is then completed over the lanes that share
+// it.  Value j is a NaN-propagating maximum when bit j of maxmask is set,
+// else a sum.  The first lane of each group writes its value to out[index].
+// 16 values take 34 cross-lane moves instead of 6 per value.
+template <int K>
+__device__ __forceinline__ void wave_reduce(double (&v)[K], unsigned maxmask, int lane, double* out) {
+  static_assert(K >= 2 && K <= 16 && (K & (K - 1)) == 0, "K = 2, 4, 8, 16");
+  int base = 0;
+#pragma unroll
+  for (int o = 32, k = K / 2; k >= 1; o >>= 1, k >>= 1) {
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < k; ++i) {
+      const double send = up ? v[i] : v[i + k];
+      const double keep = up ? v[i + k] : v[i];
+      const double recv = __shfl_xor(send, o, 64);
+      const int j = base + (up ? k : 0) + i;
+      v[i] = ((maxmask >> j) & 1u) ? nmax(keep, recv) : keep + recv;
+    }
+    if (up) base += k;
+  }
+  const bool mx = (maxmask >> base) & 1u;
+#pragma unroll
+  for (int o = 32 / K; o > 0; o >>= 1) {
+    const double recv = __shfl_xor(v[0], o, 64);
+    v[0] = mx ? nmax(v[0], recv) : v[0] + recv;
+  }
+  if ((lane & (64 / K - 1)) == 0) out[base] = v[0];
+}
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = nmax(v, __shfl_xor(v, o, 64));
@@ -136,11 +169,11 @@ __device__ __forceinline__ int avg_row(int L, int j) {
 // independent, which halves each lane's live state, and the level is uniform
 // over each wavefront.  Each lane prefetches its old strain, history base and
 // p_n / q_n before the transforms so the loads overlap them.
-//   lds: NPK * N0 complex;  red: NTHR / 64 rows of kRed doubles;  tid: the
-//   thread index.
+//   lds: NPK * N0 complex;  red: NTHR / 64 rows of kRed doubles;  tw: the
+//   N0-entry twiddle table in LDS;  tid: the thread index.
 template <class T, int MODE, int N0>
 __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int ntiles, cx<T>* lds,
-                                           double (*red)[kRed], int tid) {
+                                           double (*red)[kRed], const cx<T>* tw, int tid) {
   using X = XShape<N0>;
   constexpr int ROWS = X::ROWS, VPB = X::VPB, VPAD = X::VPAD, NTHR = X::NTHR, NH = X::NH;
   constexpr int NPK = X::NPK;
@@ -154,7 +187,6 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
   const int gi = own ? int((row0 + vr) * N0 + vx) : 0;
   const long nv = a.nvox;
   MP_GLOBAL cx<T>* const S = glob(a.S);
-  const MP_GLOBAL cx<T>* const tw = glob(a.tw);
   MP_GLOBAL T* const Elv = glob(a.E) + (long)lvl * 9 * nv;
   MP_GLOBAL T* const Eprev = glob(a.Eprev);
   MP_GLOBAL T* const Blv = glob(a.base) + (long)lvl * 9 * nv;
@@ -209,14 +241,9 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
     return;
   }
 
-  // Per-wave partial sums (or maxima) reduced as soon as they exist (fixed
-  // butterfly order), then over the waves of a level in order.
+  // Per-wave partial sums (or maxima) by a reduce-scatter over the
+  // wavefront (fixed order), then over the waves of a level in order.
   const int lane = tid & 63, wv = tid >> 6;
-  auto wave_put = [&](int j, double x, bool mx) {
-    const double y = own ? x : 0.0;
-    const double z = mx ? wave_max(y) : wave_sum(y);
-    if (lane == 0) red[wv][j] = z;
-  };
 
   // this lane's half of the phase record
   MacroC ct;
@@ -257,12 +284,17 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
       pq[lvl * nv + gi] = pc;
       glob(a.out_pq)[lvl * nv + gi] = pc;
     }
+    {
+      double v[16];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) wave_put(c, double(tc[c]), false);
+      for (int c = 0; c < 9; ++c) v[c] = own ? double(tc[c]) : 0.0;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) wave_put(9 + c, double(eo[c]), false);
-    wave_put(18, pc, false);
-    wave_put(19, eq, false);
+      for (int c = 0; c < 7; ++c) v[9 + c] = own ? double(eo[c]) : 0.0;
+      wave_reduce<16>(v, 0u, lane, red[wv]);
+      double w[4] = {own ? double(eo[7]) : 0.0, own ? double(eo[8]) : 0.0, own ? pc : 0.0,
+                     own ? eq : 0.0};
+      wave_reduce<4>(w, 0u, lane, red[wv] + 16);
+    }
     __syncthreads();
     if (tid < kNAvg) {
       const int L = tid / 20, j = tid % 20;
@@ -336,13 +368,22 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
           sa += double(e[c]) * double(e[c]);
           sb += double(t[c]) * double(t[c]);
         }
-#pragma unroll
-        for (int c = 0; c < 9; ++c) wave_put(6 + c, double(t[c]), false);
-        wave_put(4, sa, false);
-        wave_put(5, sb, false);
         da = sqrt(da);
-        wave_put(0, da, true);
-        wave_put(2, da, false);
+        {
+          // slots 0 (max) and 2 (sum) |da|, 4 |a|^2, 5 |b|^2, 6..14 b;
+          // 1 and 3 (|db|) follow below into slots 16, 17
+          double v[16];
+          v[0] = own ? da : 0.0;
+          v[1] = 0.0;
+          v[2] = v[0];
+          v[3] = 0.0;
+          v[4] = own ? sa : 0.0;
+          v[5] = own ? sb : 0.0;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) v[6 + c] = own ? double(t[c]) : 0.0;
+          v[15] = 0.0;
+          wave_reduce<16>(v, 0x1u, lane, red[wv]);
+        }
         // the old iterate's stresses, recomputed from the old strain (Alg. 1)
         double db = 0;
         if (own) {
@@ -359,15 +400,18 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
           }
         }
         db = sqrt(db);
-        wave_put(1, db, true);
-        wave_put(3, db, false);
+        {
+          double w[2] = {own ? db : 0.0, own ? db : 0.0};
+          wave_reduce<2>(w, 0x1u, lane, red[wv] + 16);
+        }
         __syncthreads();
         if (tid < kNPart) {
           const int L = tid / kLev, j = tid % kLev;
+          const int jj = j == 1 ? 16 : j == 3 ? 17 : j;
           // waves [0, VPAD/64) hold level 0, the rest level 1
           const int w0 = L * (VPAD / 64), w1 = w0 + VPAD / 64;
-          double y = red[w0][j];
-          for (int w = w0 + 1; w < w1; ++w) y = (j < 2) ? nmax(y, red[w][j]) : y + red[w][j];
+          double y = red[w0][jj];
+          for (int w = w0 + 1; w < w1; ++w) y = (j < 2) ? nmax(y, red[w][jj]) : y + red[w][jj];
           partials[(long)tid * ntiles + tile] = y;
         }
       }
@@ -389,15 +433,23 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
   }
 }
 
+// The ITER pass is held to 3 waves per SIMD in FP64 and 4 in FP32 (at most
+// 168 / 128 VGPRs).
+template <class T, int MODE>
+constexpr int x_min_waves() { return MODE != X_ITER ? 1 : sizeof(T) == 8 ? 3 : 4; }
+
 // one tile per block; every kernel of the step loop returns at once when the
 // step's control block says the loop is finished
 template <class T, int MODE, int N0>
-__global__ void __launch_bounds__(XShape<N0>::NTHR) k_xpass(XArgs<T> a, const Ctl* ctl) {
+__global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_xpass(XArgs<T> a,
+                                                                                 const Ctl* ctl) {
   using X = XShape<N0>;
   if (ctl && ctl->done) return;
   __shared__ cx<T> lds[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
-  xpass_tile<T, MODE, N0>(a, blockIdx.x, gridDim.x, lds, red, threadIdx.x);
+  __shared__ cx<T> twl[N0];
+  load_twiddles<T, N0, X::NTHR>(twl, glob(a.tw), threadIdx.x);
+  xpass_tile<T, MODE, N0>(a, blockIdx.x, gridDim.x, lds, red, twl, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,13 +480,14 @@ struct AShape {
   static constexpr size_t LDS = size_t(PTS);   // complex values
 };
 
-// tile (bx, by): kx in [bx TX, bx TX + TX), kz = by (y pass) or ky = by (z pass)
+// tile (bx, by): kx in [bx TX, bx TX + TX), kz = by (y pass) or ky = by (z
+// pass); tw: the L-entry twiddle table in LDS
 template <class T, int MODE, int L, int TX>
-__device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, cx<T>* lds, int tid) {
+__device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, cx<T>* lds,
+                                          const cx<T>* tw, int tid) {
   using A = AShape<L, TX>;
   constexpr int NB = A::NB, PTS = A::PTS, NTHR = A::NTHR;
   MP_GLOBAL cx<T>* g = glob(a.S) + (long)by * a.ostride + (long)bx * NB;
-  const MP_GLOBAL cx<T>* const tw = glob(a.tw);
   for (int w = tid; w < PTS; w += NTHR) {
     const int i = w / NB, b = w % NB;
     lds[w] = gload(g + i * a.pstride + b);
@@ -486,7 +539,9 @@ template <class T, int MODE, int L, int TX>
 __global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_axis(AxisArgs<T> a, const Ctl* ctl) {
   if (ctl && ctl->done) return;
   extern __shared__ unsigned char smem_raw[];
-  axis_tile<T, MODE, L, TX>(a, blockIdx.x, blockIdx.y, reinterpret_cast<cx<T>*>(smem_raw),
+  __shared__ cx<T> twl[L];
+  load_twiddles<T, L, AShape<L, TX>::NTHR>(twl, glob(a.tw), threadIdx.x);
+  axis_tile<T, MODE, L, TX>(a, blockIdx.x, blockIdx.y, reinterpret_cast<cx<T>*>(smem_raw), twl,
                             threadIdx.x);
 }
 

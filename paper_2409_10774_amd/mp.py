@@ -96,10 +96,10 @@ def _load():
         "mp_batch_schedule": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]),
         "mp_batch_stats": (C.c_int, [vp, C.POINTER(i64), C.POINTER(C.c_size_t), C.POINTER(i32)]),
         "mp_batch_destroy": (None, [vp]),
-        "mp_serve_batched": (C.c_int, [vp, i32, C.POINTER(mp_request), i32, dp, dp, C.POINTER(i32),
-                                       C.POINTER(i64)]),
-        "mp_serve_sequential": (C.c_int, [i32, C.POINTER(mp_request), vp, C.c_size_t, vp, dp, dp,
-                                          C.POINTER(i32), C.POINTER(i64)]),
+        "mp_serve_batched": (C.c_int, [vp, i32, C.POINTER(mp_request), i32, C.c_double, dp, dp,
+                                       C.POINTER(i32), C.POINTER(i64)]),
+        "mp_serve_sequential": (C.c_int, [i32, C.POINTER(mp_request), vp, C.c_size_t, vp, C.c_double,
+                                          dp, dp, C.POINTER(i32), C.POINTER(i64)]),
         "mp_last_error": (C.c_char_p, []),
         "mp_version": (C.c_char_p, []),
     }
@@ -450,23 +450,24 @@ def _serve_out(n):
         (C.c_int64 * max(1, n))()
 
 
-def serve_batched(batch, reqs, max_bypass=16):
+def serve_batched(batch, reqs, max_bypass=16, progress_s=0.0):
     """Continuous batching of a request trace on an empty Batch; returns per
     request (t_admit, t_done, status, iterations) as numpy arrays."""
     a, d, st, it = _serve_out(reqs.n)
-    check(lib.mp_serve_batched(batch.handle, reqs.n, reqs.arr, int(max_bypass), a, d, st, it))
+    check(lib.mp_serve_batched(batch.handle, reqs.n, reqs.arr, int(max_bypass), float(progress_s),
+                               a, d, st, it))
     n = reqs.n
     return np.array(a[:n]), np.array(d[:n]), np.array(st[:n]), np.array(it[:n])
 
 
-def serve_sequential(reqs, workspace, stream=None):
+def serve_sequential(reqs, workspace, stream=None, progress_s=0.0):
     """The trace served one request at a time with FP64 plans on `workspace`
     (a torch uint8 device tensor)."""
     import torch
     s = stream if stream is not None else torch.cuda.current_stream(workspace.device)
     a, d, st, it = _serve_out(reqs.n)
     check(lib.mp_serve_sequential(reqs.n, reqs.arr, _ptr(workspace), workspace.numel(),
-                                  C.c_void_p(s.cuda_stream), a, d, st, it))
+                                  C.c_void_p(s.cuda_stream), float(progress_s), a, d, st, it))
     n = reqs.n
     return np.array(a[:n]), np.array(d[:n]), np.array(st[:n]), np.array(it[:n])
 

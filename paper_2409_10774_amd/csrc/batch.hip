@@ -218,7 +218,10 @@ struct BEng {
     const Lists* lsp = B->ls;
     int cls = c, tiles = C.g.xblocks;
     void* args[] = {&rvp, &lsp, &cls, &tiles};
-    return launch(fn, C.xgrid, nthr, 0, s, args);
+    // transitions are rare (once per step of an RVE): a grid that fills the
+    // chip about once, so that an iteration without any costs little
+    const int grid = mode == X_ITER ? C.xgrid : std::min(C.xgrid, 4 * B->cus);
+    return launch(fn, grid, nthr, 0, s, args);
   }
 
   static hipError_t ctl(mp_batch B, int update, hipStream_t s) {
@@ -239,7 +242,7 @@ struct BEng {
       if ((e = xpass(B, c, X_ITER, s)) != hipSuccess) return e;
       if ((e = xpass(B, c, X_TRANS, s)) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_batch_rows<T>), dim3(8 * B->cus), dim3(256), 0, s, rv(B), B->ls,
+    hipLaunchKernelGGL((k_batch_rows<T>), dim3(4 * B->cus), dim3(256), 0, s, rv(B), B->ls,
                        int(B->cls.size()));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return ctl(B, 1, s);

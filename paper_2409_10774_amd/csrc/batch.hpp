@@ -116,7 +116,12 @@ __global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_batch_axis(const Rve<
     load_twiddles<T, L, AShape<L, TX>::NTHR>(
         twl, glob((MODE == Y_FWD || MODE == Y_INV) ? rv[s0].y.tw : rv[s0].z.tw), threadIdx.x);
   }
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  // round r covers items [r G, r G + n_r); within a round the items are
+  // handed out XCD-aware (xcd_tile)
+  for (int r0 = 0; r0 < total; r0 += gridDim.x) {
+    const int nr = min(int(gridDim.x), total - r0);
+    if (int(blockIdx.x) >= nr) break;
+    const int w = r0 + xcd_tile(blockIdx.x, nr);
     const int slot = ls->s[cls][w / tiles];
     const int t = w % tiles;
     __syncthreads();
@@ -166,7 +171,6 @@ __global__ void __launch_bounds__(256) k_batch_rows(Rve<T>* __restrict__ rv,
 // slot i.
 template <class T>
 __global__ void __launch_bounds__(kMaxSlots) k_batch_ctl(Rve<T>* rv, Lists* ls, int ncls, int update) {
-  __shared__ int st[kMaxSlots], cl[kMaxSlots];
   const int i = threadIdx.x;
   Rve<T>& R = rv[i];
   int state = R.state;
@@ -212,26 +216,38 @@ __global__ void __launch_bounds__(kMaxSlots) k_batch_ctl(Rve<T>* rv, Lists* ls, 
     }
   }
   if (update) R.state = state;
-  st[i] = state;
-  cl[i] = R.cls;
   ls->st[i] = state;
-  __syncthreads();
-  if (i < ncls) {
-    int ns = 0, nt = 0;
-    for (int k = 0; k < kMaxSlots; ++k) {
-      if (cl[k] != i) continue;
-      if (st[k] == RV_RUN)
-        ls->s[i][ns++] = k;
-      else if (st[k] == RV_TRANS)
-        ls->t[i][nt++] = k;
+  // work lists in slot order: a wave ballot per class, then the waves' counts
+  // in order (prefix compaction)
+  __shared__ int wcnt[2][kMaxSlots / 64];
+  const int lane = i & 63, wv = i >> 6;
+  const int cls = R.cls;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int c = 0; c < ncls; ++c) {
+    const bool fs = cls == c && state == RV_RUN;
+    const bool ft = cls == c && state == RV_TRANS;
+    const unsigned long long bs = __ballot(fs), bt = __ballot(ft);
+    if (lane == 0) {
+      wcnt[0][wv] = __popcll(bs);
+      wcnt[1][wv] = __popcll(bt);
     }
-    ls->ns[i] = ns;
-    ls->nt[i] = nt;
+    __syncthreads();
+    int os = 0, ot = 0;
+    for (int w = 0; w < wv; ++w) {
+      os += wcnt[0][w];
+      ot += wcnt[1][w];
+    }
+    if (fs) ls->s[c][os + __popcll(bs & below)] = i;
+    if (ft) ls->t[c][ot + __popcll(bt & below)] = i;
+    if (i == kMaxSlots - 1) {
+      ls->ns[c] = os + __popcll(bs);
+      ls->nt[c] = ot + __popcll(bt);
+    }
+    __syncthreads();
   }
-  if (i == kMaxSlots - 1) {
-    int a = 0;
-    for (int k = 0; k < kMaxSlots; ++k) a += (st[k] == RV_RUN || st[k] == RV_TRANS);
-    ls->active = a;
+  const int active = __syncthreads_count(state == RV_RUN || state == RV_TRANS);
+  if (i == 0) {
+    ls->active = active;
     if (update) ls->launches += 1;
   }
 }

@@ -535,13 +535,25 @@ __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, 
   }
 }
 
+// XCD-aware tile order.  The chip hands consecutive blocks to its 8 XCDs in
+// turn, and each XCD has its own L2.  A tile's runs (TX * 18 complex values
+// per point) need not end on a cache line, so neighbouring tiles share lines:
+// giving each XCD a contiguous range of tiles makes the shared lines hit in
+// one L2 instead of being fetched once per XCD.  Maps block b of n to a tile.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int per = n / kXcd;
+  return b < per * kXcd ? (b % kXcd) * per + b / kXcd : b;
+}
+
 template <class T, int MODE, int L, int TX>
 __global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_axis(AxisArgs<T> a, const Ctl* ctl) {
   if (ctl && ctl->done) return;
   extern __shared__ unsigned char smem_raw[];
   __shared__ cx<T> twl[L];
   load_twiddles<T, L, AShape<L, TX>::NTHR>(twl, glob(a.tw), threadIdx.x);
-  axis_tile<T, MODE, L, TX>(a, blockIdx.x, blockIdx.y, reinterpret_cast<cx<T>*>(smem_raw), twl,
+  const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  axis_tile<T, MODE, L, TX>(a, t % gridDim.x, t / gridDim.x, reinterpret_cast<cx<T>*>(smem_raw), twl,
                             threadIdx.x);
 }
 

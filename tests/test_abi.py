@@ -96,3 +96,44 @@ def test_mixed_workspace_is_about_half():
     a = mp.mp_plan_workspace_size(base_problem())
     b = mp.mp_plan_workspace_size(base_problem(precision="mixed"))
     assert 0.45 * a < b < 0.7 * a
+
+
+def test_batch_footprint_and_validation():
+    """Batch admission sizing runs on the host: the footprint covers the
+    plan layout plus the load path and step records, grows with the step
+    count, halves its bulk part in the mixed form, and rejects bad input."""
+    from paper_2409_10774_amd import mp, workloads as W
+    wl = W.single_sphere_16()
+    prob = mp.make_problem(wl.phase_map, wl.phases, precision="fp64")
+    cfg64 = mp.batch_config([(16, 16, 16)], precision="fp64")
+    cfg32 = mp.batch_config([(16, 16, 16)], precision="mixed")
+
+    def fp(cfg, p, n_steps):
+        n = mp.C.c_size_t()
+        st = mp.lib.mp_batch_footprint(mp.C.byref(cfg), mp.C.byref(p), n_steps, mp.C.byref(n))
+        return st, n.value
+
+    st, f10 = fp(cfg64, prob, 10)
+    assert st == mp.MP_OK
+    assert f10 >= mp.mp_plan_workspace_size(prob)
+    st, f100 = fp(cfg64, prob, 100)
+    # 90 more steps: 19 more path doubles and 48 more record doubles each
+    assert f100 - f10 >= 90 * (19 + 48) * 8 - 512
+    pmix = mp.make_problem(wl.phase_map, wl.phases, precision="mixed")
+    st, fmix = fp(cfg32, pmix, 10)
+    assert st == mp.MP_OK and fmix < 0.6 * f10
+    assert fp(cfg64, prob, 0)[0] == mp.MP_E_INVALID
+    bad = mp.make_problem(wl.phase_map, wl.phases, tol=0.0)
+    assert fp(cfg64, bad, 10)[0] == mp.MP_E_INVALID
+
+
+def test_batch_create_rejects_bad_config():
+    """Configuration errors are found before any device work."""
+    from paper_2409_10774_amd import mp
+    h = mp.C.c_void_p()
+    for kw, shapes in [(dict(max_rves=0), [(16, 16, 16)]), (dict(max_rves=513), [(16, 16, 16)]),
+                       (dict(iters_per_launch=0), [(16, 16, 16)]), ({}, [(16, 16, 17)]),
+                       ({}, [(16, 16, 16), (16, 16, 16)]), ({}, [])]:
+        cfg = mp.batch_config(shapes, **kw)
+        st = mp.lib.mp_batch_create(mp.C.byref(cfg), mp.C.c_void_p(256), 1 << 30, None, mp.C.byref(h))
+        assert st == mp.MP_E_INVALID, (kw, shapes, st)

@@ -38,8 +38,10 @@ def bytes_per_voxel(w):
 # WRITE_SIZE (scaled by a 1 GiB copy calibration: x2.000 and x1.000), valid
 # only for the kernel sources they were taken on (SHA-1 of the two headers)
 MEASURED_TRAFFIC = {
-    "spheres128_fp64": {"kernel": "x_pass", "bytes": (941.9 + 619.7) * 1e6,
-                        "src_sha1": "7007ac635df7b0fa8fe57426dd5e000c8b2de9ee"},
+    "spheres128_fp64": {"kernel": "x_pass", "bytes": (942.0 + 619.7) * 1e6,
+                        "src_sha1": "123770461c133a5dc82d07f86e4a6612fdbd9290"},
+    "spheres256_mixed": {"kernel": "x_pass", "bytes": (3909.4 + 2478.9) * 1e6,
+                         "src_sha1": "123770461c133a5dc82d07f86e4a6612fdbd9290"},
 }
 
 

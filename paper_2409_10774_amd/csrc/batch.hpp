@@ -83,6 +83,7 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_
                                                               int tiles) {
   using X = XShape<N0>;
   __shared__ cx<T> lds[X::NPK * N0];
+  __shared__ cx<T> lds2[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
   __shared__ cx<T> twl[N0];
   const int n = MODE == X_ITER ? ls->ns[cls] : ls->nt[cls];
@@ -95,7 +96,7 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_
     const int slot = list[w / tiles];
     const int tile = w % tiles;
     __syncthreads();   // the previous item is done with LDS
-    xpass_tile<T, MODE, N0>(rv[slot].x, tile, tiles, lds, red, twl, fresh_tid());
+    xpass_tile<T, MODE, N0>(rv[slot].x, tile, tiles, lds, lds2, red, twl, fresh_tid());
   }
 }
 

@@ -237,6 +237,64 @@ __device__ __forceinline__ void fft_ct(cx<T>* buf, const cx<T>* __restrict__ tw,
   }
 }
 
+// Out-of-place variant (ping-pong between two LDS buffers): each stage reads
+// src and writes dst, so one barrier per stage suffices (the in-place stage
+// needs two).  fft_pp_stages<N>() stages; the result ends in `a` when that
+// count is even, else in `b`.  Entry: the data in `a`, visible to the block.
+template <int N, int P = 1>
+constexpr int fft_pp_stages() {
+  if constexpr (P >= N) {
+    return 0;
+  } else {
+    return 1 + fft_pp_stages<N, P * NextRadix<N / P>::value>();
+  }
+}
+
+template <class T, int R, bool INV, int N, int P, int NB, int PS, int BS, bool BFAST, int NTHR>
+__device__ __forceinline__ void stage_pp(const cx<T>* src, cx<T>* dst, const cx<T>* __restrict__ tw,
+                                         int tid) {
+  constexpr int NBF = N / R;
+  constexpr int TOTAL = NBF * NB;
+  constexpr int MB = (TOTAL + NTHR - 1) / NTHR;
+  constexpr int TWS = N / (P * R);
+#pragma unroll
+  for (int j = 0; j < MB; ++j) {
+    const int w = tid + j * NTHR;
+    if (TOTAL % NTHR == 0 || w < TOTAL) {
+      const int b = BFAST ? w % NB : w / NBF;
+      const int i = BFAST ? w / NB : w % NBF;
+      const int k = i % P;
+      cx<T> u[R];
+      const cx<T>* s = src + b * BS + i * PS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[r] = s[r * NBF * PS];
+      if (P > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> t = tw[r * k * TWS];
+          if (INV) t.im = -t.im;
+          u[r] = cmul(u[r], t);
+        }
+      }
+      Dft<T, R, INV>::run(u);
+      cx<T>* d = dst + b * BS + ((i - k) * R + k) * PS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) d[r * P * PS] = u[r];
+    }
+  }
+  __syncthreads();
+}
+
+template <class T, bool INV, int N, int P, int NB, int PS, int BS, bool BFAST, int NTHR>
+__device__ __forceinline__ void fft_pp(cx<T>* a, cx<T>* b, const cx<T>* __restrict__ tw, int tid) {
+  if constexpr (P < N) {
+    constexpr int R = NextRadix<N / P>::value;
+    static_assert((N / P) % R == 0, "size must be a product of 2s and 3s");
+    stage_pp<T, R, INV, N, P, NB, PS, BS, BFAST, NTHR>(a, b, tw, tid);
+    fft_pp<T, INV, N, P * R, NB, PS, BS, BFAST, NTHR>(b, a, tw, tid);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Alg. 1: micropolar radial return at one voxel.
 // ---------------------------------------------------------------------------

@@ -169,15 +169,23 @@ __device__ __forceinline__ int avg_row(int L, int j) {
 // independent, which halves each lane's live state, and the level is uniform
 // over each wavefront.  Each lane prefetches its old strain, history base and
 // p_n / q_n before the transforms so the loads overlap them.
-//   lds: NPK * N0 complex;  red: NTHR / 64 rows of kRed doubles;  tw: the
-//   N0-entry twiddle table in LDS;  tid: the thread index.
+//   lds, lds2: NPK * N0 complex each (the x transforms ping-pong between
+//   them, one barrier per stage);  red: NTHR / 64 rows of kRed doubles;  tw:
+//   the N0-entry twiddle table in LDS;  tid: the thread index.
 template <class T, int MODE, int N0>
 __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int ntiles, cx<T>* lds,
-                                           double (*red)[kRed], const cx<T>* tw, int tid) {
+                                           cx<T>* lds2, double (*red)[kRed], const cx<T>* tw, int tid) {
   using X = XShape<N0>;
   constexpr int ROWS = X::ROWS, VPB = X::VPB, VPAD = X::VPAD, NTHR = X::NTHR, NH = X::NH;
   constexpr int NPK = X::NPK;
-  T* ldr = reinterpret_cast<T*>(lds);
+  // buffer holding the spatial-domain pencils after the inverse transform,
+  // and the buffer holding the spectra after the forward transform
+  constexpr bool ODD = fft_pp_stages<N0>() % 2 == 1;
+  constexpr bool SP2 = (MODE == X_ITER || MODE == X_INV_ONLY) && ODD;
+  cx<T>* const sp = SP2 ? lds2 : lds;
+  cx<T>* const other = SP2 ? lds : lds2;
+  cx<T>* const fq = ODD ? other : sp;
+  T* ldr = reinterpret_cast<T*>(sp);
   const long row0 = tile * ROWS;
   const int lvl = __builtin_amdgcn_readfirstlane(tid >= VPAD ? 1 : 0);
   const int v = tid - lvl * VPAD;
@@ -228,7 +236,7 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
         pen[NH] = cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    fft_ct<T, true, N0, 1, NPK, 1, N0, false, NTHR>(lds, tw, tid);
+    fft_pp<T, true, N0, 1, NPK, 1, N0, false, NTHR>(lds, lds2, tw, tid);
   }
 
   // LDS scalar slot of field c (0..17) of this lane's voxel
@@ -418,12 +426,12 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
     }
   }
   __syncthreads();
-  fft_ct<T, false, N0, 1, NPK, 1, N0, false, NTHR>(lds, tw, tid);
+  fft_pp<T, false, N0, 1, NPK, 1, N0, false, NTHR>(sp, other, tw, tid);
   // unpack: A = (Z(k) + conj Z(-k)) / 2, B = (Z(k) - conj Z(-k)) / (2 i)
   for (int w = tid; w < rows_here * NH * kPencils; w += NTHR) {
     const int r = w / (NH * kPencils), rem = w % (NH * kPencils);
     const int kx = rem / kPencils, q = rem % kPencils;
-    const cx<T>* pen = lds + (r * kPencils + q) * N0;
+    const cx<T>* pen = fq + (r * kPencils + q) * N0;
     const cx<T> zk = pen[kx];
     const cx<T> zm = pen[kx == 0 ? 0 : N0 - kx];
     MP_GLOBAL cx<T>* srow = S + (row0 + r) * (NH * 18) + kx * 18;
@@ -446,10 +454,11 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_
   using X = XShape<N0>;
   if (ctl && ctl->done) return;
   __shared__ cx<T> lds[X::NPK * N0];
+  __shared__ cx<T> lds2[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
   __shared__ cx<T> twl[N0];
   load_twiddles<T, N0, X::NTHR>(twl, glob(a.tw), threadIdx.x);
-  xpass_tile<T, MODE, N0>(a, blockIdx.x, gridDim.x, lds, red, twl, threadIdx.x);
+  xpass_tile<T, MODE, N0>(a, blockIdx.x, gridDim.x, lds, lds2, red, twl, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -216,3 +216,26 @@ def test_serving_loops(mp):
     assert (st2 == mp.MP_OK).all() and (td2 >= ts).all() and (ts >= arrivals - 1e-9).all()
     for i, w in enumerate(wls):
         assert it2[i] == sum(solo(mp, w, "fp64")["iters"])
+
+
+def test_batch_cancel_slot_limit_and_empty(mp):
+    """Releasing an unfinished RVE cancels it without disturbing the others;
+    admission beyond max_rves is refused with MP_E_NOMEM; a batch with
+    nothing resident runs and reports zero active RVEs."""
+    say("case: cancel, slot limit, empty batch")
+    wls = mixed_set(1e-8)[:3]
+    B = mp.Batch(SHAPES, arena_bytes=256 << 20, precision="fp64", max_rves=2, iters_per_launch=4)
+    assert B.run() == 0 and B.drain() == 1
+    a = B.admit(wls[0].phase_map, wls[0].phases, wls[0].times, wls[0].E, wls[0].G, tol=wls[0].tol)
+    b = B.admit(wls[1].phase_map, wls[1].phases, wls[1].times, wls[1].E, wls[1].G, tol=wls[1].tol)
+    rid, st = B.admit(wls[2].phase_map, wls[2].phases, wls[2].times, wls[2].E, wls[2].G, tol=wls[2].tol,
+                      raise_on_error=False)
+    assert rid is None and st == mp.MP_E_NOMEM
+    B.run()
+    assert B.query(a)[0] == mp.MP_RVE_RUNNING
+    B.release(a)                        # cancel mid-path
+    c = B.admit(wls[2].phase_map, wls[2].phases, wls[2].times, wls[2].E, wls[2].G, tol=wls[2].tol)
+    B.drain()
+    assert_same(batched(B, b), solo(mp, wls[1], "fp64"), b)
+    assert_same(batched(B, c), solo(mp, wls[2], "fp64"), c)
+    B.close()

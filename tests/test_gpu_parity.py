@@ -5,8 +5,10 @@ Element-by-element comparisons on the same seeded inputs:
   - the forward half spectrum against numpy's rfftn;
   - one application of the spectral operator (transform, Green operator,
     inverse transform) against the oracle's dense per-frequency solve;
-  - whole load paths (Alg. 2) on small ragged grids and on the 16^3 sphere
-    cell over all 10 steps, with equal per-step iteration counts;
+  - whole load paths (Alg. 2) on small ragged grids (down to 4 x 4 x 6), on
+    the 16^3 sphere cell over all 10 steps and on a cyclic load / unload /
+    reverse path with uneven time steps, with equal per-step iteration
+    counts; an empty load path;
   - the 128^3 random-sphere cell at full size over a fixed iteration schedule.
 Floating-point bar: 1e-10 relative (FP64 path), per field
 rel = max_x |a_gpu - a_ref| / max_x |a_ref|.
@@ -164,7 +166,7 @@ def small_workload(n, seed, contrast=5.0, steps=4, G_end=0.002):
     return W.Workload("small", ph, [mat, inc], times, E, G, tol=1e-8)
 
 
-@pytest.mark.parametrize("n", [(8, 8, 8), (12, 6, 8), (24, 16, 12), (6, 48, 4)])
+@pytest.mark.parametrize("n", [(8, 8, 8), (12, 6, 8), (24, 16, 12), (6, 48, 4), (4, 4, 6)])
 def test_full_path_small_grids(torch, mp, n):
     say(f"case: Alg. 2 small grid n={n}")
     wl = small_workload(n, seed=sum(n))
@@ -230,3 +232,36 @@ def test_continue_across_calls(torch, mp):
     b.solve(wl.times[2:], wl.E[2:], wl.G[2:])
     for k in ("e", "t", "g", "m", "p", "q"):
         assert np.array_equal(a.field(k), b.field(k))
+
+
+def test_empty_load_path(torch, mp):
+    say("case: a load path of zero steps changes nothing")
+    wl = small_workload((8, 8, 8), seed=3, steps=2)
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol)
+    assert plan.solve(wl.times[:1], wl.E[:0], wl.G[:0]) == []
+    assert plan.steps() == 0
+    plan.solve(wl.times, wl.E, wl.G)
+    e = plan.field("e")
+    assert plan.solve(wl.times[-1:], wl.E[:0], wl.G[:0]) == []
+    assert plan.steps() == 2 and np.array_equal(plan.field("e"), e)
+
+
+def test_cyclic_path_uneven_steps(torch, mp):
+    """Load, unload and reverse (E11 0 -> 0.012 -> -0.01 -> 0 with a shear
+    curvature riding along) on uneven time steps: plastic loading, elastic
+    unloading, reverse yield and the Alg. 2 extrapolation ratio at every
+    step, against the oracle."""
+    say("case: cyclic non-monotone path on uneven steps, 8x8x8")
+    base = small_workload((8, 8, 8), seed=21, contrast=4.0, steps=1)
+    amp = np.array([0.004, 0.008, 0.012, 0.006, -0.002, -0.01, -0.004, 0.0])
+    times = np.concatenate([[0.0], np.cumsum([1.0, 0.5, 1.5, 1.0, 2.0, 0.75, 1.25, 1.0])])
+    E = np.zeros((len(amp), 9))
+    E[:, 0] = amp
+    E[:, 5] = E[:, 7] = 0.3 * amp
+    G = np.zeros((len(amp), 9))
+    G[:, 1] = 0.1 * amp
+    wl = W.Workload("cyclic", base.phase_map, base.phases, times, E, G, tol=1e-8)
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol)
+    it, resp = compare_run(mp, plan, wl, len(amp))
+    # the path really unloads and reverses: the mean macro stress changes sign
+    assert resp[:, 0].max() > 0 and resp[:, 0].min() < 0

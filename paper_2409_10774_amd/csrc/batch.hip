@@ -324,9 +324,10 @@ mp_status default_sched(mp_batch B, ClassInfo& C) {
 
 // Autotuner: for each y / z pass of a class, time every tile width in
 // {1, wide / 2, wide} (wide = the largest with TX * L <= 256 dividing n0/2)
-// with the full persistent grid and a quarter of it, on replicas of the
-// class's spectrum (enough replicas for about 2^23 voxels), keep the fastest.  Results are cached
-// per (precision, shape) for the process.
+// with the full persistent grid, a quarter of it and the blocks the chip
+// holds at once, on replicas of the class's spectrum (enough replicas for
+// about 2^23 voxels), keep the fastest.  Results are cached per (precision,
+// shape) for the process.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, std::array<PassSched, 3>> g_tune_cache;
 
@@ -419,11 +420,14 @@ mp_status BEng<T>::setup_class(mp_batch B, ClassInfo& C) {
                   : mode == Y_INV ? axis_kernel<T, Y_INV>(L, tx, &fn, &nthr, &shm)
                                   : axis_kernel<T, Z_GREEN>(L, tx, &fn, &nthr, &shm);
         if (!ok) continue;
-        int full;
+        int full, per_cu = 0;
         HIP_TRY(occupancy(fn, nthr, shm, B->cus, &full));
-        for (int half = 0; half < 2; ++half) {
-          const int grid = half ? std::max(B->cus, full / 4) : full;
-          if (half && grid == full) continue;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nthr, shm));
+        // the full grid, a quarter of it, and the blocks the chip holds at once
+        const int grids[3] = {full, std::max(B->cus, full / 4), std::max(1, per_cu) * B->cus};
+        for (int gi = 0; gi < 3; ++gi) {
+          const int grid = grids[gi];
+          if ((gi > 0 && grid == grids[0]) || (gi > 1 && grid == grids[1])) continue;
           HIP_TRY(axis(B, ci, p, trv, tls, tx, grid, B->stream));   // warm-up
           float ms = 0.f;
           for (int rep = 0; rep < 3; ++rep) {

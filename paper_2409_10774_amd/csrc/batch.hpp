@@ -60,15 +60,6 @@ struct Lists {
   int t[kMaxClasses][kMaxSlots];
 };
 
-// The thread index as a fresh value on every pass of a work loop: the
-// per-thread index arithmetic of a pass then stays inside the loop instead of
-// being hoisted out of it and held in registers across every item.
-__device__ __forceinline__ int fresh_tid() {
-  int t = threadIdx.x;
-  asm volatile("" : "+v"(t));
-  return t;
-}
-
 // Work distribution: block b takes work items b, b + G, b + 2G, ... of its
 // pass (G = grid size).  Every item of a pass costs the same, so a grid that
 // is an integer multiple of what the chip holds at once loses nothing to
@@ -103,9 +94,8 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_
 // y or z pass of one shape class over its RUN RVEs; tile t of an RVE is
 // (bx, by) = (t mod gx, t / gx)
 template <class T, int MODE, int L, int TX>
-__global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_batch_axis(const Rve<T>* __restrict__ rv,
-                                                                      const Lists* __restrict__ ls,
-                                                                      int cls, int gx, int gy) {
+__global__ void __launch_bounds__((AShape<L, TX>::NTHR), (axis_min_waves<T, L, TX>()))
+    k_batch_axis(const Rve<T>* __restrict__ rv, const Lists* __restrict__ ls, int cls, int gx, int gy) {
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   __shared__ cx<T> twl[L];

@@ -68,20 +68,22 @@ void launch_x(int n0, int blocks, hipStream_t s, const XArgs<T>& a, const Ctl* c
 }
 
 template <class T, int MODE, int L, int TX>
-void launch_axis_tx(dim3 grid, hipStream_t s, const AxisArgs<T>& a, const Ctl* ctl) {
+void launch_axis_tx(int gx, int gy, hipStream_t s, const AxisArgs<T>& a, const Ctl* ctl) {
   const size_t shm = size_t(AShape<L, TX>::PTS) * sizeof(cx<T>);
-  hipLaunchKernelGGL((k_axis<T, MODE, L, TX>), grid, dim3(AShape<L, TX>::NTHR), shm, s, a, ctl);
+  hipLaunchKernelGGL((k_axis<T, MODE, L, TX>), dim3(gx * gy), dim3(AShape<L, TX>::NTHR), shm, s, a, ctl,
+                     gx);
 }
 
+// tiles: gx = n0 / 2 / tx along kx, gy along the other transverse axis
 template <class T, int MODE>
-void launch_axis(int L, int tx, dim3 grid, hipStream_t s, const AxisArgs<T>& a, const Ctl* ctl) {
+void launch_axis(int L, int tx, int gx, int gy, hipStream_t s, const AxisArgs<T>& a, const Ctl* ctl) {
   switch (L) {
-#define MP_CASE(N)                                             \
-  case N:                                                      \
-    if (tx == 1)                                               \
-      launch_axis_tx<T, MODE, N, 1>(grid, s, a, ctl);          \
-    else                                                       \
-      launch_axis_tx<T, MODE, N, tx_wide(N)>(grid, s, a, ctl); \
+#define MP_CASE(N)                                                        \
+  case N:                                                                 \
+    if (tx == 1)                                                          \
+      launch_axis_tx<T, MODE, N, 1>(gx, gy, s, a, ctl);                   \
+    else                                                                  \
+      launch_axis_tx<T, MODE, N, tx_wide(N)>(gx, gy, s, a, ctl);          \
     break;
     MP_SIZES(MP_CASE)
 #undef MP_CASE

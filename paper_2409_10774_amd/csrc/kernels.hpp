@@ -220,20 +220,43 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
 
   if (MODE == X_ITER || MODE == X_INV_ONLY) {
     // half spectra -> packed full spectra Z = A + i B, Z(n0 - k) = conj A + i conj B
-    for (int w = tid; w < rows_here * NH * kPencils; w += NTHR) {
+    const int items = rows_here * NH * kPencils;
+    auto get = [&](int w, cx<T>& A, cx<T>& B) {
       const int r = w / (NH * kPencils), rem = w % (NH * kPencils);
       const int kx = rem / kPencils, q = rem % kPencils;
       const MP_GLOBAL cx<T>* srow = S + (row0 + r) * (NH * 18) + kx * 18;
-      const int cre = pencil_re(q), cim = pencil_im(q);
-      const cx<T> A = gload(srow + cre);
-      cx<T> B = {T(0), T(0)};
+      const int cim = pencil_im(q);
+      A = gload(srow + pencil_re(q));
+      B = cx<T>{T(0), T(0)};
       if (cim >= 0) B = gload(srow + cim);
+    };
+    auto put = [&](int w, cx<T> A, cx<T> B) {
+      const int r = w / (NH * kPencils), rem = w % (NH * kPencils);
+      const int kx = rem / kPencils, q = rem % kPencils;
       cx<T>* pen = lds + (r * kPencils + q) * N0;
       pen[kx] = cx<T>{A.re - B.im, A.im + B.re};
       if (kx > 0)
         pen[N0 - kx] = cx<T>{A.re + B.im, B.re - A.im};
       else
         pen[NH] = cx<T>{T(0), T(0)};
+    };
+    if constexpr (sizeof(T) == 8) {
+      // FP64: every load of the thread is issued before the first is waited
+      // for (measured faster; in FP32 the streaming loop below is faster)
+      constexpr int MBX = (ROWS * NH * kPencils + NTHR - 1) / NTHR;
+      cx<T> A[MBX], B[MBX];
+#pragma unroll
+      for (int j = 0; j < MBX; ++j)
+        if (tid + j * NTHR < items) get(tid + j * NTHR, A[j], B[j]);
+#pragma unroll
+      for (int j = 0; j < MBX; ++j)
+        if (tid + j * NTHR < items) put(tid + j * NTHR, A[j], B[j]);
+    } else {
+      for (int w = tid; w < items; w += NTHR) {
+        cx<T> A, B;
+        get(w, A, B);
+        put(w, A, B);
+      }
     }
     __syncthreads();
     fft_pp<T, true, N0, 1, NPK, 1, N0, false, NTHR>(lds, lds2, tw, tid);
@@ -486,20 +509,51 @@ struct AShape {
   static constexpr int NB = TX * 18;
   static constexpr int PTS = L * NB;
   static constexpr int NTHR = PTS > 2304 ? 512 : 256;
+  static constexpr int MB = (PTS + NTHR - 1) / NTHR;   // values per thread of a tile
   static constexpr size_t LDS = size_t(PTS);   // complex values
 };
 
+// The thread index as a fresh value on every pass of a work loop: the
+// per-thread index arithmetic of a pass then stays inside the loop instead of
+// being hoisted out of it and held in registers across every item.
+__device__ __forceinline__ int fresh_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Loads of tile (bx, by) into registers, MB values per thread.  All of a
+// thread's loads are issued before the first is waited for; a loop that
+// stores each value into LDS as it arrives keeps only one load in flight.
+template <class T, int L, int TX>
+__device__ __forceinline__ void axis_fetch(const AxisArgs<T>& a, int bx, int by,
+                                           cx<T> (&v)[AShape<L, TX>::MB], int tid) {
+  using A = AShape<L, TX>;
+  const MP_GLOBAL cx<T>* g = glob(a.S) + (long)by * a.ostride + (long)bx * A::NB;
+  const long ps = a.pstride;
+#pragma unroll
+  for (int j = 0; j < A::MB; ++j) {
+    const int w = tid + j * A::NTHR;
+    if (A::PTS % A::NTHR == 0 || w < A::PTS) v[j] = gload(g + (w / A::NB) * ps + w % A::NB);
+  }
+}
+
 // tile (bx, by): kx in [bx TX, bx TX + TX), kz = by (y pass) or ky = by (z
-// pass); tw: the L-entry twiddle table in LDS
+// pass); tw: the L-entry twiddle table in LDS.  The caller has synchronised
+// the block since LDS was last read.
 template <class T, int MODE, int L, int TX>
 __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, cx<T>* lds,
                                           const cx<T>* tw, int tid) {
   using A = AShape<L, TX>;
   constexpr int NB = A::NB, PTS = A::PTS, NTHR = A::NTHR;
-  MP_GLOBAL cx<T>* g = glob(a.S) + (long)by * a.ostride + (long)bx * NB;
-  for (int w = tid; w < PTS; w += NTHR) {
-    const int i = w / NB, b = w % NB;
-    lds[w] = gload(g + i * a.pstride + b);
+  {
+    cx<T> v[A::MB];
+    axis_fetch<T, L, TX>(a, bx, by, v, tid);
+#pragma unroll
+    for (int j = 0; j < A::MB; ++j) {
+      const int w = tid + j * NTHR;
+      if (PTS % NTHR == 0 || w < PTS) lds[w] = v[j];
+    }
   }
   __syncthreads();
   constexpr bool INV = MODE == Y_INV;
@@ -538,10 +592,9 @@ __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, 
     __syncthreads();
     fft_ct<T, true, L, 1, NB, NB, 1, true, NTHR>(lds, tw, tid);
   }
-  for (int w = tid; w < PTS; w += NTHR) {
-    const int i = w / NB, b = w % NB;
-    gstore(g + i * a.pstride + b, lds[w]);
-  }
+  MP_GLOBAL cx<T>* g = glob(a.S) + (long)by * a.ostride + (long)bx * NB;
+  const long ps = a.pstride;
+  for (int w = tid; w < PTS; w += NTHR) gstore(g + (w / NB) * ps + w % NB, lds[w]);
 }
 
 // XCD-aware tile order.  The chip hands consecutive blocks to its 8 XCDs in
@@ -555,15 +608,32 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return b < per * kXcd ? (b % kXcd) * per + b / kXcd : b;
 }
 
+// y or z pass of one cell over its gx * gy tiles (tile t = (t mod gx, t / gx))
+// with a persistent grid of G <= tiles blocks: round r covers tiles
+// [r G, r G + n_r), handed out XCD-aware within the round, and each block
+// loads its next tile while it transforms the current one.
+// Waves per SIMD that the LDS tiles of a y / z pass allow (160 KB per CU),
+// at most 4: the register budget then stays at 128 or more per lane.
+template <class T, int L, int TX>
+constexpr int axis_min_waves() {
+  using A = AShape<L, TX>;
+  const int bytes = int((A::LDS + L) * sizeof(cx<T>));
+  const int blocks = (160 * 1024) / bytes;
+  const int w = blocks * A::NTHR / 256;
+  return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
+// y or z pass of one cell: block b takes tile xcd_tile(b) of the gx * gy
+// tiles (tile t = (t mod gx, t / gx)); the grid is one block per tile
 template <class T, int MODE, int L, int TX>
-__global__ void __launch_bounds__((AShape<L, TX>::NTHR)) k_axis(AxisArgs<T> a, const Ctl* ctl) {
+__global__ void __launch_bounds__((AShape<L, TX>::NTHR), (axis_min_waves<T, L, TX>()))
+    k_axis(AxisArgs<T> a, const Ctl* ctl, int gx) {
   if (ctl && ctl->done) return;
   extern __shared__ unsigned char smem_raw[];
   __shared__ cx<T> twl[L];
   load_twiddles<T, L, AShape<L, TX>::NTHR>(twl, glob(a.tw), threadIdx.x);
-  const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  axis_tile<T, MODE, L, TX>(a, t % gridDim.x, t / gridDim.x, reinterpret_cast<cx<T>*>(smem_raw), twl,
-                            threadIdx.x);
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  axis_tile<T, MODE, L, TX>(a, t % gx, t / gx, reinterpret_cast<cx<T>*>(smem_raw), twl, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -112,8 +112,6 @@ struct Eng {
     a.ref = P->ref;
     return a;
   }
-  static dim3 ygrid(const Geometry& g) { return dim3(g.nh / g.txy, g.n2); }
-  static dim3 zgrid(const Geometry& g) { return dim3(g.nh / g.txz, g.n1); }
 
   // y fwd, z fwd + Green + z inv, y inv (ev: optional events before each
   // kernel and after the last)
@@ -122,11 +120,11 @@ struct Eng {
     auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], P->stream); };
     const AxisArgs<T> ay = yargs(P, S), az = zargs(P, S);
     mark(0);
-    launch_axis<T, Y_FWD>(g.n1, g.txy, ygrid(g), P->stream, ay, ctl);
+    launch_axis<T, Y_FWD>(g.n1, g.txy, g.nh / g.txy, g.n2, P->stream, ay, ctl);
     mark(1);
-    launch_axis<T, Z_GREEN>(g.n2, g.txz, zgrid(g), P->stream, az, ctl);
+    launch_axis<T, Z_GREEN>(g.n2, g.txz, g.nh / g.txz, g.n1, P->stream, az, ctl);
     mark(2);
-    launch_axis<T, Y_INV>(g.n1, g.txy, ygrid(g), P->stream, ay, ctl);
+    launch_axis<T, Y_INV>(g.n1, g.txy, g.nh / g.txy, g.n2, P->stream, ay, ctl);
     mark(3);
   }
 
@@ -517,8 +515,10 @@ mp_status mp_spectrum_forward(mp_plan P, const void* dev_in, void* dev_out) {
   cx<double>* S = static_cast<cx<double>*>(dev_out);
   xa.S = S;
   launch_x<double, X_FWD_ONLY>(g.n0, g.xblocks, P->stream, xa, nullptr);
-  launch_axis<double, Y_FWD>(g.n1, g.txy, E8::ygrid(g), P->stream, E8::yargs(P, S), nullptr);
-  launch_axis<double, Z_FWD>(g.n2, g.txz, E8::zgrid(g), P->stream, E8::zargs(P, S), nullptr);
+  launch_axis<double, Y_FWD>(g.n1, g.txy, g.nh / g.txy, g.n2, P->stream, E8::yargs(P, S),
+                             nullptr);
+  launch_axis<double, Z_FWD>(g.n2, g.txz, g.nh / g.txz, g.n1, P->stream, E8::zargs(P, S),
+                             nullptr);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(P->stream));
   return MP_OK;

@@ -171,41 +171,56 @@ def run_serve(args, torch, mp, W):
         return {"p50_s": float(np.percentile(L, 50)), "p99_s": float(np.percentile(L, 99)),
                 "mean_s": float(L.mean())}
 
-    B = mp.Batch(shapes, arena_bytes=arena, precision="mixed", max_rves=256,
-                 iters_per_launch=args.iters_per_launch, autotune=True)
-    print(f"# closed loop: {n} requests at t = 0", file=sys.stderr, flush=True)
-    zero = np.zeros(n)
-    ta, td, st, it = mp.serve_batched(B, mp.Requests(items(zero), "mixed"), progress_s=20.0)
-    makespan = float(td.max())
-    sat = n / makespan
-    rate = 0.8 * sat
+    vox = np.array([w.phase_map.size for w in wls])
+    closed = batched = sequential = None
+    if args.serve_rate > 0:
+        # the open-loop rate of an earlier closed-loop run: the same trace again
+        rate = args.serve_rate
+    else:
+        B = mp.Batch(shapes, arena_bytes=arena, precision="mixed", max_rves=256,
+                     iters_per_launch=args.iters_per_launch, autotune=True)
+        print(f"# closed loop: {n} requests at t = 0", file=sys.stderr, flush=True)
+        ta, td, st, it = mp.serve_batched(B, mp.Requests(items(np.zeros(n)), "mixed"), progress_s=20.0)
+        B.close()
+        del B
+        torch.cuda.empty_cache()
+        makespan = float(td.max())
+        sat = n / makespan
+        rate = 0.8 * sat
+        closed = {"requests_per_s": sat, "makespan_s": makespan,
+                  "voxel_iterations_per_s": float((it * vox).sum()) / makespan}
     gaps = np.random.default_rng(4).exponential(1.0 / rate, size=n)
     arr = np.cumsum(gaps) - gaps[0]
-    print(f"# saturation {sat:.3f} req/s; open loop at {rate:.3f} req/s", file=sys.stderr, flush=True)
-    ta2, td2, st2, it2 = mp.serve_batched(B, mp.Requests(items(arr), "mixed"), progress_s=20.0)
-    B.close()
-    del B
-    torch.cuda.empty_cache()
-    print("# sequential fp64 on the same trace", file=sys.stderr, flush=True)
-    ws = torch.empty(arena, dtype=torch.uint8, device="cuda:0")
-    ts3, td3, st3, it3 = mp.serve_sequential(mp.Requests(items(arr), "fp64"), ws, progress_s=20.0)
-    vox = np.array([w.phase_map.size for w in wls])
+    if args.servers in ("both", "batched"):
+        print(f"# open loop at {rate:.4f} req/s, continuous batching", file=sys.stderr, flush=True)
+        B = mp.Batch(shapes, arena_bytes=arena, precision="mixed", max_rves=256,
+                     iters_per_launch=args.iters_per_launch, autotune=True)
+        ta2, td2, st2, it2 = mp.serve_batched(B, mp.Requests(items(arr), "mixed"), progress_s=20.0)
+        B.close()
+        del B
+        torch.cuda.empty_cache()
+        batched = dict(lat(arr, td2), makespan_s=float(td2.max()), statuses=[int(v) for v in set(st2)],
+                       voxel_iterations_per_s=float((it2 * vox).sum()) / float(td2.max()))
+    if args.servers in ("both", "sequential"):
+        print(f"# open loop at {rate:.4f} req/s, sequential fp64", file=sys.stderr, flush=True)
+        ws = torch.empty(arena, dtype=torch.uint8, device="cuda:0")
+        ts3, td3, st3, it3 = mp.serve_sequential(mp.Requests(items(arr), "fp64"), ws, progress_s=20.0)
+        sequential = dict(lat(arr, td3), makespan_s=float(td3.max()), statuses=[int(v) for v in set(st3)],
+                          voxel_iterations_per_s=float((it3 * vox).sum()) / float(td3.max()))
+    head = batched or sequential
     return {
-        "metric": "requests/s", "value": n / float(td2.max()), "unit": "requests/s", "n_gpus": 1,
-        "steps": n, "warmup": 0, "ms_per_step": float(td2.max()) / n * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32 bulk / f64 reductions",
+        "metric": "requests/s", "value": n / head["makespan_s"], "unit": "requests/s", "n_gpus": 1,
+        "steps": n, "warmup": 0, "ms_per_step": head["makespan_s"] / n * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 bulk / f64 reductions" if batched else "f64",
         "data": "synthetic (seeded Poisson trace of random-sphere RVEs)",
         "config": {"workload": WORKLOADS["serve_mixed"]["desc"], "requests": n,
                    "arrival_rate_per_s": rate, "iters_per_launch": args.iters_per_launch,
-                   "arena_gib": args.arena_gib, "parallelism": "single GPU"},
-        "closed_loop": {"requests_per_s": sat, "makespan_s": makespan,
-                        "voxel_iterations_per_s": float((it * vox).sum()) / makespan},
-        "batched_mixed": dict(lat(arr, td2), makespan_s=float(td2.max()),
-                              statuses=[int(v) for v in set(st2)],
-                              voxel_iterations_per_s=float((it2 * vox).sum()) / float(td2.max())),
-        "sequential_fp64": dict(lat(arr, td3), makespan_s=float(td3.max()),
-                                statuses=[int(v) for v in set(st3)],
-                                voxel_iterations_per_s=float((it3 * vox).sum()) / float(td3.max())),
+                   "arena_gib": args.arena_gib, "servers": args.servers,
+                   "parallelism": "single GPU"},
+        "closed_loop": closed,
+        "batched_mixed": batched,
+        "sequential_fp64": sequential,
     }
 
 
@@ -224,6 +239,10 @@ def main():
                     help="batch64_mixed: also solve the first N RVEs one by one with FP64 plans")
     ap.add_argument("--requests", type=int, default=24, help="serve_mixed: requests in the trace")
     ap.add_argument("--arena-gib", type=int, default=48, help="serve_mixed: device arena (GiB)")
+    ap.add_argument("--servers", default="both", choices=("both", "batched", "sequential"),
+                    help="serve_mixed: which servers replay the open-loop trace")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="serve_mixed: open-loop arrival rate (req/s) instead of 0.8x a closed-loop run")
     ap.add_argument("--iters-per-launch", type=int, default=8,
                     help="batch / serve: loop iterations per graph launch")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -647,6 +647,19 @@ __device__ __forceinline__ double row_reduce(const MP_GLOBAL double* row, int nb
   const int tid = threadIdx.x;
   double v0 = 0.0, v1 = 0.0;
   int b = tid;
+  // chunks of 2U values per thread, all loaded before they are combined (in
+  // the same order as the loop below, which takes the rest)
+  constexpr int U = 8;
+  for (; b + 512 * (U - 1) + 256 < nblk; b += 512 * U) {
+    double x[2 * U];
+#pragma unroll
+    for (int k = 0; k < 2 * U; ++k) x[k] = row[b + 256 * k];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      v0 = mx ? nmax(v0, x[2 * k]) : v0 + x[2 * k];
+      v1 = mx ? nmax(v1, x[2 * k + 1]) : v1 + x[2 * k + 1];
+    }
+  }
   for (; b + 256 < nblk; b += 512) {
     const double x = row[b], y = row[b + 256];
     v0 = mx ? nmax(v0, x) : v0 + x;

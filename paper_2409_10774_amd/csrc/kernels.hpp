@@ -608,10 +608,6 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return b < per * kXcd ? (b % kXcd) * per + b / kXcd : b;
 }
 
-// y or z pass of one cell over its gx * gy tiles (tile t = (t mod gx, t / gx))
-// with a persistent grid of G <= tiles blocks: round r covers tiles
-// [r G, r G + n_r), handed out XCD-aware within the round, and each block
-// loads its next tile while it transforms the current one.
 // Waves per SIMD that the LDS tiles of a y / z pass allow (160 KB per CU),
 // at most 4: the register budget then stays at 128 or more per lane.
 template <class T, int L, int TX>

@@ -140,6 +140,17 @@ mp_status mp_get_fields(mp_plan plan, int32_t field, double* host_dst);
  * Lets parity tests follow a given iteration schedule. */
 mp_status mp_set_fixed_iterations(mp_plan plan, int32_t n_fixed);
 
+/* Eigenstress: the verification form of the polarization used by the
+ * method of numerically manufactured solutions (App. D.1, the manufactured
+ * polarization equation), tau = t - A0 e - tau_m, mu = m - B0 gamma - mu_m.
+ * dev_eig: 18*n device values of the plan's precision (double for MP_FP64,
+ * float for MP_MIXED), SoA [c][voxel] with c = 3k + l for tau_m (0..8) and
+ * 9 + 3k + l for mu_m.  The caller owns the buffer; it is read, not copied,
+ * by every polarization of later mp_solve_load_path calls until it is
+ * replaced, or cleared with NULL.  A manufactured stress that changes from
+ * step to step is set before each single-step call. */
+mp_status mp_set_eigenstress(mp_plan plan, const void* dev_eig);
+
 /* Number of committed steps. */
 mp_status mp_plan_steps(mp_plan plan, int32_t* steps);
 

@@ -78,6 +78,7 @@ struct XArgs {
   int pad;
   const T* fin;     // X_FWD_ONLY input (18 n)
   T* fout;          // X_INV_ONLY output (18 n)
+  const T* eig;     // optional eigenstress (18 n): subtracted in every polarization
 };
 
 // deterministic sum over a 64-lane wavefront (every lane gets the total)
@@ -375,15 +376,24 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
           macro_return<T>(ct, e, bb, hn, t, pnew);
         else
           micro_return<T>(cm, e, bb, hn, t, pnew);
-        // polarization (Eq. 34): tau = t - A0 e ; mu = m - B0 gamma
+        // polarization (Eq. 34): tau = t - A0 e ; mu = m - B0 gamma, less the
+        // eigenstress when one is set (the manufactured stresses of the code
+        // verification, App. D.1)
         T r0[9];
         if (lvl == 0)
           apply_A<T>(T(a.ref.lam), T(a.ref.mu), T(a.ref.kap), e, r0);
         else
           apply_B<T>(T(a.ref.alp), T(a.ref.bet), T(a.ref.gam), e, r0);
 #pragma unroll
+        for (int c = 0; c < 9; ++c) r0[c] = t[c] - r0[c];
+        if (a.eig) {
+          const MP_GLOBAL T* const eg = glob(a.eig) + (long)lvl * 9 * nv;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) r0[c] -= eg[c * nv + gi];
+        }
+#pragma unroll
         for (int c = 0; c < 9; ++c) {
-          ldr[slot(lvl * 9 + c)] = t[c] - r0[c];
+          ldr[slot(lvl * 9 + c)] = r0[c];
           Elv[c * nv + gi] = e[c];
         }
       }

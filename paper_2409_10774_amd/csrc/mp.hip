@@ -60,6 +60,7 @@ struct mp_plan_s {
   uint8_t* phase;
   PhaseC* params;
   void* tw0;      // cx<T>, n0 + n1 + n2 entries
+  const void* eig;   // optional eigenstress (T, 18 n, caller-owned)
   Ctl* ctl;
   Ctl* ctl_host;
   double* tot_host;   // pinned, kNAvg entries
@@ -145,6 +146,7 @@ struct Eng {
     a.params = P->params;
     a.partials = P->partials;
     a.ref = P->ref;
+    a.eig = static_cast<const T*>(P->eig);
     return a;
   }
 
@@ -337,6 +339,7 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   P->phase = wsp + L.phase;
   P->params = reinterpret_cast<PhaseC*>(wsp + L.params);
   P->tw0 = wsp + L.tw;
+  P->eig = nullptr;
   P->partials = reinterpret_cast<double*>(wsp + L.partials);
   P->ctl = reinterpret_cast<Ctl*>(wsp + L.ctl);
   P->tot = reinterpret_cast<double*>(wsp + L.tot);
@@ -438,6 +441,12 @@ mp_status mp_set_fixed_iterations(mp_plan P, int32_t n_fixed) {
   if (!P) return fail(MP_E_INVALID, "plan is NULL");
   if (n_fixed < 0) return fail(MP_E_INVALID, "n_fixed < 0");
   P->fixed = n_fixed;
+  return MP_OK;
+}
+
+mp_status mp_set_eigenstress(mp_plan P, const void* dev_eig) {
+  if (!P) return fail(MP_E_INVALID, "plan is NULL");
+  P->eig = dev_eig;
   return MP_OK;
 }
 

@@ -74,6 +74,7 @@ def _load():
         "mp_get_fields": (C.c_int, [vp, i32, dp]),
         "mp_step_error_parts": (C.c_int, [vp, i32, dp]),
         "mp_set_fixed_iterations": (C.c_int, [vp, i32]),
+        "mp_set_eigenstress": (C.c_int, [vp, vp]),
         "mp_plan_steps": (C.c_int, [vp, C.POINTER(i32)]),
         "mp_green_apply": (C.c_int, [vp, vp, vp]),
         "mp_spectrum_forward": (C.c_int, [vp, vp, vp]),
@@ -232,6 +233,21 @@ class Plan:
 
     def set_fixed_iterations(self, n):
         check(lib.mp_set_fixed_iterations(self.handle, int(n)))
+
+    def set_eigenstress(self, tm=None):
+        """Eigenstress subtracted in every later polarization (mp_set_eigenstress):
+        tm (18, n2, n1, n0) host array, tau_m then mu_m with component 3k + l,
+        or None to clear.  The plan holds the device copy."""
+        if tm is None:
+            check(lib.mp_set_eigenstress(self.handle, None))
+            self._eig = None
+            return
+        dt = self.torch.float64 if self.prob.precision == MP_FP64 else self.torch.float32
+        a = np.ascontiguousarray(np.asarray(tm, np.float64).reshape((18,) + self.shape))
+        t = self.torch.from_numpy(a).to(device=self.device, dtype=dt)
+        self.torch.cuda.synchronize(self.device)
+        check(lib.mp_set_eigenstress(self.handle, C.c_void_p(t.data_ptr())))
+        self._eig = t
 
     # -- single steps of the hot path ---------------------------------------
     def green_apply(self, tau_mu):

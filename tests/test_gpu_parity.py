@@ -9,7 +9,9 @@ Element-by-element comparisons on the same seeded inputs:
     the 16^3 sphere cell over all 10 steps and on a cyclic load / unload /
     reverse path with uneven time steps, with equal per-step iteration
     counts; an empty load path;
-  - the 128^3 random-sphere cell at full size over a fixed iteration schedule.
+  - the 128^3 random-sphere cell at full size over a fixed iteration schedule;
+  - the paper's manufactured-solution check (App. D.1) with the manufactured
+    stresses as an eigenstress, against the manufactured fields and the oracle.
 Floating-point bar: 1e-10 relative (FP64 path), per field
 rel = max_x |a_gpu - a_ref| / max_x |a_ref|.
 """
@@ -265,3 +267,47 @@ def test_cyclic_path_uneven_steps(torch, mp):
     it, resp = compare_run(mp, plan, wl, len(amp))
     # the path really unloads and reverses: the mean macro stress changes sign
     assert resp[:, 0].max() > 0 and resp[:, 0].min() < 0
+
+
+def test_manufactured_solution_app_d1(torch, mp):
+    """The paper's code verification (App. D.1) on the HIP path: the
+    manufactured stresses enter every polarization as an eigenstress
+    (mp_set_eigenstress), one load step per call on the 4^3 two-phase cube
+    over 25 steps.  The GPU must return the manufactured strains and stresses
+    within a few epsilon (the paper reports errors below epsilon = 1e-9), and
+    the oracle's fields within 1e-10 on the same iteration schedule."""
+    from tests.mnms_case import case
+    say("case: App. D.1 manufactured solution, 4^3, 25 steps, eigenstress")
+    n_steps = 25
+    c = case(n_steps)
+    times, Em, Gm, tm, mm = c["times"], c["Em"], c["Gm"], c["tm"], c["mm"]
+    E = times[1:, None] * Em.reshape(1, 9)
+    G = times[1:, None] * Gm.reshape(1, 9)
+    check = (n_steps // 2, n_steps)
+    plan = mp.Plan(c["pm"], c["phases"], h=c["h"], tol=c["eps"])
+    it_gpu, got = [], {}
+    for s in range(1, n_steps + 1):
+        plan.set_eigenstress(np.concatenate([O.to_f9(tm[s - 1]), O.to_f9(mm[s - 1])]))
+        it_gpu += plan.solve(times[s - 1: s + 1], E[s - 1: s], G[s - 1: s])
+        if s in check:
+            got[s] = {k: plan.field(k) for k in ("e", "g", "t", "m")}
+    eig = lambda s: (tm[s - 1], mm[s - 1])
+    out = O.Solver(c["pm"], c["phases"], h=c["h"], tol=c["eps"]).solve(
+        times, E, G, eig=eig, fields_at=check)
+    say("iterations gpu", it_gpu, "oracle", out["iters"])
+    if it_gpu != out["iters"]:
+        # a step ended on the other side of epsilon: follow the GPU's schedule
+        out = O.Solver(c["pm"], c["phases"], h=c["h"], tol=c["eps"]).solve(
+            times, E, G, schedule=it_gpu, eig=eig, fields_at=check)
+        assert sum(abs(a - b) for a, b in zip(it_gpu, out["iters"])) <= 1, (it_gpu, out["iters"])
+    for s in check:
+        tt = times[s]
+        man = {"e": O.to_f9(tt * c["De"]), "g": O.to_f9(tt * c["Dg"]),
+               "t": O.to_f9(tm[s - 1]), "m": O.to_f9(mm[s - 1])}
+        for k, ref in man.items():
+            err_man = np.abs(got[s][k] - ref).max()
+            err_orc = rel(got[s][k], out["fields"][s][k])
+            say(f"step {s} {k}: |gpu - manufactured| {err_man:.2e}, rel vs oracle {err_orc:.2e}")
+            assert err_man < c["bound"], (s, k, err_man)
+            assert err_orc < TOL, (s, k, err_orc)
+    plan.set_eigenstress(None)

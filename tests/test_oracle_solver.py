@@ -12,14 +12,10 @@
   manufactured stresses subtracted in the polarization (Eq. 85), the scheme
   returns the manufactured strains and stresses.
 """
-import json
-import os
-
 import numpy as np
 import pytest
 
 from oracle import micropolar as O
-from oracle import tangent as T
 from paper_2409_10774_amd import workloads as W
 from tests import helpers as H
 
@@ -107,7 +103,7 @@ def test_centred_sphere_symmetry():
     assert np.abs(t11 - t11[:, :, ::-1]).max() < 1e-12 * scale
 
 
-GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mnms_app_d1.json")))
+from tests.mnms_case import GOLDEN, case as mnms_case
 
 
 def test_manufactured_cell_matches_paper_values():
@@ -119,58 +115,21 @@ def test_manufactured_cell_matches_paper_values():
             assert getattr(ph, k) == v, (key, k)
 
 
-def manufactured(n_steps):
-    """Manufactured strains of the code check on the 4^3 cube (unit cell, h = 1/4).
-
-    u_l = t S(x), phi_m = t S(x) with S = sin(2 pi x1) sin(2 pi x2) sin(2 pi x3);
-    uniform parts E(t) = t [1..9], Gamma(t) = t [1.5..9.5] added as means.
-    """
-    N, h = 4, 0.25
-    c = (np.arange(N) + 0.5) * h
-    x3, x2, x1 = np.meshgrid(c, c, c, indexing="ij")
-    tp = 2 * np.pi
-    S = np.sin(tp * x1) * np.sin(tp * x2) * np.sin(tp * x3)
-    dS = [tp * np.cos(tp * x1) * np.sin(tp * x2) * np.sin(tp * x3),
-          tp * np.sin(tp * x1) * np.cos(tp * x2) * np.sin(tp * x3),
-          tp * np.sin(tp * x1) * np.sin(tp * x2) * np.cos(tp * x3)]
-    Em = np.array(GOLDEN["E_rate"])
-    Gm = np.array(GOLDEN["Gamma_rate"])
-    De = np.zeros(S.shape + (3, 3))
-    Dg = np.zeros(S.shape + (3, 3))
-    for k in range(3):
-        for l in range(3):
-            De[..., k, l] = dS[k] + sum(H.LC[l, k, m] for m in range(3)) * S + Em[k, l]
-            Dg[..., k, l] = dS[l] + Gm[k, l]
-    times = np.linspace(0.0, 1.0, n_steps + 1)
-    return h, De, Dg, times, Em, Gm
-
-
 def test_manufactured_solution():
     n_steps = 25
-    pm, phases = W.mnms_cube4()
-    h, De, Dg, times, Em, Gm = manufactured(n_steps)
-    # manufactured stresses: continuum-tangent integration at every voxel
-    tab = O.phase_table(phases)[pm.ravel().astype(int)]
-    c = {k: tab[:, i] for i, k in enumerate(O.PHASE_KEYS)}
-    V = pm.size
-    st = (np.zeros((V, 3, 3)), np.zeros((V, 3, 3)), np.zeros(V), np.zeros(V))
-    tm, mm = [], []
-    for s in range(n_steps):
-        st = T.integrate(c, st, De.reshape(V, 3, 3), Dg.reshape(V, 3, 3),
-                         times[s + 1] - times[s], substeps=40)
-        tm.append(st[0].reshape(pm.shape + (3, 3)))
-        mm.append(st[1].reshape(pm.shape + (3, 3)))
-    assert st[2].max() > 0 and st[3].max() > 0          # both levels yield
-    solver = O.Solver(pm, phases, h=h, tol=GOLDEN["epsilon"])
+    c = mnms_case(n_steps)
+    assert c["p"].max() > 0 and c["q"].max() > 0          # both levels yield
+    times, Em, Gm, tm, mm = c["times"], c["Em"], c["Gm"], c["tm"], c["mm"]
+    solver = O.Solver(c["pm"], c["phases"], h=c["h"], tol=c["eps"])
     out = solver.solve(times, times[1:, None] * Em.reshape(1, 9), times[1:, None] * Gm.reshape(1, 9),
                        eig=lambda s: (tm[s - 1], mm[s - 1]), fields_at=(n_steps // 2, n_steps))
     for s in (n_steps // 2, n_steps):
         f = out["fields"][s]
         tt = times[s]
         # the paper reports errors below epsilon; allow a few epsilon here
-        bound = 5 * GOLDEN["reported_max_abs_error_below"]
-        assert np.abs(f["e"] - O.to_f9(tt * De)).max() < bound
-        assert np.abs(f["g"] - O.to_f9(tt * Dg)).max() < bound
+        bound = c["bound"]
+        assert np.abs(f["e"] - O.to_f9(tt * c["De"])).max() < bound
+        assert np.abs(f["g"] - O.to_f9(tt * c["Dg"])).max() < bound
         assert np.abs(f["t"] - O.to_f9(tm[s - 1])).max() < bound
         assert np.abs(f["m"] - O.to_f9(mm[s - 1])).max() < bound
 

@@ -302,6 +302,31 @@ def mnms_cube4():
     return ph, [p1, p2]
 
 
+def ratchet_laminate(cycles: int = 10, dt: float = 0.01, rate: float = 1.0, tY: float = 2.5,
+                     mH: float = 0.0025, mY: float = 0.005, tol: float = 1e-5) -> Workload:
+    """Micro-plastic ratcheting cell of Sec. 3.2: a 4^3 laminate at 50 %
+    volume fraction (layers normal to x2), unit cube (h = 1/4), the phase
+    constants of Tab. 2, and `cycles` one-second shear cycles with
+    dE12/dt = +rate for the first half of each cycle and -rate for the second
+    (E12 from 0 up to rate / 2 and back), time step dt, all other strain and
+    curvature components zero.  tY, mH and mY override Tab. 2's (tY = 1.9,
+    mH = 0 is the variant of the second ratcheting study; mY = inf turns the
+    micro level elastic)."""
+    ph = laminate(4, axis=1)
+    p1 = Phase(lam=1.0, mu=1.0, kappa=1.0, alpha=0.0, beta=1.0, gamma=2.0,
+               tY=tY, tH=0.0, mY=mY, mH=mH, a1=1.5, b1=1.5)
+    p2 = Phase(lam=2.0, mu=2.0, kappa=2.0, alpha=0.0, beta=2.0, gamma=4.0,
+               tY=tY, tH=0.0, mY=mY, mH=mH, a1=1.5, b1=1.5)
+    per = int(round(1.0 / dt))
+    S = cycles * per
+    times = dt * np.arange(S + 1)
+    k = np.arange(1, S + 1) % per                   # steps into the current cycle
+    E = np.zeros((S, 9))
+    E[:, 1] = rate * dt * np.minimum(k, per - k)
+    return Workload(f"ratchet_{cycles}c", ph, [p1, p2], times, E, np.zeros((S, 9)), tol=tol, h=0.25,
+                    info=dict(cycles=cycles, dt=dt, tY=tY, mH=mH, mY=mY))
+
+
 def random_state(nvox: int, seed: int, scale: float = 1e-2):
     """Random pointwise inputs for return-map checks: e, g, e_n, g_n, t_n, m_n
     as (9, nvox) arrays, p_n, q_n >= 0 as (nvox,)."""

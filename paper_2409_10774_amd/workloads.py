@@ -327,6 +327,40 @@ def ratchet_laminate(cycles: int = 10, dt: float = 0.01, rate: float = 1.0, tY: 
                     info=dict(cycles=cycles, dt=dt, tY=tY, mH=mH, mY=mY))
 
 
+def four_spheres_16(seed: int = 5, vf: float = 0.2) -> np.ndarray:
+    """16^3 matrix (phase 0) with four equal non-overlapping periodic spheres
+    (phase 1) of nominal total volume fraction vf, centres by random
+    sequential addition (the length-scale cell of Sec. 3.3; the paper's
+    sphere positions are not given)."""
+    n = 16
+    r = (3.0 * vf * n ** 3 / (4 * 4.0 * math.pi)) ** (1.0 / 3.0)
+    ph, _ = random_spheres(n, seed, 4, r, r)
+    return ph
+
+
+def length_scale_rve(le: float, lp: float, seed: int = 5, n_steps: int = 100,
+                     tol: float = 1e-5) -> Workload:
+    """One cell of the Sec. 3.3 length-scale study: the constants of Tab. 3
+    for elastic length le = sqrt(gamma / mu) and plastic length
+    lp = sqrt(a / b) (gamma and b fixed; lambda = mu = kappa = gamma / le^2,
+    beta = gamma / 2, a1 = b1 lp^2), matrix = phase 1 of the table, spheres
+    = phase 2, on the unit cube (h = 1/16); monotone dE32/dt = 1 and
+    dGamma11/dt = 1 over N steps of dt = 0.01."""
+    def phase(gam, tY, tH):
+        m = gam / le ** 2
+        return Phase(lam=m, mu=m, kappa=m, alpha=0.0, beta=gam / 2.0, gamma=gam,
+                     tY=tY, tH=tH, mY=tY, mH=tH, a1=1.5 * lp ** 2, b1=1.5)
+    ph = four_spheres_16(seed)
+    dt = 0.01
+    times = dt * np.arange(n_steps + 1)
+    E = np.zeros((n_steps, 9))
+    G = np.zeros((n_steps, 9))
+    E[:, 7] = times[1:]          # E32 (component 3k + l with k = 2, l = 1)
+    G[:, 0] = times[1:]          # Gamma11
+    return Workload(f"lscale_le{le:g}_lp{lp:g}", ph, [phase(1.0, 0.5, 0.125), phase(2.0, 0.75, 0.25)],
+                    times, E, G, tol=tol, h=1.0 / 16, info=dict(le=le, lp=lp, seed=seed))
+
+
 def random_state(nvox: int, seed: int, scale: float = 1e-2):
     """Random pointwise inputs for return-map checks: e, g, e_n, g_n, t_n, m_n
     as (9, nvox) arrays, p_n, q_n >= 0 as (nvox,)."""

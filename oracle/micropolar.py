@@ -193,9 +193,15 @@ def radial_return(e, g, e_n, g_n, t_n, m_n, p_n, q_n, phase_map, phases):
     for ph in np.unique(pm):
         sel = pm == ph
         lam, mu_, kap, alp, bet, gam = tab[ph, :6]
-        # Eq. 30: elastic trial stresses
-        t_tr[sel] = tn[sel] + apply_A(stiffness_A(lam, mu_, kap), de[sel])
-        m_tr[sel] = mn[sel] + apply_B(stiffness_B(alp, bet, gam), dg[sel])
+        # Eq. 30: elastic trial stresses, with the phase's general
+        # centrosymmetric tensors of Eq. 5 when it has them (A, B attributes;
+        # B in index order (l, k, m, n) as stiffness_B), else those of Eq. 6
+        A = getattr(phases[ph], "A", None)
+        B = getattr(phases[ph], "B", None)
+        A = stiffness_A(lam, mu_, kap) if A is None else np.asarray(A, float)
+        B = stiffness_B(alp, bet, gam) if B is None else np.asarray(B, float)
+        t_tr[sel] = tn[sel] + apply_A(A, de[sel])
+        m_tr[sel] = mn[sel] + apply_B(B, dg[sel])
 
     # a2 = a1 mu / kappa, b2 = b1 (gamma + beta) / (gamma - beta)
     a1, b1 = c["a1"], c["b1"]

@@ -42,6 +42,12 @@ class Phase:
     mH: float = 0.0
     a1: float = 1.5
     b1: float = 1.5
+    # optional general elastic tensors of Eq. 5 (elastic phases only):
+    # A[k, l, m, n] = A_klmn and B[l, k, m, n] = B_lkmn, so that
+    # t_kl = A_klmn e_mn and m_kl = B_lkmn gamma_mn; the isotropic constants
+    # above then serve the reference medium and the Eqs. 14, 17 weights
+    A: "np.ndarray | None" = None
+    B: "np.ndarray | None" = None
 
     def as_tuple(self):
         return tuple(float(getattr(self, k)) for k in PHASE_KEYS)
@@ -325,6 +331,26 @@ def ratchet_laminate(cycles: int = 10, dt: float = 0.01, rate: float = 1.0, tY: 
     E[:, 1] = rate * dt * np.minimum(k, per - k)
     return Workload(f"ratchet_{cycles}c", ph, [p1, p2], times, E, np.zeros((S, 9)), tol=tol, h=0.25,
                     info=dict(cycles=cycles, dt=dt, tY=tY, mH=mH, mY=mY))
+
+
+def anisotropic_phase(seed: int, t_scale: float = 4.0, m_scale: float = 2.0) -> Phase:
+    """Elastic phase with general centrosymmetric tensors of Eq. 5: A_klmn
+    and B_lkmn from random symmetric positive definite 9 x 9 matrices over
+    the index pairs (kl, mn) and (lk, mn), mean eigenvalue t_scale and
+    m_scale (eigenvalues within a factor of about 2).  Its isotropic constants
+    (used for the reference medium and the Eqs. 14, 17 weights) have the
+    same mean eigenvalues."""
+    rng = np.random.default_rng(seed)
+
+    def spd(scale):
+        R = rng.standard_normal((9, 9))
+        M = 0.25 * (R @ R.T) / 9.0 + np.eye(9)
+        return M * (9.0 * scale / np.trace(M))
+
+    A = spd(t_scale).reshape(3, 3, 3, 3)
+    B = spd(m_scale).reshape(3, 3, 3, 3)
+    return Phase(lam=0.0, mu=0.5 * t_scale, kappa=0.5 * t_scale, alpha=0.0, beta=0.25 * m_scale,
+                 gamma=0.75 * m_scale, A=A, B=B)
 
 
 def four_spheres_16(seed: int = 5, vf: float = 0.2) -> np.ndarray:

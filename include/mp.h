@@ -69,6 +69,18 @@ typedef struct {
   double tY, tH, mY, mH, a1, b1;
 } mp_phase;
 
+/* A phase with general centrosymmetric elastic tensors (Eq. 5) in place of
+ * the isotropic ones of Eq. 6.  Both tensors must be symmetric over their
+ * index pairs (A_klmn = A_mnkl, B_lkmn = B_mnlk) and positive definite as
+ * 9 x 9 matrices.  The phase must be elastic (tY = mY = INFINITY); its
+ * isotropic constants in mp_phase still enter the reference medium and the
+ * Eqs. 14, 17 equivalent stresses reported as Teq, Meq. */
+typedef struct {
+  int32_t phase;            /* phase id (< n_phases), listed at most once */
+  double A[81];             /* A_klmn at index 27k + 9l + 3m + n: t_kl = A_klmn e_mn */
+  double B[81];             /* B_lkmn at index 27l + 9k + 3m + n: m_kl = B_lkmn gamma_mn */
+} mp_aniso;
+
 /* Problem statement (inputs of Alg. 2). */
 typedef struct {
   int32_t n[3];             /* voxels along x, y, z */
@@ -88,6 +100,9 @@ typedef struct {
                                when the error measure stops improving for 100
                                iterations (its FP32 rounding floor), which
                                mp_step_error_parts reports */
+  int32_t n_aniso;          /* phases with Eq. 5 tensors, 0..n_phases (plans
+                               only: a batch rejects n_aniso > 0) */
+  const mp_aniso* aniso;    /* host, n_aniso records (unused when n_aniso = 0) */
 } mp_problem;
 
 typedef struct mp_plan_s* mp_plan;
@@ -173,7 +188,8 @@ mp_status mp_spectrum_forward(mp_plan plan, const void* dev_in, void* dev_out);
  * phase: n_vox uint8 ids into the plan's phase table.  e, g, e_n, g_n, t_n,
  * m_n: 9*n_vox SoA; p_n, q_n: n_vox.  Outputs t, m (9*n_vox), p, q (n_vox).
  * Uses the same device code as the solver (trial stresses formed from the
- * history base t_n - A e_n, m_n - B g_n). */
+ * history base t_n - A e_n, m_n - B g_n).  MP_E_INVALID for a plan whose
+ * problem has Eq. 5 phases (n_aniso > 0). */
 mp_status mp_radial_return(mp_plan plan, int64_t n_vox, const void* phase,
                            const void* e, const void* g, const void* e_n, const void* g_n,
                            const void* t_n, const void* m_n, const void* p_n, const void* q_n,

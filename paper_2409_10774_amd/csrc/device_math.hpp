@@ -303,7 +303,7 @@ struct MacroC {
   double lam, mu, kap;   // Eq. 6 moduli of A
   double tY, tH;         // Eq. 15 yield stress and hardening
   double a1, a2;         // Eq. 14 weights, a2 = a1 mu / kappa (Alg. 1)
-  double pad;
+  double aid;            // index of the phase's Eq. 5 tensors, -1 for Eq. 6
 };
 struct MicroC {
   double alp, bet, gam;  // Eq. 6 moduli of B
@@ -316,6 +316,19 @@ struct PhaseC {
   MacroC t;
   MicroC m;
 };
+
+// Eq. 5 with general tensors: out_i = R_ij x_j for a 9 x 9 row matrix R
+// (FP64 in global memory), i = 3k + l, j = 3m + n
+template <class T>
+__device__ __forceinline__ void aniso_apply(const MP_GLOBAL double* R, const T* x, T* out) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    T s = T(0);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) s += T(R[9 * i + j]) * x[j];
+    out[i] = s;
+  }
+}
 
 // t_kl = lam tr(e) d_kl + (mu + kappa) e_kl + (mu - kappa) e_lk      (Eq. 6)
 template <class T>

@@ -55,12 +55,17 @@ constexpr int tx_wide(int L) {
 
 inline int x_rows(int n0) { return n0 >= 128 ? 1 : 128 / n0; }
 
+// an: the problem has phases with Eq. 5 tensors (ITER and TRANS passes)
 template <class T, int MODE>
-void launch_x(int n0, int blocks, hipStream_t s, const XArgs<T>& a, const Ctl* ctl) {
+void launch_x(int n0, int blocks, hipStream_t s, const XArgs<T>& a, const Ctl* ctl, bool an = false) {
+  constexpr bool LAW = MODE == X_ITER || MODE == X_TRANS;
   switch (n0) {
-#define MP_CASE(N)                                                                                \
-  case N:                                                                                         \
-    hipLaunchKernelGGL((k_xpass<T, MODE, N>), dim3(blocks), dim3(XShape<N>::NTHR), 0, s, a, ctl); \
+#define MP_CASE(N)                                                                                    \
+  case N:                                                                                             \
+    if (LAW && an)                                                                                    \
+      hipLaunchKernelGGL((k_xpass<T, MODE, N, LAW>), dim3(blocks), dim3(XShape<N>::NTHR), 0, s, a, ctl); \
+    else                                                                                              \
+      hipLaunchKernelGGL((k_xpass<T, MODE, N>), dim3(blocks), dim3(XShape<N>::NTHR), 0, s, a, ctl);   \
     break;
     MP_SIZES(MP_CASE)
 #undef MP_CASE
@@ -120,14 +125,49 @@ constexpr int kFloorWindow = 100;
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t S, E, Eprev, base, pq, out_tm, out_pq, phase, params, tw, partials, ctl, tot, total;
+  size_t S, E, Eprev, base, pq, out_tm, out_pq, phase, params, aniso, tw, partials, ctl, tot, total;
 };
 
 struct Geometry {
   int n0, n1, n2, nh;
   long nvox, nspec, nrows;
   int xblocks, txy, txz;
+  int n_aniso;     // phases with Eq. 5 tensors
 };
+
+// Symmetric positive definite 9 x 9 matrix (row-major), by Cholesky
+inline bool spd9(const double* M) {
+  double scale = 0.0;
+  for (int i = 0; i < 81; ++i) {
+    if (!std::isfinite(M[i])) return false;
+    scale = std::max(scale, std::fabs(M[i]));
+  }
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < i; ++j)
+      if (std::fabs(M[9 * i + j] - M[9 * j + i]) > 1e-12 * scale) return false;
+  double L[81] = {};
+  for (int j = 0; j < 9; ++j) {
+    double d = M[9 * j + j];
+    for (int k = 0; k < j; ++k) d -= L[9 * j + k] * L[9 * j + k];
+    if (!(d > 1e-14 * scale)) return false;
+    L[9 * j + j] = std::sqrt(d);
+    for (int i = j + 1; i < 9; ++i) {
+      double v = M[9 * i + j];
+      for (int k = 0; k < j; ++k) v -= L[9 * i + k] * L[9 * j + k];
+      L[9 * i + j] = v / L[9 * j + j];
+    }
+  }
+  return true;
+}
+
+// Row matrices of an Eq. 5 record: out[0..80] R with t_kl = R[3k + l][3m + n] e_mn
+// (= A_klmn), out[81..161] with m_kl = R[3k + l][3m + n] gamma_mn (= B_lkmn)
+inline void aniso_rows(const mp_aniso& a, double* out) {
+  for (int i = 0; i < 81; ++i) out[i] = a.A[i];
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l)
+      for (int j = 0; j < 9; ++j) out[81 + 9 * (3 * k + l) + j] = a.B[9 * (3 * l + k) + j];
+}
 
 inline mp_status validate(const mp_problem* p, Geometry* g) {
   if (!p) return fail(MP_E_INVALID, "problem is NULL");
@@ -165,6 +205,22 @@ inline mp_status validate(const mp_problem* p, Geometry* g) {
     for (int k = 0; k < 6; ++k)
       if (!std::isfinite(v[k])) return fail(MP_E_INVALID, tag + "moduli must be finite");
   }
+  if (p->n_aniso < 0 || p->n_aniso > p->n_phases) return fail(MP_E_INVALID, "n_aniso out of 0..n_phases");
+  if (p->n_aniso > 0 && !p->aniso) return fail(MP_E_INVALID, "aniso is NULL");
+  {
+    std::vector<char> listed(size_t(p->n_phases), 0);
+    for (int j = 0; j < p->n_aniso; ++j) {
+      const mp_aniso& a = p->aniso[j];
+      const std::string tag = "anisotropic record " + std::to_string(j) + ": ";
+      if (a.phase < 0 || a.phase >= p->n_phases) return fail(MP_E_INVALID, tag + "phase id out of range");
+      if (listed[a.phase]++) return fail(MP_E_INVALID, tag + "phase listed twice");
+      const mp_phase& c = p->phases[a.phase];
+      if (std::isfinite(c.tY) || std::isfinite(c.mY))
+        return fail(MP_E_INVALID, tag + "the phase must be elastic (tY = mY = inf)");
+      if (!spd9(a.A) || !spd9(a.B))
+        return fail(MP_E_INVALID, tag + "A and B must be symmetric positive definite over their index pairs");
+    }
+  }
   const long nvox = long(p->n[0]) * p->n[1] * p->n[2];
   for (long i = 0; i < nvox; ++i)
     if (p->phase[i] >= p->n_phases) return fail(MP_E_INVALID, "phase id out of range");
@@ -178,6 +234,7 @@ inline mp_status validate(const mp_problem* p, Geometry* g) {
   G.xblocks = int((G.nrows + rows - 1) / rows);
   G.txy = (G.nh % tx_wide(G.n1) == 0) ? tx_wide(G.n1) : 1;
   G.txz = (G.nh % tx_wide(G.n2) == 0) ? tx_wide(G.n2) : 1;
+  G.n_aniso = p->n_aniso;
   *g = G;
   return MP_OK;
 }
@@ -195,6 +252,7 @@ inline Layout layout(const Geometry& g, size_t w /* bytes per bulk word */) {
   L.out_pq = take(2 * g.nvox * sizeof(double));
   L.phase = take(g.nvox);
   L.params = take(256 * sizeof(PhaseC));
+  L.aniso = take(size_t(std::max(g.n_aniso, 1)) * 162 * sizeof(double));
   L.tw = take(size_t(g.n0 + g.n1 + g.n2) * 2 * w);
   L.partials = take(size_t(g.xblocks) * kNAvg * sizeof(double));
   L.ctl = take(sizeof(Ctl));
@@ -208,6 +266,7 @@ inline PhaseC derive(const mp_phase& c) {
   d.t.lam = c.lambda; d.t.mu = c.mu; d.t.kap = c.kappa;
   d.t.tY = c.tY; d.t.tH = c.tH; d.t.a1 = c.a1;
   d.t.a2 = c.a1 * c.mu / c.kappa;
+  d.t.aid = -1.0;
   d.m.alp = c.alpha; d.m.bet = c.beta; d.m.gam = c.gamma;
   d.m.mY = c.mY; d.m.mH = c.mH; d.m.b1 = c.b1;
   if (c.gamma != c.beta) {

@@ -79,6 +79,7 @@ struct XArgs {
   const T* fin;     // X_FWD_ONLY input (18 n)
   T* fout;          // X_INV_ONLY output (18 n)
   const T* eig;     // optional eigenstress (18 n): subtracted in every polarization
+  const double* aniso;  // Eq. 5 row matrices, [record][level][81] (AN kernels)
 };
 
 // deterministic sum over a 64-lane wavefront (every lane gets the total)
@@ -173,7 +174,9 @@ __device__ __forceinline__ int avg_row(int L, int j) {
 //   lds, lds2: NPK * N0 complex each (the x transforms ping-pong between
 //   them, one barrier per stage);  red: NTHR / 64 rows of kRed doubles;  tw:
 //   the N0-entry twiddle table in LDS;  tid: the thread index.
-template <class T, int MODE, int N0>
+//   AN: some phases have the general tensors of Eq. 5 (elastic phases: their
+//   stresses are the elastic law from the history base, no return map).
+template <class T, int MODE, int N0, bool AN = false>
 __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int ntiles, cx<T>* lds,
                                            cx<T>* lds2, double (*red)[kRed], const cx<T>* tw, int tid) {
   using X = XShape<N0>;
@@ -286,6 +289,12 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
     else
       cm = gread(&glob(a.params)[ph].m);
   }
+  // this lane's Eq. 5 row matrix (AN kernels), null for an Eq. 6 phase
+  const MP_GLOBAL double* an = nullptr;
+  if (AN && MODE != X_FWD_ONLY) {
+    const int aid = int(glob(&a.params[ph].t.aid)[0]);
+    if (aid >= 0) an = glob(a.aniso) + (2L * aid + lvl) * 81;
+  }
 
   if (MODE == X_TRANS && a.commit) {
     // commit (end of the step loop): final return map at the converged
@@ -296,7 +305,13 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
     for (int c = 0; c < 9; ++c) tc[c] = T(0);
     if (own) {
       T r0[9];
-      if (lvl == 0) {
+      if (AN && an) {
+        aniso_apply<T>(an, eo, r0);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) tc[c] = r0[c] + bb[c];
+        pc = hn;
+        eq = lvl == 0 ? macro_equivalent<T>(ct, tc) : micro_equivalent<T>(cm, tc);
+      } else if (lvl == 0) {
         macro_return<T>(ct, eo, bb, hn, tc, pc);
         apply_A<T>(T(ct.lam), T(ct.mu), T(ct.kap), eo, r0);
         eq = macro_equivalent<T>(ct, tc);
@@ -372,10 +387,16 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
       for (int c = 0; c < 9; ++c) t[c] = T(0);
       double pnew;
       if (own) {
-        if (lvl == 0)
+        if (AN && an) {
+          aniso_apply<T>(an, e, t);
+#pragma unroll
+          for (int c = 0; c < 9; ++c) t[c] += bb[c];
+          pnew = hn;
+        } else if (lvl == 0) {
           macro_return<T>(ct, e, bb, hn, t, pnew);
-        else
+        } else {
           micro_return<T>(cm, e, bb, hn, t, pnew);
+        }
         // polarization (Eq. 34): tau = t - A0 e ; mu = m - B0 gamma, less the
         // eigenstress when one is set (the manufactured stresses of the code
         // verification, App. D.1)
@@ -430,10 +451,15 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
         if (own) {
           T to[9];
           double pold;
-          if (lvl == 0)
+          if (AN && an) {
+            aniso_apply<T>(an, eo, to);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) to[c] += bb[c];
+          } else if (lvl == 0) {
             macro_return<T>(ct, eo, bb, hn, to, pold);
-          else
+          } else {
             micro_return<T>(cm, eo, bb, hn, to, pold);
+          }
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
             const double y = double(t[c]) - double(to[c]);
@@ -481,7 +507,7 @@ constexpr int x_min_waves() { return MODE != X_ITER ? 1 : sizeof(T) == 8 ? 3 : 4
 
 // one tile per block; every kernel of the step loop returns at once when the
 // step's control block says the loop is finished
-template <class T, int MODE, int N0>
+template <class T, int MODE, int N0, bool AN = false>
 __global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_xpass(XArgs<T> a,
                                                                                  const Ctl* ctl) {
   using X = XShape<N0>;
@@ -491,7 +517,7 @@ __global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_
   __shared__ double red[X::NTHR / 64][kRed];
   __shared__ cx<T> twl[N0];
   load_twiddles<T, N0, X::NTHR>(twl, glob(a.tw), threadIdx.x);
-  xpass_tile<T, MODE, N0>(a, blockIdx.x, gridDim.x, lds, lds2, red, twl, threadIdx.x);
+  xpass_tile<T, MODE, N0, AN>(a, blockIdx.x, gridDim.x, lds, lds2, red, twl, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

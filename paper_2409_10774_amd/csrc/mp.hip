@@ -61,6 +61,7 @@ struct mp_plan_s {
   PhaseC* params;
   void* tw0;      // cx<T>, n0 + n1 + n2 entries
   const void* eig;   // optional eigenstress (T, 18 n, caller-owned)
+  const double* aniso;   // Eq. 5 row matrices, [record][level][81]
   Ctl* ctl;
   Ctl* ctl_host;
   double* tot_host;   // pinned, kNAvg entries
@@ -147,6 +148,7 @@ struct Eng {
     a.partials = P->partials;
     a.ref = P->ref;
     a.eig = static_cast<const T*>(P->eig);
+    a.aniso = P->aniso;
     return a;
   }
 
@@ -213,7 +215,7 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     P->ctl_host->done = 0;
     // commit of the previous step, first iterate of this one (extrapolated
     // or uniform), its return map and polarization
-    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr);
+    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr, g.n_aniso > 0);
     if (pending) {
       mp_status r = record(P, rec);
       if (r != MP_OK) return r;
@@ -238,7 +240,7 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
       for (int k = 0; k < batch; ++k) {
         hipEvent_t* ev = P->prof ? &P->ev[size_t(k) * kProfEv] : nullptr;
         spectral(P, S(P), P->ctl, ev);
-        launch_x<T, X_ITER>(g.n0, g.xblocks, P->stream, xa, P->ctl);
+        launch_x<T, X_ITER>(g.n0, g.xblocks, P->stream, xa, P->ctl, g.n_aniso > 0);
         if (ev) HIP_TRY(hipEventRecord(ev[4], P->stream));
         hipLaunchKernelGGL(k_rows, dim3(kNPart), dim3(256), 0, P->stream, P->partials, g.xblocks, 0,
                            P->tot, P->ctl);
@@ -283,7 +285,7 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     // commit only: the last step of this call (or the failed one)
     xa.commit = 1;
     xa.init = 0;
-    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr);
+    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr, g.n_aniso > 0);
     mp_status r = record(P, rec);
     if (r != MP_OK) return r;
   }
@@ -340,6 +342,7 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   P->params = reinterpret_cast<PhaseC*>(wsp + L.params);
   P->tw0 = wsp + L.tw;
   P->eig = nullptr;
+  P->aniso = reinterpret_cast<const double*>(wsp + L.aniso);
   P->partials = reinterpret_cast<double*>(wsp + L.partials);
   P->ctl = reinterpret_cast<Ctl*>(wsp + L.ctl);
   P->tot = reinterpret_cast<double*>(wsp + L.tot);
@@ -364,6 +367,11 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
 
   std::vector<PhaseC> pc(256);
   for (int i = 0; i < prob->n_phases; ++i) pc[i] = derive(prob->phases[i]);
+  std::vector<double> arows(size_t(std::max(g.n_aniso, 1)) * 162, 0.0);
+  for (int j = 0; j < g.n_aniso; ++j) {
+    aniso_rows(prob->aniso[j], &arows[size_t(j) * 162]);
+    pc[prob->aniso[j].phase].t.aid = double(j);
+  }
   std::vector<cx<double>> tw;
   std::vector<cx<float>> twf;
   if (mixed) {
@@ -397,6 +405,8 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   CREATE_TRY(hipMemcpyAsync(P->phase, prob->phase, g.nvox, hipMemcpyHostToDevice, P->stream));
   CREATE_TRY(hipMemcpyAsync(P->params, pc.data(), pc.size() * sizeof(PhaseC), hipMemcpyHostToDevice,
                             P->stream));
+  CREATE_TRY(hipMemcpyAsync(wsp + L.aniso, arows.data(), arows.size() * sizeof(double),
+                            hipMemcpyHostToDevice, P->stream));
   if (mixed) {
     CREATE_TRY(hipMemcpyAsync(P->tw0, twf.data(), twf.size() * sizeof(cx<float>),
                               hipMemcpyHostToDevice, P->stream));
@@ -558,6 +568,7 @@ mp_status mp_radial_return(mp_plan P, int64_t n, const void* phase, const void* 
   if (!phase || !e || !g || !e_n || !g_n || !t_n || !m_n || !p_n || !q_n || !t || !m || !p || !q)
     return fail(MP_E_INVALID, "NULL argument");
   if (P->precision != MP_FP64) return fail(MP_E_INVALID, "FP64 plans only");
+  if (P->g.n_aniso > 0) return fail(MP_E_INVALID, "plans with Eq. 5 phases are not supported here");
   hipLaunchKernelGGL((k_rrm_points<double>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, P->stream,
                      long(n), static_cast<const uint8_t*>(phase), P->params,
                      static_cast<const double*>(e), static_cast<const double*>(g),

@@ -33,11 +33,16 @@ class mp_phase(C.Structure):
                                           "tY", "tH", "mY", "mH", "a1", "b1")]
 
 
+class mp_aniso(C.Structure):
+    _fields_ = [("phase", C.c_int32), ("A", C.c_double * 81), ("B", C.c_double * 81)]
+
+
 class mp_problem(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double), ("phase", C.POINTER(C.c_uint8)),
                 ("n_phases", C.c_int32), ("phases", C.POINTER(mp_phase)), ("ref_mode", C.c_int32),
                 ("ref", mp_phase), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("err_norm", C.c_int32), ("precision", C.c_int32)]
+                ("err_norm", C.c_int32), ("precision", C.c_int32), ("n_aniso", C.c_int32),
+                ("aniso", C.POINTER(mp_aniso))]
 
 
 class mp_batch_config(C.Structure):
@@ -153,7 +158,17 @@ def make_problem(phase_map, phases, h=1.0, tol=1e-8, max_iter=20000, err_norm="l
     prob.max_iter = int(max_iter)
     prob.err_norm = {"local": MP_ERR_LOCAL, "average": MP_ERR_AVERAGE}[err_norm]
     prob.precision = {"fp64": MP_FP64, "mixed": MP_MIXED}[precision]
-    prob._keep = (pm, arr)
+    # phases carrying general Eq. 5 tensors: A[k, l, m, n] = A_klmn and
+    # B[l, k, m, n] = B_lkmn, flattened in that index order
+    tens = [(i, p) for i, p in enumerate(phases) if getattr(p, "A", None) is not None]
+    recs = (mp_aniso * max(len(tens), 1))()
+    for j, (i, p) in enumerate(tens):
+        recs[j].phase = i
+        recs[j].A[:] = [float(v) for v in np.asarray(p.A, np.float64).reshape(81)]
+        recs[j].B[:] = [float(v) for v in np.asarray(p.B, np.float64).reshape(81)]
+    prob.n_aniso = len(tens)
+    prob.aniso = C.cast(recs, C.POINTER(mp_aniso))
+    prob._keep = (pm, arr, recs)
     return prob
 
 

@@ -338,8 +338,11 @@ def anisotropic_phase(seed: int, t_scale: float = 4.0, m_scale: float = 2.0) -> 
     and B_lkmn from random symmetric positive definite 9 x 9 matrices over
     the index pairs (kl, mn) and (lk, mn), mean eigenvalue t_scale and
     m_scale (eigenvalues within a factor of about 2).  Its isotropic constants
-    (used for the reference medium and the Eqs. 14, 17 weights) have the
-    same mean eigenvalues."""
+    (used for the reference medium and the Eqs. 14, 17 weights) bound the
+    tensors from above: every eigenvalue of their Eq. 6 tensors equals the
+    largest eigenvalue of A or B (lam = alpha = beta = 0, mu = kappa =
+    max eig A / 2, gamma = max eig B), which keeps a phase-mean reference
+    medium above half of every phase's stiffness."""
     rng = np.random.default_rng(seed)
 
     def spd(scale):
@@ -347,10 +350,10 @@ def anisotropic_phase(seed: int, t_scale: float = 4.0, m_scale: float = 2.0) -> 
         M = 0.25 * (R @ R.T) / 9.0 + np.eye(9)
         return M * (9.0 * scale / np.trace(M))
 
-    A = spd(t_scale).reshape(3, 3, 3, 3)
-    B = spd(m_scale).reshape(3, 3, 3, 3)
-    return Phase(lam=0.0, mu=0.5 * t_scale, kappa=0.5 * t_scale, alpha=0.0, beta=0.25 * m_scale,
-                 gamma=0.75 * m_scale, A=A, B=B)
+    MA, MB = spd(t_scale), spd(m_scale)
+    a_max, b_max = np.linalg.eigvalsh(MA).max(), np.linalg.eigvalsh(MB).max()
+    return Phase(lam=0.0, mu=0.5 * a_max, kappa=0.5 * a_max, alpha=0.0, beta=0.0, gamma=b_max,
+                 A=MA.reshape(3, 3, 3, 3), B=MB.reshape(3, 3, 3, 3))
 
 
 def four_spheres_16(seed: int = 5, vf: float = 0.2) -> np.ndarray:

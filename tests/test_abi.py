@@ -137,3 +137,53 @@ def test_batch_create_rejects_bad_config():
         cfg = mp.batch_config(shapes, **kw)
         st = mp.lib.mp_batch_create(mp.C.byref(cfg), mp.C.c_void_p(256), 1 << 30, None, mp.C.byref(h))
         assert st == mp.MP_E_INVALID, (kw, shapes, st)
+
+
+def aniso_problem(**change):
+    """16^3 sphere cell whose inclusion carries Eq. 5 tensors."""
+    from paper_2409_10774_amd import workloads as W
+    wl = W.single_sphere_16()
+    inc = W.anisotropic_phase(5, t_scale=3.0, m_scale=4.0)
+    for k, v in change.items():
+        setattr(inc, k, v)
+    return base_problem(phases=[wl.phases[0], inc])
+
+
+def test_accepts_anisotropic_elastic_phase():
+    from paper_2409_10774_amd import mp
+    p = aniso_problem()
+    assert p.n_aniso == 1 and p.aniso[0].phase == 1
+    assert mp.mp_plan_workspace_size(p) >= mp.mp_plan_workspace_size(base_problem())
+
+
+def _asym(A):
+    A = np.array(A, copy=True)
+    A[0, 1, 2, 2] += 0.5          # breaks A_klmn = A_mnkl
+    return A
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(tY=1.0), "must be elastic"),
+    (dict(mY=1.0), "must be elastic"),
+    ("asym", "symmetric positive definite"),
+    ("indef", "symmetric positive definite"),
+])
+def test_rejects_bad_anisotropic_phase(change, msg):
+    from paper_2409_10774_amd import mp, workloads as W
+    if change == "asym":
+        change = dict(A=_asym(W.anisotropic_phase(5).A))
+    elif change == "indef":
+        B = -np.eye(9).reshape(3, 3, 3, 3)
+        change = dict(B=B)
+    with pytest.raises(mp.MPError) as ei:
+        mp.mp_plan_workspace_size(aniso_problem(**change))
+    assert ei.value.status == mp.MP_E_INVALID and msg in str(ei.value)
+
+
+def test_batch_rejects_anisotropic_phase():
+    from paper_2409_10774_amd import mp
+    cfg = mp.batch_config([(16, 16, 16)], precision="fp64")
+    n = mp.C.c_size_t()
+    p = aniso_problem()
+    st = mp.lib.mp_batch_footprint(mp.C.byref(cfg), mp.C.byref(p), 3, mp.C.byref(n))
+    assert st == mp.MP_E_INVALID and b"plans only" in mp.lib.mp_last_error()

@@ -1,0 +1,104 @@
+"""Phases with the general centrosymmetric elastic tensors of Eq. 5 on the
+HIP path (the x pass's Eq. 5 variant), against the oracle:
+  - a homogeneous anisotropic cell: t = A:E, m = B:Gamma (index sums
+    written out), uniform;
+  - an anisotropic inclusion in a plastic matrix on a ragged grid, FP64: equal
+    iteration counts, fields and response curves within 1e-10;
+  - the same cell in mixed precision on a fixed schedule, against the FP64
+    path on that schedule.
+"""
+import numpy as np
+import pytest
+
+from oracle import micropolar as O
+from paper_2409_10774_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_10774_amd import mp as _mp
+    return _mp
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    r = np.abs(b).max()
+    return np.abs(a - b).max() / r if r > 0 else np.abs(a - b).max()
+
+
+def cell(n=(12, 6, 8), steps=3):
+    ph, _ = W.random_spheres(max(n), 11, 3, 1.5, 3.0)
+    ph = ph[: n[2], : n[1], : n[0]].copy()
+    mat = W.matrix_phase(kappa=0.5, length=1.0, tY=0.004)
+    mat.beta = 0.8 * mat.gamma
+    inc = W.anisotropic_phase(5, t_scale=3.0, m_scale=4.0)
+    times, E, G = W.ramp_path(steps, E_end=W.unit((0, 0), 0.01) + W.unit((1, 2), 0.004),
+                              G_end=W.unit((0, 1), 0.002), t_end=float(steps))
+    return W.Workload("aniso", ph, [mat, inc], times, E, G, tol=1e-8)
+
+
+def test_homogeneous_anisotropic_cell(mp):
+    say("case: homogeneous Eq. 5 cell, 8^3, 2 steps")
+    ph = W.anisotropic_phase(4)
+    pm = np.zeros((8, 8, 8), np.uint8)
+    Ev = np.array([0.3, 0.1, -0.2, 0.05, -0.4, 0.2, 0.1, 0.0, 0.25]) * 1e-2
+    Gv = np.array([0.0, 0.2, 0.1, -0.1, 0.05, 0.0, 0.3, -0.2, 0.1]) * 1e-2
+    times = np.array([0.0, 1.0, 2.0])
+    plan = mp.Plan(pm, [ph], tol=1e-12)
+    it = plan.solve(times, times[1:, None] * Ev, times[1:, None] * Gv)
+    assert max(it) <= 2, it
+    E, G = (2 * Ev).reshape(3, 3), (2 * Gv).reshape(3, 3)
+    t_ref = np.einsum("klmn,mn->kl", ph.A, E).reshape(9)
+    m_ref = np.einsum("lkmn,mn->kl", ph.B, G).reshape(9)
+    t = plan.field("t").reshape(9, -1)
+    m = plan.field("m").reshape(9, -1)
+    assert np.abs(t - t_ref[:, None]).max() < 1e-14 * np.abs(t_ref).max()
+    assert np.abs(m - m_ref[:, None]).max() < 1e-14 * np.abs(m_ref).max()
+
+
+def test_anisotropic_inclusion_fp64_vs_oracle(mp):
+    say("case: Eq. 5 inclusion in a plastic matrix, 12x6x8, 3 steps, FP64")
+    w = cell()
+    plan = mp.Plan(w.phase_map, w.phases, tol=w.tol)
+    it = plan.solve(w.times, w.E, w.G)
+    out = O.Solver(w.phase_map, w.phases, tol=w.tol).solve(w.times, w.E, w.G, fields_at=(3,))
+    say("iterations gpu", it, "oracle", out["iters"])
+    if it != out["iters"]:
+        out = O.Solver(w.phase_map, w.phases, tol=w.tol).solve(w.times, w.E, w.G, schedule=it,
+                                                               fields_at=(3,))
+    f = out["fields"][3]
+    assert f["p"].max() > 0
+    errs = {k: rel(plan.field(k), f[k]) for k in ("e", "g", "t", "m", "p", "q")}
+    say("field rel errors", errs)
+    assert max(errs.values()) < TOL
+    resp = plan.responses()[:, :40]
+    scale = np.abs(out["resp"]).max(axis=0)
+    big = scale > 1e-12 * scale.max()
+    curve = (np.abs(resp - out["resp"])[:, big].max(axis=0) / scale[big]).max()
+    say(f"curves max rel {curve:.2e}")
+    assert curve < TOL
+
+
+def test_anisotropic_inclusion_mixed_vs_fp64(mp):
+    say("case: Eq. 5 inclusion, mixed vs FP64 on a fixed schedule of 40 iterations per step")
+    w = cell()
+    f = {}
+    for prec in ("fp64", "mixed"):
+        plan = mp.Plan(w.phase_map, w.phases, tol=w.tol, precision=prec)
+        plan.set_fixed_iterations(40)
+        plan.solve(w.times, w.E, w.G)
+        f[prec] = {k: plan.field(k) for k in ("e", "g", "t", "m")}
+    errs = {k: rel(f["mixed"][k], f["fp64"][k]) for k in f["fp64"]}
+    say("mixed vs fp64 field rel", errs)
+    assert max(errs.values()) < 1e-5

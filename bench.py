@@ -76,11 +76,12 @@ WORKLOADS = {
 
 
 def cpu_baseline(wl, iters=2):
+    """The oracle, untuned, on a bounded sample: load step 1 of the same cell
+    with a fixed schedule of `iters` loop iterations (one above 128^3), one
+    thread (setup excluded)."""
     nvox = wl.phase_map.size
     if nvox > 128 ** 3:
         iters = 1
-    """The oracle, untuned, on a bounded sample: load step 1 of the same cell
-    with a fixed schedule of `iters` loop iterations (setup excluded)."""
     from threadpoolctl import threadpool_limits
     from oracle import micropolar as O
     with threadpool_limits(limits=1):

@@ -195,15 +195,17 @@ mp_status mp_radial_return(mp_plan plan, int64_t n_vox, const void* phase,
                            const void* t_n, const void* m_n, const void* p_n, const void* q_n,
                            void* t, void* m, void* p, void* q);
 
-/* Per-kernel timing of loop iterations, for measurement.  With enable != 0
- * the plan records hipEvents on its stream between the kernels of every
- * iteration that runs and accumulates their durations (counters reset on
- * every call).  mp_profile_read fills ms_total[j] (milliseconds) and
- * launches[j] for j < min(n, 5), kernel j in iteration order: 0 y forward,
- * 1 z forward + Green operator + z inverse, 2 y inverse, 3 x pass (inverse
- * x transform, return maps, error partials, polarization, forward x
- * transform), 4 error reduction.  Adds event records between kernels. */
-mp_status mp_profile(mp_plan plan, int32_t enable);
+/* Per-kernel timing of loop iterations, for measurement.  mode 1: the plan
+ * records hipEvents on its stream between the kernels of every iteration
+ * that runs and accumulates their durations; mode 2: events around the x
+ * pass only (two records per iteration, the least added to the loop);
+ * mode 0: off.  Counters reset on every call.  mp_profile_read fills
+ * ms_total[j] (milliseconds) and launches[j] for j < min(n, 5), kernel j in
+ * iteration order: 0 y forward, 1 z forward + Green operator + z inverse,
+ * 2 y inverse, 3 x pass (inverse x transform, return maps, error partials,
+ * polarization, forward x transform), 4 error reduction.  Each event record
+ * adds a few microseconds between two kernels. */
+mp_status mp_profile(mp_plan plan, int32_t mode);
 mp_status mp_profile_read(mp_plan plan, int32_t n, double* ms_total, int64_t* launches);
 
 void mp_plan_destroy(mp_plan plan);

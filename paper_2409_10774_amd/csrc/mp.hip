@@ -73,7 +73,7 @@ struct mp_plan_s {
   double t_prev, t_cur;   // times of the last two committed states
   std::vector<std::vector<double>> resp_hist;
   // optional per-kernel timing of loop iterations (hipEvents on the plan's stream)
-  bool prof;
+  int prof;   // 0 off, 1 every loop kernel, 2 the x pass only
   std::vector<hipEvent_t> ev;
   double prof_ms[8];
   long prof_n[8];
@@ -238,14 +238,17 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
         for (size_t i = old; i < P->ev.size(); ++i) HIP_TRY(hipEventCreate(&P->ev[i]));
       }
       for (int k = 0; k < batch; ++k) {
+        // profiling: events between all loop kernels (mode 1) or around the
+        // x pass only (mode 2, two event records per iteration)
         hipEvent_t* ev = P->prof ? &P->ev[size_t(k) * kProfEv] : nullptr;
-        spectral(P, S(P), P->ctl, ev);
+        spectral(P, S(P), P->ctl, P->prof == 1 ? ev : nullptr);
+        if (P->prof == 2) HIP_TRY(hipEventRecord(ev[3], P->stream));
         launch_x<T, X_ITER>(g.n0, g.xblocks, P->stream, xa, P->ctl, g.n_aniso > 0);
         if (ev) HIP_TRY(hipEventRecord(ev[4], P->stream));
         hipLaunchKernelGGL(k_rows, dim3(kNPart), dim3(256), 0, P->stream, P->partials, g.xblocks, 0,
                            P->tot, P->ctl);
         hipLaunchKernelGGL(k_err_final, dim3(1), dim3(64), 0, P->stream, P->tot, g.nvox, P->ctl, em);
-        if (ev) HIP_TRY(hipEventRecord(ev[5], P->stream));
+        if (P->prof == 1) HIP_TRY(hipEventRecord(ev[5], P->stream));
       }
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P->stream));
@@ -255,6 +258,7 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
         const int ran = std::min(batch, P->ctl_host->iters - it0);
         for (int k = 0; k < ran; ++k)
           for (int j = 0; j < kProfEv - 1; ++j) {
+            if (P->prof == 2 && j != 3) continue;
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, P->ev[size_t(k) * kProfEv + j],
                                         P->ev[size_t(k) * kProfEv + j + 1]));
@@ -350,7 +354,7 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   P->max_iter = prob->max_iter;
   P->norm = prob->err_norm;
   P->fixed = 0;
-  P->prof = false;
+  P->prof = 0;
   for (int j = 0; j < 8; ++j) { P->prof_ms[j] = 0.0; P->prof_n[j] = 0; }
   P->n_phases = prob->n_phases;
   P->steps = 0;
@@ -428,9 +432,10 @@ void mp_plan_destroy(mp_plan P) {
   delete P;
 }
 
-mp_status mp_profile(mp_plan P, int32_t enable) {
+mp_status mp_profile(mp_plan P, int32_t mode) {
   if (!P) return fail(MP_E_INVALID, "plan is NULL");
-  P->prof = enable != 0;
+  if (mode < 0 || mode > 2) return fail(MP_E_INVALID, "profile mode must be 0, 1 or 2");
+  P->prof = mode;
   for (int j = 0; j < 8; ++j) {
     P->prof_ms[j] = 0.0;
     P->prof_n[j] = 0;

@@ -302,7 +302,10 @@ class Plan:
     KERNELS = ("y_fwd", "z_green", "y_inv", "x_pass", "err_reduce")
 
     def profile(self, enable=True):
-        check(lib.mp_profile(self.handle, 1 if enable else 0))
+        """True / 1: events between all loop kernels; 2: around the x pass
+        only; False / 0: off (mp_profile)."""
+        mode = 1 if enable is True else 0 if enable is False else int(enable)
+        check(lib.mp_profile(self.handle, mode))
 
     def profile_read(self):
         """{kernel: (total ms, launches)} accumulated since profile(True)."""

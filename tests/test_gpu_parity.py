@@ -311,3 +311,27 @@ def test_manufactured_solution_app_d1(torch, mp):
             assert err_man < c["bound"], (s, k, err_man)
             assert err_orc < TOL, (s, k, err_orc)
     plan.set_eigenstress(None)
+
+
+def test_profile_modes(torch, mp):
+    """mp_profile: mode 1 times every loop kernel, mode 2 the x pass only,
+    and neither changes the results."""
+    say("case: profiling modes on 8^3, 2 steps")
+    wl = small_workload((8, 8, 8), seed=5, steps=2)
+    fields, counts = [], []
+    for mode in (0, 1, 2):
+        plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol)
+        plan.profile(mode)
+        it = plan.solve(wl.times, wl.E, wl.G)
+        prof = plan.profile_read()
+        counts.append({k: n for k, (ms, n) in prof.items()})
+        fields.append(plan.field("t"))
+        plan.close()
+    n = sum(it)
+    assert all(v == 0 for v in counts[0].values())
+    assert all(v == n for v in counts[1].values()), counts[1]
+    assert counts[2]["x_pass"] == n and sum(counts[2].values()) == n, counts[2]
+    assert np.array_equal(fields[0], fields[1]) and np.array_equal(fields[0], fields[2])
+    with pytest.raises(mp.MPError):
+        plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol)
+        plan.profile(3)

@@ -75,7 +75,7 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(wl, iters=2):
+def cpu_baseline(wl, iters=4):
     """The oracle, untuned, on a bounded sample: load step 1 of the same cell
     with a fixed schedule of `iters` loop iterations (one above 128^3), one
     thread (setup excluded)."""

@@ -335,3 +335,24 @@ def test_profile_modes(torch, mp):
     with pytest.raises(mp.MPError):
         plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol)
         plan.profile(3)
+
+
+def test_iterations_grow_as_hardening_vanishes(torch, mp):
+    """The paper's observation that the basic scheme needs more iterations
+    as the hardening moduli go to zero (Sec. 3.4), on the 16^3 sphere cell
+    over 6 steps; the softest case also matches the oracle's counts."""
+    say("case: iterations vs hardening, 16^3 sphere, 6 steps")
+    totals = []
+    for tH in (0.1, 0.01, 0.0):
+        wl = W.single_sphere_16()
+        for p in wl.phases:
+            if math.isfinite(p.tY):
+                p.tH = p.mH = tH
+        plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol)
+        it = plan.solve(wl.times[:7], wl.E[:6], wl.G[:6])
+        say(f"tH = mH = {tH}: iterations {it}")
+        totals.append(sum(it))
+        plan.close()
+    assert totals[0] < totals[1] < totals[2], totals
+    out = O.Solver(wl.phase_map, wl.phases, tol=wl.tol).solve(wl.times[:7], wl.E[:6], wl.G[:6])
+    assert sum(abs(a - b) for a, b in zip(it, out["iters"])) <= 1, (it, out["iters"])

@@ -234,9 +234,10 @@ typedef struct {
   int32_t iters_per_launch;  /* loop iterations per graph launch, 1..64 */
   int32_t autotune;          /* 1: at creation, time each class's y / z tile
                                 widths {1, wide/2, wide} with the full
-                                persistent grid and a quarter of it and keep
-                                the fastest (cached per shape for the
-                                process); 0: the single-plan tile widths */
+                                persistent grid, a quarter of it and the
+                                blocks the chip holds at once, and keep the
+                                fastest (cached per shape for the process);
+                                0: the single-plan tile widths */
 } mp_batch_config;
 
 enum { MP_RVE_RUNNING = 0, MP_RVE_DONE = 1 };

@@ -173,7 +173,7 @@ bool x_kernel(int n0, const void** fn, int* nthr) {
 #define MP_CASE(N)                                                 \
   case N:                                                          \
     *fn = reinterpret_cast<const void*>(&k_batch_x<T, MODE, N>);   \
-    *nthr = XShape<N>::NTHR;                                       \
+    *nthr = XShape<T, N>::NTHR;                                    \
     return true;
     MP_SIZES(MP_CASE)
 #undef MP_CASE
@@ -220,7 +220,8 @@ struct BEng {
     void* args[] = {&rvp, &lsp, &cls, &tiles};
     // transitions are rare (once per step of an RVE): a grid that fills the
     // chip about once, so that an iteration without any costs little
-    const int grid = mode == X_ITER ? C.xgrid : std::min(C.xgrid, 4 * B->cus);
+    // a multiple of 16: the two levels of an item then share an XCD (x_item)
+    const int grid = ((mode == X_ITER ? C.xgrid : std::min(C.xgrid, 4 * B->cus)) + 15) / 16 * 16;
     return launch(fn, grid, nthr, 0, s, args);
   }
 

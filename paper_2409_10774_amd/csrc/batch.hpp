@@ -69,25 +69,31 @@ struct Lists {
 // x pass of one shape class: ITER over the RUN list, or TRANS over the
 // TRANS list (separate kernels, so each keeps its own register budget)
 template <class T, int MODE, int N0>
-__global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_batch_x(const Rve<T>* __restrict__ rv,
+__global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE>())) k_batch_x(const Rve<T>* __restrict__ rv,
                                                               const Lists* __restrict__ ls, int cls,
                                                               int tiles) {
-  using X = XShape<N0>;
+  using X = XShape<T, N0>;
   __shared__ cx<T> lds[X::NPK * N0];
   __shared__ cx<T> lds2[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
   __shared__ cx<T> twl[N0];
   const int n = MODE == X_ITER ? ls->ns[cls] : ls->nt[cls];
   const int* list = MODE == X_ITER ? ls->s[cls] : ls->t[cls];
-  const int total = n * tiles;
+  const long total = long(n) * tiles;   // (RVE, tile) items, two levels each
+  if (total == 0) return;
   // every RVE of a class has the same twiddles: load them once per block
-  if (int(blockIdx.x) < total)
-    load_twiddles<T, N0, X::NTHR>(twl, glob(rv[list[blockIdx.x / tiles]].x.tw), threadIdx.x);
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int slot = list[w / tiles];
-    const int tile = w % tiles;
+  load_twiddles<T, N0, X::NTHR>(twl, glob(rv[list[0]].x.tw), threadIdx.x);
+  // items w -> ((RVE, tile), first level) as x_item; the grid is a multiple
+  // of 16, so the two levels of an item in separate blocks run on one XCD
+  for (long w = blockIdx.x; w < x_grid<X::LPB>(total); w += gridDim.x) {
+    long u;
+    int lvl;
+    x_item<X::LPB>(w, &u, &lvl);
+    if (u >= total) continue;
+    const int slot = list[u / tiles];
+    const int tile = int(u % tiles);
     __syncthreads();   // the previous item is done with LDS
-    xpass_tile<T, MODE, N0>(rv[slot].x, tile, tiles, lds, lds2, red, twl, fresh_tid());
+    xpass_tile<T, MODE, N0>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid());
   }
 }
 

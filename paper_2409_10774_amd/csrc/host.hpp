@@ -59,14 +59,18 @@ inline int x_rows(int n0) { return n0 >= 128 ? 1 : 128 / n0; }
 template <class T, int MODE>
 void launch_x(int n0, int blocks, hipStream_t s, const XArgs<T>& a, const Ctl* ctl, bool an = false) {
   constexpr bool LAW = MODE == X_ITER || MODE == X_TRANS;
+  // blocks = row tiles; x_grid gives the blocks that run their levels
   switch (n0) {
-#define MP_CASE(N)                                                                                    \
-  case N:                                                                                             \
-    if (LAW && an)                                                                                    \
-      hipLaunchKernelGGL((k_xpass<T, MODE, N, LAW>), dim3(blocks), dim3(XShape<N>::NTHR), 0, s, a, ctl); \
-    else                                                                                              \
-      hipLaunchKernelGGL((k_xpass<T, MODE, N>), dim3(blocks), dim3(XShape<N>::NTHR), 0, s, a, ctl);   \
-    break;
+#define MP_CASE(N)                                                                              \
+  case N: {                                                                                     \
+    using X = XShape<T, N>;                                                                     \
+    const dim3 grid(unsigned(x_grid<X::LPB>(blocks)));                                          \
+    if (LAW && an)                                                                              \
+      hipLaunchKernelGGL((k_xpass<T, MODE, N, LAW>), grid, dim3(X::NTHR), 0, s, a, ctl, blocks); \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_xpass<T, MODE, N>), grid, dim3(X::NTHR), 0, s, a, ctl, blocks);      \
+    break;                                                                                      \
+  }
     MP_SIZES(MP_CASE)
 #undef MP_CASE
   }

@@ -129,18 +129,43 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// x-pass launch shape for a row length N0: ROWS rows per tile (the last
-// tile may be ragged), two lanes per voxel (one per Alg. 1 level), each
-// level padded to whole wavefronts.
-template <int N0>
+// x-pass launch shape for a row length N0 in precision T: ROWS rows per tile
+// (the last tile may be ragged), one lane per voxel and Alg. 1 level, each
+// level padded to whole wavefronts.  The levels are independent through the
+// whole pass (transforms, return map, error partials), so a block runs LPB
+// of them: both (FP64 rows up to 128, the faster form there) or one, which
+// halves the block's LDS (5 pencils per row instead of 10) and lets more
+// blocks share a CU (FP64 rows of 256: three blocks per CU instead of one).
+template <class T, int N0>
 struct XShape {
+  static constexpr int LPB = (sizeof(T) == 8 && N0 <= 128) ? 2 : 1;
   static constexpr int ROWS = N0 >= 128 ? 1 : 128 / N0;
   static constexpr int VPB = ROWS * N0;
   static constexpr int VPAD = (VPB + 63) / 64 * 64;
-  static constexpr int NTHR = 2 * VPAD;
+  static constexpr int NTHR = LPB * VPAD;
   static constexpr int NH = N0 / 2;
-  static constexpr int NPK = 10 * ROWS;   // complex pencils held in LDS
+  static constexpr int NPK = 5 * LPB * ROWS;   // complex pencils held in LDS
 };
+
+// Block b of an x-pass grid -> (tile, first level).  With both levels in a
+// block, block b is tile b.  With one, blocks b and b + 8 take the two levels
+// of one tile: the chip deals consecutive blocks to its 8 XCDs in turn, so
+// both run on one XCD at about the same time and the spectrum lines they
+// share (the two levels' components interleave in one run per kx) are
+// fetched into one L2 once.  Tiles >= ntiles (padding to a multiple of 8)
+// have no work.
+template <int LPB>
+__device__ __forceinline__ void x_item(long b, long* tile, int* lvl0) {
+  if (LPB == 2) {
+    *lvl0 = 0;
+    *tile = b;
+  } else {
+    *lvl0 = int((b >> 3) & 1);
+    *tile = (b >> 4) * 8 + (b & 7);
+  }
+}
+template <int LPB>
+constexpr long x_grid(long ntiles) { return LPB == 2 ? ntiles : 2 * ((ntiles + 7) / 8 * 8); }
 
 // Real fields packed two per complex pencil for the x transforms, only like
 // with like: pencils 0-3 carry strain-like components 0-7 in pairs, pencil 4
@@ -164,22 +189,24 @@ __device__ __forceinline__ int avg_row(int L, int j) {
   return j < 9 ? L * 9 + j : j < 18 ? 18 + L * 9 + (j - 9) : j == 18 ? 36 + L : 38 + L;
 }
 
-// x pass over one tile of ROWS rows of N0 voxels, all 18 components, held in
-// LDS as 10 complex pencils per row (two real transforms in one complex
-// transform).  Lanes [0, VPAD) run the macro level of Alg. 1 (e -> t, tau),
-// lanes [VPAD, 2 VPAD) the micro level (gamma -> m, mu): the levels are
-// independent, which halves each lane's live state, and the level is uniform
-// over each wavefront.  Each lane prefetches its old strain, history base and
-// p_n / q_n before the transforms so the loads overlap them.
+// x pass over levels [lvl0, lvl0 + LPB) of one tile of ROWS rows of N0
+// voxels: level 0 the macro level of Alg. 1 (e -> t, tau; components 0..8),
+// level 1 the micro level (gamma -> m, mu; components 9..17), each level's 9
+// fields held in LDS as 5 complex pencils per row (two real transforms in one
+// complex transform).  Lanes [0, VPAD) run level lvl0, lanes [VPAD, 2 VPAD)
+// level lvl0 + 1 when the block has both: the level is uniform over each
+// wavefront.
+// Each lane prefetches its old strain, history base and p_n / q_n before the
+// transforms so the loads overlap them.
 //   lds, lds2: NPK * N0 complex each (the x transforms ping-pong between
 //   them, one barrier per stage);  red: NTHR / 64 rows of kRed doubles;  tw:
 //   the N0-entry twiddle table in LDS;  tid: the thread index.
 //   AN: some phases have the general tensors of Eq. 5 (elastic phases: their
 //   stresses are the elastic law from the history base, no return map).
 template <class T, int MODE, int N0, bool AN = false>
-__device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int ntiles, cx<T>* lds,
+__device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl0, int ntiles, cx<T>* lds,
                                            cx<T>* lds2, double (*red)[kRed], const cx<T>* tw, int tid) {
-  using X = XShape<N0>;
+  using X = XShape<T, N0>;
   constexpr int ROWS = X::ROWS, VPB = X::VPB, VPAD = X::VPAD, NTHR = X::NTHR, NH = X::NH;
   constexpr int NPK = X::NPK;
   // buffer holding the spatial-domain pencils after the inverse transform,
@@ -190,9 +217,12 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
   cx<T>* const other = SP2 ? lds : lds2;
   cx<T>* const fq = ODD ? other : sp;
   T* ldr = reinterpret_cast<T*>(sp);
+  constexpr int KP = kPencils / 2;     // pencils of one level
+  constexpr int KPB = KP * X::LPB;     // pencils of the block's levels, per row
   const long row0 = tile * ROWS;
-  const int lvl = __builtin_amdgcn_readfirstlane(tid >= VPAD ? 1 : 0);
-  const int v = tid - lvl * VPAD;
+  // (both levels in the block: lvl0 = 0)
+  const int lvl = X::LPB == 2 ? __builtin_amdgcn_readfirstlane(tid >= VPAD ? 1 : 0) : lvl0;
+  const int v = tid - (lvl - lvl0) * VPAD;
   const int vr = v < VPB ? v / N0 : 0, vx = v < VPB ? v % N0 : 0;
   const bool own = v < VPB && row0 + vr < a.nrows;
   // 32-bit voxel offset into wave-uniform component bases (at most 2^24 voxels)
@@ -224,10 +254,10 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
 
   if (MODE == X_ITER || MODE == X_INV_ONLY) {
     // half spectra -> packed full spectra Z = A + i B, Z(n0 - k) = conj A + i conj B
-    const int items = rows_here * NH * kPencils;
+    const int items = rows_here * NH * KPB;
     auto get = [&](int w, cx<T>& A, cx<T>& B) {
-      const int r = w / (NH * kPencils), rem = w % (NH * kPencils);
-      const int kx = rem / kPencils, q = rem % kPencils;
+      const int r = w / (NH * KPB), rem = w % (NH * KPB);
+      const int kx = rem / KPB, q = lvl0 * KP + rem % KPB;
       const MP_GLOBAL cx<T>* srow = S + (row0 + r) * (NH * 18) + kx * 18;
       const int cim = pencil_im(q);
       A = gload(srow + pencil_re(q));
@@ -235,9 +265,9 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
       if (cim >= 0) B = gload(srow + cim);
     };
     auto put = [&](int w, cx<T> A, cx<T> B) {
-      const int r = w / (NH * kPencils), rem = w % (NH * kPencils);
-      const int kx = rem / kPencils, q = rem % kPencils;
-      cx<T>* pen = lds + (r * kPencils + q) * N0;
+      const int r = w / (NH * KPB), rem = w % (NH * KPB);
+      const int kx = rem / KPB, ql = rem % KPB;
+      cx<T>* pen = lds + (r * KPB + ql) * N0;
       pen[kx] = cx<T>{A.re - B.im, A.im + B.re};
       if (kx > 0)
         pen[N0 - kx] = cx<T>{A.re + B.im, B.re - A.im};
@@ -247,7 +277,7 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
     if constexpr (sizeof(T) == 8) {
       // FP64: every load of the thread is issued before the first is waited
       // for (measured faster; in FP32 the streaming loop below is faster)
-      constexpr int MBX = (ROWS * NH * kPencils + NTHR - 1) / NTHR;
+      constexpr int MBX = (ROWS * NH * KPB + NTHR - 1) / NTHR;
       cx<T> A[MBX], B[MBX];
 #pragma unroll
       for (int j = 0; j < MBX; ++j)
@@ -266,8 +296,8 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
     fft_pp<T, true, N0, 1, NPK, 1, N0, false, NTHR>(lds, lds2, tw, tid);
   }
 
-  // LDS scalar slot of field c (0..17) of this lane's voxel
-  auto slot = [&](int c) { return 2 * ((vr * kPencils + pencil_of(c)) * N0 + vx) + part_of(c); };
+  // LDS scalar slot of field c (0..17, of the block's levels) of this lane's voxel
+  auto slot = [&](int c) { return 2 * ((vr * KPB + pencil_of(c) - lvl0 * KP) * N0 + vx) + part_of(c); };
 
   if (MODE == X_INV_ONLY) {
     if (own)
@@ -343,9 +373,9 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
       wave_reduce<4>(w, 0u, lane, red[wv] + 16);
     }
     __syncthreads();
-    if (tid < kNAvg) {
-      const int L = tid / 20, j = tid % 20;
-      const int w0 = L * (VPAD / 64), w1 = w0 + VPAD / 64;
+    if (tid < X::LPB * kNAvg / 2) {   // 20 rows per level, its waves in order
+      const int L = lvl0 + tid / 20, j = tid % 20;
+      const int w0 = (L - lvl0) * (VPAD / 64), w1 = w0 + VPAD / 64;
       double y = red[w0][j];
       for (int w = w0 + 1; w < w1; ++w) y += red[w][j];
       partials[(long)avg_row(L, j) * ntiles + tile] = y;
@@ -376,7 +406,7 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
     }
     // the single-field pencil of this level (4 or 9) has no imaginary field:
     // clear it, the transform must not read stale LDS
-    if (own) ldr[2 * ((vr * kPencils + (lvl ? 9 : 4)) * N0 + vx) + 1] = T(0);
+    if (own) ldr[2 * ((vr * KPB + (lvl - lvl0) * KP + KP - 1) * N0 + vx) + 1] = T(0);
     if (MODE == X_FWD_ONLY) {
       if (own)
 #pragma unroll
@@ -472,14 +502,13 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
           wave_reduce<2>(w, 0x1u, lane, red[wv] + 16);
         }
         __syncthreads();
-        if (tid < kNPart) {
-          const int L = tid / kLev, j = tid % kLev;
+        if (tid < X::LPB * kLev) {   // kLev rows per level, its waves in order
+          const int L = lvl0 + tid / kLev, j = tid % kLev;
           const int jj = j == 1 ? 16 : j == 3 ? 17 : j;
-          // waves [0, VPAD/64) hold level 0, the rest level 1
-          const int w0 = L * (VPAD / 64), w1 = w0 + VPAD / 64;
+          const int w0 = (L - lvl0) * (VPAD / 64), w1 = w0 + VPAD / 64;
           double y = red[w0][jj];
           for (int w = w0 + 1; w < w1; ++w) y = (j < 2) ? nmax(y, red[w][jj]) : y + red[w][jj];
-          partials[(long)tid * ntiles + tile] = y;
+          partials[(long)(L * kLev + j) * ntiles + tile] = y;
         }
       }
     }
@@ -487,10 +516,10 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
   __syncthreads();
   fft_pp<T, false, N0, 1, NPK, 1, N0, false, NTHR>(sp, other, tw, tid);
   // unpack: A = (Z(k) + conj Z(-k)) / 2, B = (Z(k) - conj Z(-k)) / (2 i)
-  for (int w = tid; w < rows_here * NH * kPencils; w += NTHR) {
-    const int r = w / (NH * kPencils), rem = w % (NH * kPencils);
-    const int kx = rem / kPencils, q = rem % kPencils;
-    const cx<T>* pen = fq + (r * kPencils + q) * N0;
+  for (int w = tid; w < rows_here * NH * KPB; w += NTHR) {
+    const int r = w / (NH * KPB), rem = w % (NH * KPB);
+    const int kx = rem / KPB, ql = rem % KPB, q = lvl0 * KP + ql;
+    const cx<T>* pen = fq + (r * KPB + ql) * N0;
     const cx<T> zk = pen[kx];
     const cx<T> zm = pen[kx == 0 ? 0 : N0 - kx];
     MP_GLOBAL cx<T>* srow = S + (row0 + r) * (NH * 18) + kx * 18;
@@ -505,19 +534,30 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int nti
 template <class T, int MODE>
 constexpr int x_min_waves() { return MODE != X_ITER ? 1 : sizeof(T) == 8 ? 3 : 4; }
 
-// one tile per block; every kernel of the step loop returns at once when the
-// step's control block says the loop is finished
+// the levels of one tile per block (x_item; grid x_grid(ntiles)); every
+// kernel of the step loop returns at once when the step's control block says
+// the loop is finished
 template <class T, int MODE, int N0, bool AN = false>
-__global__ void __launch_bounds__(XShape<N0>::NTHR, (x_min_waves<T, MODE>())) k_xpass(XArgs<T> a,
-                                                                                 const Ctl* ctl) {
-  using X = XShape<N0>;
+__global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE>())) k_xpass(XArgs<T> a,
+                                                                                       const Ctl* ctl,
+                                                                                       int ntiles) {
+  using X = XShape<T, N0>;
   if (ctl && ctl->done) return;
   __shared__ cx<T> lds[X::NPK * N0];
   __shared__ cx<T> lds2[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
   __shared__ cx<T> twl[N0];
-  load_twiddles<T, N0, X::NTHR>(twl, glob(a.tw), threadIdx.x);
-  xpass_tile<T, MODE, N0, AN>(a, blockIdx.x, gridDim.x, lds, lds2, red, twl, threadIdx.x);
+  if constexpr (X::LPB == 2) {   // grid = ntiles, block b is tile b
+    load_twiddles<T, N0, X::NTHR>(twl, glob(a.tw), threadIdx.x);
+    xpass_tile<T, MODE, N0, AN>(a, blockIdx.x, 0, gridDim.x, lds, lds2, red, twl, threadIdx.x);
+  } else {
+    long tile;
+    int lvl;
+    x_item<X::LPB>(blockIdx.x, &tile, &lvl);
+    if (tile >= ntiles) return;
+    load_twiddles<T, N0, X::NTHR>(twl, glob(a.tw), threadIdx.x);
+    xpass_tile<T, MODE, N0, AN>(a, tile, lvl, ntiles, lds, lds2, red, twl, threadIdx.x);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -63,6 +63,10 @@ WORKLOADS = {
         precision="mixed", dtype="f32 bulk / f64 reductions",
         desc="spheres256_mixed: 256^3 voxels, random elastic spheres r~U[5,15] to volume fraction "
              "0.25, contrast 10, E11->0.01 over 20 steps, tol 1e-6 (Eq. 38), FP32 bulk arithmetic"),
+    "spheres256_fp64": dict(
+        precision="fp64", dtype="f64",
+        desc="spheres256_fp64: the 256^3 cell of spheres256_mixed in FP64 (the reference of the "
+             "mixed form), tol 1e-6 (Eq. 38)"),
     "batch64_mixed": dict(
         precision="mixed", dtype="f32 bulk / f64 reductions",
         desc="batch64_mixed: 64 resident RVEs, edge U{32,64,96,128}, 1-60 spheres r~U[n/20,n/10], "
@@ -276,7 +280,7 @@ def main():
     cfg = WORKLOADS[args.workload]
     if args.workload == "spheres128_fp64":
         wl = W.random_spheres_128(n_steps=W_ + K)
-    else:
+    else:   # spheres256_mixed, spheres256_fp64
         wl = W.random_spheres_256(n_steps=W_ + K)
     nvox = wl.phase_map.size
     BYTES_PER_VOXEL = bytes_per_voxel(8 if cfg["precision"] == "fp64" else 4)

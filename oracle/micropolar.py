@@ -8,6 +8,8 @@ Written from the paper, step by step, in its notation:
   * micropolar radial-return mapping                            -- Alg. 1
   * polarization stresses                                       -- Eq. 34
   * reference-medium Green operator, applied per frequency      -- Eqs. 33-35
+  * reference medium A0 = <A(x)>, B0 = <B(x)>, isotropic or as
+    general tensors of the phases' Eq. 5 / Eq. 6 laws             -- Alg. 2
   * error measure                                               -- Eqs. 36-38
   * elastoplastic FFT-based basic scheme                        -- Alg. 2
 
@@ -15,8 +17,8 @@ Readings of points the paper leaves open (each listed in the design notes):
   - The Green tensors are only cited.  Here they are not written out: for
     every frequency the oracle assembles the 6x6 Fourier symbol of the
     reference-medium balance operator (Eqs. 1, 2 with no body force/couple,
-    Eq. 6 stiffnesses) by applying it to unit displacement / microrotation
-    amplitudes, and solves it with numpy.linalg.solve.  The uniform part
+    the reference stiffnesses) by applying it to unit displacement /
+    microrotation amplitudes, and inverts it with numpy.linalg.inv.  The uniform part
     A0:E of the second polarization only lives at k = 0, where the
     fluctuation is zero, so it never enters.
   - Continuous frequencies xi = 2 pi m / (n h); at k = 0 and at every
@@ -256,7 +258,14 @@ def reference_medium(phase_map, phases, mode="phase_mean"):
     "volume_mean": <A(x)>, <B(x)> over the cell (Alg. 2).  For isotropic
     phases this is the volume average of each modulus.
     "phase_mean": unweighted mean of each modulus over the phases present.
+    "tensor_mean", "tensor_phase_mean": the same two means taken over every
+    phase's own tensors; they return the pair (A0, B0) of tensors instead of
+    constants (see reference_tensors).
     """
+    if mode == "tensor_mean":
+        return reference_tensors(phase_map, phases)
+    if mode == "tensor_phase_mean":
+        return reference_tensors(phase_map, phases, weights="phase")
     tab = phase_table(phases)[:, :6]
     pm = np.asarray(phase_map).astype(np.intp)
     if mode == "volume_mean":
@@ -265,6 +274,26 @@ def reference_medium(phase_map, phases, mode="phase_mean"):
         present = np.unique(pm)
         return tuple(float(v) for v in tab[present].mean(axis=0))
     raise ValueError(mode)
+
+
+def reference_tensors(phase_map, phases, weights="volume"):
+    """Alg. 2 taken literally: A0 = <A(x)>, B0 = <B(x)> over the cell, with
+    the Eq. 5 tensors of a phase that has them (A, B attributes) and the
+    Eq. 6 tensors of the others.  weights="phase": the unweighted mean over
+    the phases present instead.  B0 in index order (l, k, m, n)."""
+    pm = np.asarray(phase_map).astype(np.intp)
+    tab = phase_table(phases)[:, :6]
+    present = np.unique(pm)
+    A0 = np.zeros((3, 3, 3, 3))
+    B0 = np.zeros((3, 3, 3, 3))
+    for ph in present:
+        w = np.count_nonzero(pm == ph) / pm.size if weights == "volume" else 1.0 / len(present)
+        lam, mu, kap, alp, bet, gam = tab[ph]
+        A = getattr(phases[ph], "A", None)
+        B = getattr(phases[ph], "B", None)
+        A0 += w * (stiffness_A(lam, mu, kap) if A is None else np.asarray(A, float))
+        B0 += w * (stiffness_B(alp, bet, gam) if B is None else np.asarray(B, float))
+    return A0, B0
 
 
 def frequencies(n, h, half=True):
@@ -315,13 +344,20 @@ class GreenOperator:
     balance residual is assembled column by column from unit amplitudes and
     inverted once per frequency (the paper allows the Green tensors to be
     pre-computed and stored).
+
+    ref: the six Eq. 6 constants of an isotropic reference medium, or a pair
+    (A0, B0) of general tensors (B0 in index order (l, k, m, n)).
     """
 
     def __init__(self, n, h, ref, chunk=1 << 16):
         self.n, self.h = tuple(int(v) for v in n), float(h)
-        lam, mu, kappa, alpha, beta, gamma = ref
-        self.A0 = stiffness_A(lam, mu, kappa)
-        self.B0 = stiffness_B(alpha, beta, gamma)
+        if len(ref) == 2:
+            self.A0 = np.asarray(ref[0], float).reshape(3, 3, 3, 3)
+            self.B0 = np.asarray(ref[1], float).reshape(3, 3, 3, 3)
+        else:
+            lam, mu, kappa, alpha, beta, gamma = ref
+            self.A0 = stiffness_A(lam, mu, kappa)
+            self.B0 = stiffness_B(alpha, beta, gamma)
         xi1, xi2, xi3, nyq = frequencies(self.n, self.h, half=True)
         shp = nyq.shape
         X = np.stack(np.broadcast_arrays(xi1 + 0 * xi2 + 0 * xi3,
@@ -416,6 +452,9 @@ class Solver:
 
     phase_map (n2, n1, n0) uint8; phases: list of constant records; h voxel
     size; tol = epsilon; norm "local" (Eq. 38) or "average" (Eq. 37).
+    ref_mode "phase_mean", "volume_mean" (isotropic reference media) or
+    "tensor_mean", "tensor_phase_mean" (the same means of the phases'
+    tensors); ref overrides it with six constants or a pair of tensors.
     eigen_t, eigen_m: optional manufactured stresses subtracted inside the
     polarization (verification form of the first loop line), callable
     step -> (9, n2, n1, n0) arrays.

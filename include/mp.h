@@ -55,7 +55,21 @@ typedef enum {
 
 enum { MP_FP64 = 0, MP_MIXED = 1 };                 /* arithmetic of the bulk fields */
 enum { MP_ERR_LOCAL = 0, MP_ERR_AVERAGE = 1 };      /* Eq. 38 | Eq. 37 */
-enum { MP_REF_PHASE_MEAN = 0, MP_REF_VOLUME_MEAN = 1, MP_REF_EXPLICIT = 2 };
+/* Reference medium A0, B0 (Alg. 2).  PHASE_MEAN, VOLUME_MEAN and EXPLICIT
+ * give an isotropic medium (Eq. 6 constants: the unweighted mean over the
+ * phases present, the volume average, or mp_problem.ref), whose Green
+ * operator (Eqs. 33-35) has a closed form.  TENSOR_MEAN takes Alg. 2
+ * literally with every phase's own tensors: A0 = <A(x)>, B0 = <B(x)> over
+ * the cell, Eq. 5 tensors where a phase has them (mp_aniso), Eq. 6 ones
+ * elsewhere; TENSOR_PHASE_MEAN is the unweighted mean of those tensors over
+ * the phases present (like PHASE_MEAN, it keeps the basic scheme convergent
+ * when a stiff phase fills a small volume).  With a tensor reference the
+ * Green operator factors the 6x6 Fourier symbol at every frequency (it is
+ * positive definite whenever <A> is, which valid phases ensure; <B> may be
+ * singular on skew tensors, gamma = beta).  Plans only: a batch rejects the
+ * tensor modes. */
+enum { MP_REF_PHASE_MEAN = 0, MP_REF_VOLUME_MEAN = 1, MP_REF_EXPLICIT = 2, MP_REF_TENSOR_MEAN = 3,
+       MP_REF_TENSOR_PHASE_MEAN = 4 };
 enum { MP_FIELD_E = 0, MP_FIELD_GAMMA = 1, MP_FIELD_T = 2, MP_FIELD_M = 3,
        MP_FIELD_P = 4, MP_FIELD_Q = 5 };
 
@@ -73,8 +87,9 @@ typedef struct {
  * the isotropic ones of Eq. 6.  Both tensors must be symmetric over their
  * index pairs (A_klmn = A_mnkl, B_lkmn = B_mnlk) and positive definite as
  * 9 x 9 matrices.  The phase must be elastic (tY = mY = INFINITY); its
- * isotropic constants in mp_phase still enter the reference medium and the
- * Eqs. 14, 17 equivalent stresses reported as Teq, Meq. */
+ * tensors enter an MP_REF_TENSOR_* reference medium, and its isotropic
+ * constants in mp_phase the isotropic reference media and the Eqs. 14, 17
+ * equivalent stresses reported as Teq, Meq. */
 typedef struct {
   int32_t phase;            /* phase id (< n_phases), listed at most once */
   double A[81];             /* A_klmn at index 27k + 9l + 3m + n: t_kl = A_klmn e_mn */

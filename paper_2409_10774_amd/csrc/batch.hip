@@ -469,6 +469,7 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   mp_status st = validate(prob, &g);
   if (st != MP_OK) return st;
   if (g.n_aniso > 0) return fail(MP_E_INVALID, "phases with Eq. 5 tensors are supported by plans only");
+  if (g.ref_tensor) return fail(MP_E_INVALID, "tensor reference media are supported by plans only");
   int ci = -1;
   for (int c = 0; c < int(B->cls.size()); ++c)
     if (B->cls[c].n[0] == g.n0 && B->cls[c].n[1] == g.n1 && B->cls[c].n[2] == g.n2) ci = c;
@@ -661,6 +662,7 @@ mp_status mp_batch_footprint(const mp_batch_config* cfg, const mp_problem* prob,
   mp_status st = validate(prob, &g);
   if (st != MP_OK) return st;
   if (g.n_aniso > 0) return fail(MP_E_INVALID, "phases with Eq. 5 tensors are supported by plans only");
+  if (g.ref_tensor) return fail(MP_E_INVALID, "tensor reference media are supported by plans only");
   size_t po, ro;
   *bytes = align256(rve_bytes(layout(g, cfg->precision == MP_MIXED ? sizeof(float) : sizeof(double)),
                               n_steps, &po, &ro));

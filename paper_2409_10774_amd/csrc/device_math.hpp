@@ -11,6 +11,8 @@
 //   green_apply      reference-medium Green operator at one frequency
 //                    (closed-form solve of the 6x6 Fourier symbol of the
 //                    balance equations, Eqs. 1, 2, 6, 33-35)
+//   green_apply_gen  the same for a general (Eq. 5) reference medium: the
+//                    symbol assembled from stored coefficients and factored
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -473,22 +475,14 @@ __device__ __forceinline__ double micro_equivalent(const MicroC& c, const T* m) 
 // Green operator at one frequency.
 //   Sources of the reference-medium balance equations (Eq. 2 with the
 //   polarization as eigenstress): bu_l = i xi_k tau_kl,
-//   bp_l = i xi_k mu_kl + eps_lkm tau_km.  The 6x6 Hermitian symbol
-//     K = [[(mu0+k0) s^2 I + (lam0+mu0-k0) xi xi^T, -2 i k0 W],
-//          [-2 i k0 W, (g0 s^2 + 4 k0) I + (a0 + b0) xi xi^T]],  W v = xi x v,
-//   splits into a longitudinal part along n = xi/s and a 2x2 transverse
-//   block, solved in closed form.  Then e_kl = i xi_k u_l + eps_lkm phi_m and
+//   bp_l = i xi_k mu_kl + eps_lkm tau_km.  The amplitudes (u, phi) of the
+//   fluctuation solve K (u, phi) = (bu, bp) with K the 6x6 Hermitian Fourier
+//   symbol of the reference medium; then e_kl = i xi_k u_l + eps_lkm phi_m and
 //   g_kl = i xi_l phi_k (Eq. 1), scaled by `scale` (the inverse-DFT 1/N).
 // ---------------------------------------------------------------------------
-struct RefC {
-  double lam, mu, kap, alp, bet, gam;
-};
-
 template <class T>
-__device__ __forceinline__ void green_apply(const RefC& r, T x1, T x2, T x3, T scale,
-                                            cx<T>* tau /*9 in, e out*/, cx<T>* mu /*9 in, g out*/) {
-  const T xi[3] = {x1, x2, x3};
-  cx<T> bu[3], bp[3];
+__device__ __forceinline__ void green_sources(const T (&xi)[3], const cx<T>* tau, const cx<T>* mu,
+                                              cx<T> (&bu)[3], cx<T> (&bp)[3]) {
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     cx<T> su = {0, 0}, sp = {0, 0};
@@ -504,6 +498,47 @@ __device__ __forceinline__ void green_apply(const RefC& r, T x1, T x2, T x3, T s
   bp[0] = cadd(bp[0], csub(tau[5], tau[7]));
   bp[1] = cadd(bp[1], csub(tau[6], tau[2]));
   bp[2] = cadd(bp[2], csub(tau[1], tau[3]));
+}
+
+template <class T>
+__device__ __forceinline__ void green_strains(const T (&xi)[3], const cx<T> (&u)[3], const cx<T> (&ph)[3],
+                                              T scale, cx<T>* tau /*e out*/, cx<T>* mu /*g out*/) {
+  // e_kl = i xi_k u_l + eps_lkm phi_m ; g_kl = i xi_l phi_k
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      tau[3 * k + l] = mul_i(cscale(u[l], xi[k]));
+      mu[3 * k + l] = mul_i(cscale(ph[k], xi[l]));
+    }
+  tau[1] = csub(tau[1], ph[2]);
+  tau[2] = cadd(tau[2], ph[1]);
+  tau[3] = cadd(tau[3], ph[2]);
+  tau[5] = csub(tau[5], ph[0]);
+  tau[6] = csub(tau[6], ph[1]);
+  tau[7] = cadd(tau[7], ph[0]);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    tau[i] = cscale(tau[i], scale);
+    mu[i] = cscale(mu[i], scale);
+  }
+}
+
+// Isotropic reference medium (Eq. 6 constants): the symbol is
+//   K = [[(mu0+k0) s^2 I + (lam0+mu0-k0) xi xi^T, -2 i k0 W],
+//        [-2 i k0 W, (g0 s^2 + 4 k0) I + (a0 + b0) xi xi^T]],  W v = xi x v,
+// which splits into a longitudinal part along n = xi/s and a 2x2 transverse
+// block, solved in closed form.
+struct RefC {
+  double lam, mu, kap, alp, bet, gam;
+};
+
+template <class T>
+__device__ __forceinline__ void green_apply(const RefC& r, T x1, T x2, T x3, T scale,
+                                            cx<T>* tau /*9 in, e out*/, cx<T>* mu /*9 in, g out*/) {
+  const T xi[3] = {x1, x2, x3};
+  cx<T> bu[3], bp[3];
+  green_sources<T>(xi, tau, mu, bu, bp);
 
   const T s2 = x1 * x1 + x2 * x2 + x3 * x3;
   const T s = sqrt(s2);
@@ -541,25 +576,90 @@ __device__ __forceinline__ void green_apply(const RefC& r, T x1, T x2, T x3, T s
     u[l] = cadd(uT, cscale(nbu, n[l] * iL));
     ph[l] = cadd(pT, cscale(nbp, n[l] * iP));
   }
-  // e_kl = i xi_k u_l + eps_lkm phi_m ; g_kl = i xi_l phi_k
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
+  green_strains<T>(xi, u, ph, scale, tau, mu);
+}
+
+// General reference medium (Eq. 5 tensors A0_klmn, B0_lkmn).  Writing
+// phi = i psi turns K into the real symmetric positive definite matrix
+//   S = [[A0_alkj xi_a xi_k,  xi_a C_alj],
+//        [xi_a C_ajl,         B0_lkjn xi_k xi_n - F_lj]],
+//   C_abj = A0_abkl eps_lkj,  F_lj = eps_lkm C_kmj,
+// and the system into S (u, psi) = (bu, -i bp).  Each of the 21 upper
+// entries of S (row by row) is a polynomial in xi; G holds its 10
+// coefficients of xi1^2, xi2^2, xi3^2, xi1 xi2, xi1 xi3, xi2 xi3, xi1, xi2,
+// xi3, 1.  S is factored as L D L^T (no pivoting: S is positive definite),
+// and the real and imaginary parts of the sources are its two right-hand
+// sides.
+constexpr int kSymEntries = 21;
+constexpr int kSymCoef = 10;
+
+template <class T>
+__device__ __forceinline__ void green_apply_gen(const MP_GLOBAL double* G, T x1, T x2, T x3, T scale,
+                                                cx<T>* tau /*9 in, e out*/, cx<T>* mu /*9 in, g out*/) {
+  const T xi[3] = {x1, x2, x3};
+  cx<T> b[6];
+  {
+    cx<T> bu[3], bp[3];
+    green_sources<T>(xi, tau, mu, bu, bp);
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      tau[3 * k + l] = mul_i(cscale(u[l], xi[k]));
-      mu[3 * k + l] = mul_i(cscale(ph[k], xi[l]));
+      b[l] = bu[l];
+      b[3 + l] = cx<T>{bp[l].im, -bp[l].re};   // -i bp
     }
-  tau[1] = csub(tau[1], ph[2]);
-  tau[2] = cadd(tau[2], ph[1]);
-  tau[3] = cadd(tau[3], ph[2]);
-  tau[5] = csub(tau[5], ph[0]);
-  tau[6] = csub(tau[6], ph[1]);
-  tau[7] = cadd(tau[7], ph[0]);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    tau[i] = cscale(tau[i], scale);
-    mu[i] = cscale(mu[i], scale);
   }
+  const T mono[9] = {x1 * x1, x2 * x2, x3 * x3, x1 * x2, x1 * x3, x2 * x3, x1, x2, x3};
+  // entry (i, j), i <= j, of S: the u-psi block is linear in xi, the u-u
+  // block quadratic, the psi-psi block quadratic plus a constant (the other
+  // coefficients of an entry are zero and not read)
+  auto entry = [&](int i, int j) {
+    const MP_GLOBAL double* g = G + kSymCoef * (i * (11 - i) / 2 + j);
+    T v = T(0);
+    if (i < 3 && j >= 3) {
+#pragma unroll
+      for (int m = 6; m < 9; ++m) v += T(g[m]) * mono[m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < 6; ++m) v += T(g[m]) * mono[m];
+      if (i >= 3) v += T(g[9]);
+    }
+    return v;
+  };
+  // S = L D L^T column by column, each entry of S evaluated where it is
+  // needed.  U = L D (below the diagonal) and 1/D are kept, which the
+  // elimination and both triangular solves use as they are.
+  T U[6][6], id[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    T d = entry(j, j);
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= U[j][k] * U[j][k] * id[k];
+    id[j] = T(1) / d;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      T v = entry(j, i);
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= U[i][k] * U[j][k] * id[k];
+      U[i][j] = v;
+    }
+  }
+  // w = D^-1 L^-1 b: w_i = (b_i - sum_k U_ik w_k) / d_i; then
+  // x = L^-T w: x_i = w_i - (sum_k U_ki x_k) / d_i
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int k = 0; k < i; ++k) b[i] = csub(b[i], cscale(b[k], U[i][k]));
+    b[i] = cscale(b[i], id[i]);
+  }
+#pragma unroll
+  for (int i = 4; i >= 0; --i) {
+    cx<T> r = {0, 0};
+#pragma unroll
+    for (int k = i + 1; k < 6; ++k) r = cadd(r, cscale(b[k], U[k][i]));
+    b[i] = csub(b[i], cscale(r, id[i]));
+  }
+  const cx<T> u[3] = {b[0], b[1], b[2]};
+  const cx<T> ph[3] = {mul_i(b[3]), mul_i(b[4]), mul_i(b[5])};   // phi = i psi
+  green_strains<T>(xi, u, ph, scale, tau, mu);
 }
 
 }  // namespace mp

@@ -137,7 +137,16 @@ struct Geometry {
   long nvox, nspec, nrows;
   int xblocks, txy, txz;
   int n_aniso;     // phases with Eq. 5 tensors
+  int ref_tensor;  // 1: general reference medium of the phases' tensors (MP_REF_TENSOR_*)
 };
+
+// Doubles of the workspace's tensor table: the Eq. 5 row matrices of the
+// anisotropic phases, then those of a general reference medium and its
+// Green-operator symbol coefficients.
+inline size_t aniso_words(const Geometry& g) {
+  return size_t(std::max(g.n_aniso + g.ref_tensor, 1)) * 162 +
+         (g.ref_tensor ? size_t(kSymEntries) * kSymCoef : 0);
+}
 
 // Symmetric positive definite 9 x 9 matrix (row-major), by Cholesky
 inline bool spd9(const double* M) {
@@ -173,6 +182,58 @@ inline void aniso_rows(const mp_aniso& a, double* out) {
       for (int j = 0; j < 9; ++j) out[81 + 9 * (3 * k + l) + j] = a.B[9 * (3 * l + k) + j];
 }
 
+// Eq. 6 tensors of an isotropic phase in the storage orders of mp_aniso:
+// A[27k + 9l + 3m + n] = A_klmn, B[27l + 9k + 3m + n] = B_lkmn.
+inline void iso_tensors(const mp_phase& c, double* A, double* B) {
+  auto d = [](int i, int j) { return i == j ? 1.0 : 0.0; };
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l)
+      for (int m = 0; m < 3; ++m)
+        for (int n = 0; n < 3; ++n) {
+          A[27 * k + 9 * l + 3 * m + n] = c.lambda * d(k, l) * d(m, n) + (c.mu + c.kappa) * d(k, m) * d(l, n) +
+                                          (c.mu - c.kappa) * d(k, n) * d(l, m);
+          B[27 * l + 9 * k + 3 * m + n] =
+              c.alpha * d(k, l) * d(m, n) + c.beta * d(k, m) * d(l, n) + c.gamma * d(k, n) * d(l, m);
+        }
+}
+
+// General reference medium, Alg. 2 taken literally: A0 = <A(x)>, B0 = <B(x)>
+// over the cell with every phase's own tensors (Eq. 5 where the phase has
+// them, else Eq. 6), in the storage orders of mp_aniso; with
+// MP_REF_TENSOR_PHASE_MEAN the unweighted mean over the phases present.
+inline mp_status reference_tensors(const mp_problem* prob, long nvox, mp_aniso* out) {
+  std::vector<long> count(prob->n_phases, 0);
+  for (long i = 0; i < nvox; ++i) count[prob->phase[i]]++;
+  std::vector<const mp_aniso*> rec(prob->n_phases, nullptr);
+  for (int j = 0; j < prob->n_aniso; ++j) rec[prob->aniso[j].phase] = &prob->aniso[j];
+  int present = 0;
+  for (int i = 0; i < prob->n_phases; ++i) present += count[i] ? 1 : 0;
+  mp_aniso r{};
+  r.phase = -1;
+  for (int i = 0; i < prob->n_phases; ++i) {
+    if (!count[i]) continue;
+    double A[81], B[81];
+    if (rec[i]) {
+      std::memcpy(A, rec[i]->A, sizeof A);
+      std::memcpy(B, rec[i]->B, sizeof B);
+    } else {
+      iso_tensors(prob->phases[i], A, B);
+    }
+    const double w = prob->ref_mode == MP_REF_TENSOR_PHASE_MEAN ? 1.0 / present
+                                                                 : double(count[i]) / double(nvox);
+    for (int k = 0; k < 81; ++k) {
+      r.A[k] += w * A[k];
+      r.B[k] += w * B[k];
+    }
+  }
+  // <A> positive definite keeps the Fourier symbol positive definite at
+  // every xi != 0 (no nonzero (u, phi) has e = 0), so <B> may be singular on
+  // skew tensors (gamma = beta).  Valid phases give both; this is a guard.
+  if (!spd9(r.A)) return fail(MP_E_INVALID, "reference tensor <A> is not positive definite over its index pairs");
+  *out = r;
+  return MP_OK;
+}
+
 inline mp_status validate(const mp_problem* p, Geometry* g) {
   if (!p) return fail(MP_E_INVALID, "problem is NULL");
   for (int i = 0; i < 3; ++i)
@@ -187,7 +248,7 @@ inline mp_status validate(const mp_problem* p, Geometry* g) {
   if (p->err_norm != MP_ERR_LOCAL && p->err_norm != MP_ERR_AVERAGE)
     return fail(MP_E_INVALID, "err_norm");
   if (p->precision != MP_FP64 && p->precision != MP_MIXED) return fail(MP_E_INVALID, "precision");
-  if (p->ref_mode < 0 || p->ref_mode > 2) return fail(MP_E_INVALID, "ref_mode");
+  if (p->ref_mode < 0 || p->ref_mode > 4) return fail(MP_E_INVALID, "ref_mode");
   for (int i = 0; i < p->n_phases; ++i) {
     const mp_phase& c = p->phases[i];
     const std::string tag = "phase " + std::to_string(i) + ": ";
@@ -239,6 +300,12 @@ inline mp_status validate(const mp_problem* p, Geometry* g) {
   G.txy = (G.nh % tx_wide(G.n1) == 0) ? tx_wide(G.n1) : 1;
   G.txz = (G.nh % tx_wide(G.n2) == 0) ? tx_wide(G.n2) : 1;
   G.n_aniso = p->n_aniso;
+  G.ref_tensor = p->ref_mode == MP_REF_TENSOR_MEAN || p->ref_mode == MP_REF_TENSOR_PHASE_MEAN ? 1 : 0;
+  if (G.ref_tensor) {
+    mp_aniso r;
+    const mp_status rs = reference_tensors(p, nvox, &r);
+    if (rs != MP_OK) return rs;
+  }
   *g = G;
   return MP_OK;
 }
@@ -256,7 +323,7 @@ inline Layout layout(const Geometry& g, size_t w /* bytes per bulk word */) {
   L.out_pq = take(2 * g.nvox * sizeof(double));
   L.phase = take(g.nvox);
   L.params = take(256 * sizeof(PhaseC));
-  L.aniso = take(size_t(std::max(g.n_aniso, 1)) * 162 * sizeof(double));
+  L.aniso = take(aniso_words(g) * sizeof(double));
   L.tw = take(size_t(g.n0 + g.n1 + g.n2) * 2 * w);
   L.partials = take(size_t(g.xblocks) * kNAvg * sizeof(double));
   L.ctl = take(sizeof(Ctl));
@@ -293,8 +360,10 @@ void twiddles(int n, std::vector<cx<T>>* out) {
 }
 
 
-// Reference medium (Alg. 2: A0 = <A>, B0 = <B>): the unweighted mean of each
-// modulus over the phases present (default), the volume average, or given.
+// Isotropic reference medium (Alg. 2: A0 = <A>, B0 = <B>): the unweighted
+// mean of each modulus over the phases present (default), the volume average,
+// or given.  With MP_REF_TENSOR_* the matching mean of the constants is kept
+// beside the tensors (the kernels then use the tensors).
 inline mp_status reference_medium(const mp_problem* prob, long nvox, RefC* out) {
   double refv[6] = {0, 0, 0, 0, 0, 0};
   if (prob->ref_mode == MP_REF_EXPLICIT) {
@@ -307,7 +376,8 @@ inline mp_status reference_medium(const mp_problem* prob, long nvox, RefC* out) 
     double wsum = 0;
     for (int i = 0; i < prob->n_phases; ++i) {
       if (!count[i]) continue;
-      const double wgt = prob->ref_mode == MP_REF_VOLUME_MEAN ? double(count[i]) : 1.0;
+      const bool by_phase = prob->ref_mode == MP_REF_PHASE_MEAN || prob->ref_mode == MP_REF_TENSOR_PHASE_MEAN;
+      const double wgt = by_phase ? 1.0 : double(count[i]);
       const mp_phase& c = prob->phases[i];
       const double v[6] = {c.lambda, c.mu, c.kappa, c.alpha, c.beta, c.gamma};
       for (int k = 0; k < 6; ++k) refv[k] += wgt * v[k];
@@ -321,6 +391,47 @@ inline mp_status reference_medium(const mp_problem* prob, long nvox, RefC* out) 
     return fail(MP_E_INVALID, "reference medium is not positive definite");
   *out = r;
   return MP_OK;
+}
+
+// Coefficients of the real symmetric Fourier symbol S(xi) of a general
+// reference medium (the form green_apply_gen factors): entry e of the upper
+// triangle, row by row, is sum_m G[10 e + m] mono_m(xi) with the monomials
+// xi1^2, xi2^2, xi3^2, xi1 xi2, xi1 xi3, xi2 xi3, xi1, xi2, xi3, 1.
+//   S_uu[l][j]   = A0_alkj xi_a xi_k
+//   S_upsi[l][j] = xi_a C_alj,            C_abj = A0_abkl eps_lkj
+//   S_psipsi[l][j] = B0_lkjn xi_k xi_n - F_lj,  F_lj = eps_lkm C_kmj
+inline void green_symbol(const mp_aniso& r, double* G) {
+  auto eps = [](int i, int j, int k) {
+    return double((i - j) * (j - k) * (k - i)) / 2.0;   // Levi-Civita on 0..2
+  };
+  auto quad = [](int a, int k) { return a == k ? a : (a + k == 1 ? 3 : (a + k == 2 ? 4 : 5)); };
+  auto A = [&](int k, int l, int m, int n) { return r.A[27 * k + 9 * l + 3 * m + n]; };
+  auto B = [&](int l, int k, int m, int n) { return r.B[27 * l + 9 * k + 3 * m + n]; };
+  double C[3][3][3] = {}, F[3][3] = {};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) C[a][b][j] += A(a, b, k, l) * eps(l, k, j);
+  for (int l = 0; l < 3; ++l)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        for (int m = 0; m < 3; ++m) F[l][j] += eps(l, k, m) * C[k][m][j];
+  std::fill(G, G + kSymEntries * kSymCoef, 0.0);
+  for (int i = 0, e = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j, ++e) {
+      double* g = G + kSymCoef * e;
+      if (j < 3) {          // u-u
+        for (int a = 0; a < 3; ++a)
+          for (int k = 0; k < 3; ++k) g[quad(a, k)] += A(a, i, k, j);
+      } else if (i < 3) {   // u-psi
+        for (int a = 0; a < 3; ++a) g[6 + a] += C[a][i][j - 3];
+      } else {              // psi-psi
+        for (int k = 0; k < 3; ++k)
+          for (int n = 0; n < 3; ++n) g[quad(k, n)] += B(i - 3, k, j - 3, n);
+        g[9] -= F[i - 3][j - 3];
+      }
+    }
 }
 
 }  // namespace mp

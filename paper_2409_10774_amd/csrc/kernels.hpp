@@ -52,7 +52,8 @@ struct Ctl {
 };
 
 enum XMode { X_ITER = 0, X_TRANS = 1, X_FWD_ONLY = 2, X_INV_ONLY = 3 };
-enum AMode { Y_FWD = 0, Y_INV = 1, Z_GREEN = 2, Z_FWD = 3 };
+// Z_GREEN_AN: Z_GREEN with a general (Eq. 5) reference medium
+enum AMode { Y_FWD = 0, Y_INV = 1, Z_GREEN = 2, Z_FWD = 3, Z_GREEN_AN = 4 };
 
 template <class T>
 struct XArgs {
@@ -80,6 +81,8 @@ struct XArgs {
   T* fout;          // X_INV_ONLY output (18 n)
   const T* eig;     // optional eigenstress (18 n): subtracted in every polarization
   const double* aniso;  // Eq. 5 row matrices, [record][level][81] (AN kernels)
+  const double* refan;  // row matrices [level][81] of a general reference medium
+                        // (AN kernels), or null: the isotropic constants `ref`
 };
 
 // deterministic sum over a 64-lane wavefront (every lane gets the total)
@@ -431,7 +434,9 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
         // eigenstress when one is set (the manufactured stresses of the code
         // verification, App. D.1)
         T r0[9];
-        if (lvl == 0)
+        if (AN && a.refan)
+          aniso_apply<T>(glob(a.refan) + lvl * 81, e, r0);
+        else if (lvl == 0)
           apply_A<T>(T(a.ref.lam), T(a.ref.mu), T(a.ref.kap), e, r0);
         else
           apply_B<T>(T(a.ref.alp), T(a.ref.bet), T(a.ref.gam), e, r0);
@@ -574,10 +579,11 @@ struct AxisArgs {
   long ostride;    // stride (complex) of the tile row index: kz for y, ky for z
   long pstride;    // stride (complex) between points of the transformed axis
   const cx<T>* tw;
-  // Z_GREEN only
+  // Z_GREEN, Z_GREEN_AN only
   int n0, n1, n2;
   double h, scale;
   RefC ref;
+  const double* gsym;   // Z_GREEN_AN: symbol coefficients [21][10]
 };
 
 template <int L, int TX>
@@ -634,7 +640,7 @@ __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, 
   __syncthreads();
   constexpr bool INV = MODE == Y_INV;
   fft_ct<T, INV, L, 1, NB, NB, 1, true, NTHR>(lds, tw, tid);
-  if (MODE == Z_GREEN) {
+  if (MODE == Z_GREEN || MODE == Z_GREEN_AN) {
     // Green operator at the L * TX frequencies of the tile
     for (int f = tid; f < L * TX; f += NTHR) {
       const int kz = f / TX, xl = f % TX;
@@ -657,7 +663,10 @@ __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, 
         const T x1 = T(tp * kx / (a.n0 * a.h));
         const T x2 = T(tp * my / (a.n1 * a.h));
         const T x3 = T(tp * mz / (a.n2 * a.h));
-        green_apply<T>(a.ref, x1, x2, x3, T(a.scale), tau, mu);
+        if constexpr (MODE == Z_GREEN_AN)
+          green_apply_gen<T>(glob(a.gsym), x1, x2, x3, T(a.scale), tau, mu);
+        else
+          green_apply<T>(a.ref, x1, x2, x3, T(a.scale), tau, mu);
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
           p[c] = tau[c];
@@ -670,7 +679,10 @@ __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, 
   }
   MP_GLOBAL cx<T>* g = glob(a.S) + (long)by * a.ostride + (long)bx * NB;
   const long ps = a.pstride;
-  for (int w = tid; w < PTS; w += NTHR) gstore(g + (w / NB) * ps + w % NB, lds[w]);
+  // the general Green step needs the registers that would otherwise keep the
+  // load addresses alive for these stores: recompute them
+  const int ts = MODE == Z_GREEN_AN ? fresh_tid() : tid;
+  for (int w = ts; w < PTS; w += NTHR) gstore(g + (w / NB) * ps + w % NB, lds[w]);
 }
 
 // XCD-aware tile order.  The chip hands consecutive blocks to its 8 XCDs in

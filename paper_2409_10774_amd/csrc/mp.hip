@@ -62,6 +62,8 @@ struct mp_plan_s {
   void* tw0;      // cx<T>, n0 + n1 + n2 entries
   const void* eig;   // optional eigenstress (T, 18 n, caller-owned)
   const double* aniso;   // Eq. 5 row matrices, [record][level][81]
+  const double* refan;   // general reference medium: its row matrices, or null
+  const double* gsym;    // and its symbol coefficients [21][10], or null
   Ctl* ctl;
   Ctl* ctl_host;
   double* tot_host;   // pinned, kNAvg entries
@@ -112,6 +114,7 @@ struct Eng {
     a.h = P->h;
     a.scale = 1.0 / double(g.nvox);
     a.ref = P->ref;
+    a.gsym = P->gsym;
     return a;
   }
 
@@ -124,7 +127,10 @@ struct Eng {
     mark(0);
     launch_axis<T, Y_FWD>(g.n1, g.txy, g.nh / g.txy, g.n2, P->stream, ay, ctl);
     mark(1);
-    launch_axis<T, Z_GREEN>(g.n2, g.txz, g.nh / g.txz, g.n1, P->stream, az, ctl);
+    if (P->gsym)
+      launch_axis<T, Z_GREEN_AN>(g.n2, g.txz, g.nh / g.txz, g.n1, P->stream, az, ctl);
+    else
+      launch_axis<T, Z_GREEN>(g.n2, g.txz, g.nh / g.txz, g.n1, P->stream, az, ctl);
     mark(2);
     launch_axis<T, Y_INV>(g.n1, g.txy, g.nh / g.txy, g.n2, P->stream, ay, ctl);
     mark(3);
@@ -149,6 +155,7 @@ struct Eng {
     a.ref = P->ref;
     a.eig = static_cast<const T*>(P->eig);
     a.aniso = P->aniso;
+    a.refan = P->refan;
     return a;
   }
 
@@ -159,6 +166,7 @@ struct Eng {
       if ((e = allow_lds<T, Y_FWD>(L)) != hipSuccess) return e;
       if ((e = allow_lds<T, Y_INV>(L)) != hipSuccess) return e;
       if ((e = allow_lds<T, Z_GREEN>(L)) != hipSuccess) return e;
+      if ((e = allow_lds<T, Z_GREEN_AN>(L)) != hipSuccess) return e;
       if ((e = allow_lds<T, Z_FWD>(L)) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -215,7 +223,7 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     P->ctl_host->done = 0;
     // commit of the previous step, first iterate of this one (extrapolated
     // or uniform), its return map and polarization
-    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr, g.n_aniso > 0);
+    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr, g.n_aniso > 0 || g.ref_tensor);
     if (pending) {
       mp_status r = record(P, rec);
       if (r != MP_OK) return r;
@@ -243,7 +251,7 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
         hipEvent_t* ev = P->prof ? &P->ev[size_t(k) * kProfEv] : nullptr;
         spectral(P, S(P), P->ctl, P->prof == 1 ? ev : nullptr);
         if (P->prof == 2) HIP_TRY(hipEventRecord(ev[3], P->stream));
-        launch_x<T, X_ITER>(g.n0, g.xblocks, P->stream, xa, P->ctl, g.n_aniso > 0);
+        launch_x<T, X_ITER>(g.n0, g.xblocks, P->stream, xa, P->ctl, g.n_aniso > 0 || g.ref_tensor);
         if (ev) HIP_TRY(hipEventRecord(ev[4], P->stream));
         hipLaunchKernelGGL(k_rows, dim3(kNPart), dim3(256), 0, P->stream, P->partials, g.xblocks, 0,
                            P->tot, P->ctl);
@@ -289,7 +297,7 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     // commit only: the last step of this call (or the failed one)
     xa.commit = 1;
     xa.init = 0;
-    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr, g.n_aniso > 0);
+    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr, g.n_aniso > 0 || g.ref_tensor);
     mp_status r = record(P, rec);
     if (r != MP_OK) return r;
   }
@@ -347,6 +355,8 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   P->tw0 = wsp + L.tw;
   P->eig = nullptr;
   P->aniso = reinterpret_cast<const double*>(wsp + L.aniso);
+  P->refan = nullptr;
+  P->gsym = nullptr;
   P->partials = reinterpret_cast<double*>(wsp + L.partials);
   P->ctl = reinterpret_cast<Ctl*>(wsp + L.ctl);
   P->tot = reinterpret_cast<double*>(wsp + L.tot);
@@ -371,10 +381,25 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
 
   std::vector<PhaseC> pc(256);
   for (int i = 0; i < prob->n_phases; ++i) pc[i] = derive(prob->phases[i]);
-  std::vector<double> arows(size_t(std::max(g.n_aniso, 1)) * 162, 0.0);
+  std::vector<double> arows(aniso_words(g), 0.0);
   for (int j = 0; j < g.n_aniso; ++j) {
     aniso_rows(prob->aniso[j], &arows[size_t(j) * 162]);
     pc[prob->aniso[j].phase].t.aid = double(j);
+  }
+  if (g.ref_tensor) {
+    // general reference medium: its row matrices after the phases' records,
+    // then the coefficients of its Fourier symbol
+    mp_aniso r;
+    const mp_status rs = reference_tensors(prob, g.nvox, &r);
+    if (rs != MP_OK) {
+      delete P;
+      return rs;
+    }
+    const size_t sym = size_t(std::max(g.n_aniso + 1, 1)) * 162;
+    aniso_rows(r, &arows[size_t(g.n_aniso) * 162]);
+    green_symbol(r, &arows[sym]);
+    P->refan = P->aniso + size_t(g.n_aniso) * 162;
+    P->gsym = P->aniso + sym;
   }
   std::vector<cx<double>> tw;
   std::vector<cx<float>> twf;

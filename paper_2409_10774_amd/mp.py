@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "MP_OK", 1: "MP_E_INVALID", 2: "MP_E_NOMEM", 3: "MP_E_DEVICE"
                 4: "MP_E_NOT_CONVERGED", 5: "MP_E_DIVERGED", 6: "MP_E_STATE"}
 MP_FP64, MP_MIXED = 0, 1
 MP_ERR_LOCAL, MP_ERR_AVERAGE = 0, 1
-MP_REF_PHASE_MEAN, MP_REF_VOLUME_MEAN, MP_REF_EXPLICIT = 0, 1, 2
+MP_REF_PHASE_MEAN, MP_REF_VOLUME_MEAN, MP_REF_EXPLICIT, MP_REF_TENSOR_MEAN, MP_REF_TENSOR_PHASE_MEAN = range(5)
 FIELDS = {"e": 0, "g": 1, "t": 2, "m": 3, "p": 4, "q": 5}
 
 
@@ -151,7 +151,8 @@ def make_problem(phase_map, phases, h=1.0, tol=1e-8, max_iter=20000, err_norm="l
     prob.n_phases = len(phases)
     prob.phases = C.cast(arr, C.POINTER(mp_phase))
     prob.ref_mode = {"phase_mean": MP_REF_PHASE_MEAN, "volume_mean": MP_REF_VOLUME_MEAN,
-                     "explicit": MP_REF_EXPLICIT}[ref_mode]
+                     "explicit": MP_REF_EXPLICIT, "tensor_mean": MP_REF_TENSOR_MEAN,
+                     "tensor_phase_mean": MP_REF_TENSOR_PHASE_MEAN}[ref_mode]
     if ref is not None:
         prob.ref = mp_phase(*(list(float(v) for v in ref) + [0.0] * (12 - len(ref))))
     prob.tol = float(tol)

@@ -67,6 +67,11 @@ WORKLOADS = {
         precision="fp64", dtype="f64",
         desc="spheres256_fp64: the 256^3 cell of spheres256_mixed in FP64 (the reference of the "
              "mixed form), tol 1e-6 (Eq. 38)"),
+    "aniso128_fp64": dict(
+        precision="fp64", dtype="f64",
+        desc="aniso128_fp64: the 128^3 cell of spheres128_fp64 with Eq. 5 anisotropic spheres "
+             "(general tensors, mean eigenvalues 17 and 50) and the unweighted mean of the phases' "
+             "tensors as reference medium (per-frequency factored Green operator); same load path"),
     "batch64_mixed": dict(
         precision="mixed", dtype="f32 bulk / f64 reductions",
         desc="batch64_mixed: 64 resident RVEs, edge U{32,64,96,128}, 1-60 spheres r~U[n/20,n/10], "
@@ -89,7 +94,8 @@ def cpu_baseline(wl, iters=4):
     from threadpoolctl import threadpool_limits
     from oracle import micropolar as O
     with threadpool_limits(limits=1):
-        solver = O.Solver(wl.phase_map, wl.phases, h=wl.h, tol=wl.tol, norm=wl.err_norm)
+        solver = O.Solver(wl.phase_map, wl.phases, h=wl.h, tol=wl.tol, norm=wl.err_norm,
+                          ref_mode=wl.ref_mode)
         t0 = time.perf_counter()
         solver.solve(wl.times[:2], wl.E[:1], wl.G[:1], schedule=[iters])
         dt = time.perf_counter() - t0
@@ -280,12 +286,14 @@ def main():
     cfg = WORKLOADS[args.workload]
     if args.workload == "spheres128_fp64":
         wl = W.random_spheres_128(n_steps=W_ + K)
+    elif args.workload == "aniso128_fp64":
+        wl = W.anisotropic_spheres_128(n_steps=W_ + K)
     else:   # spheres256_mixed, spheres256_fp64
         wl = W.random_spheres_256(n_steps=W_ + K)
     nvox = wl.phase_map.size
     BYTES_PER_VOXEL = bytes_per_voxel(8 if cfg["precision"] == "fp64" else 4)
     BYTES_PER_VOXEL_ITER = sum(BYTES_PER_VOXEL.values())
-    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision=cfg["precision"])
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision=cfg["precision"], ref_mode=wl.ref_mode)
     if args.fixed_iters:
         plan.set_fixed_iterations(args.fixed_iters)
     print(f"# workload {wl.name}: {wl.info}, warmup {W_} step(s), timed {K}", file=sys.stderr,

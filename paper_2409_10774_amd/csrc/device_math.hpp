@@ -39,6 +39,13 @@ template <class T>
 __device__ __forceinline__ const MP_GLOBAL T* glob(const T* p) {
   return (const MP_GLOBAL T*)p;
 }
+// Read-only memory through the constant address space: loads at a
+// wave-uniform address become scalar loads.
+#define MP_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const MP_CONST T* cnst(const T* p) {
+  return (const MP_CONST T*)p;
+}
 
 // complex values and constant records move through global memory as whole
 // vector words (one dwordx2 / dwordx4 access per complex value)
@@ -321,14 +328,31 @@ struct PhaseC {
 
 // Eq. 5 with general tensors: out_i = R_ij x_j for a 9 x 9 row matrix R
 // (FP64 in global memory), i = 3k + l, j = 3m + n
+// Row-matrix product out = R x of an Eq. 5 law (R in the constant address
+// space: a wave-uniform R is read through the scalar cache).
 template <class T>
-__device__ __forceinline__ void aniso_apply(const MP_GLOBAL double* R, const T* x, T* out) {
+__device__ __forceinline__ void aniso_apply(const MP_CONST double* R, const T* x, T* out) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     T s = T(0);
 #pragma unroll
     for (int j = 0; j < 9; ++j) s += T(R[9 * i + j]) * x[j];
     out[i] = s;
+  }
+}
+
+// The Eq. 5 law of this lane's record aid (0 <= aid < n) at level lvl
+// (wave-uniform) of the table [record][level][81].  The records are visited
+// in a wave-uniform loop so that each one's rows are read at a wave-uniform
+// address; the match is made opaque, or the compiler would address the rows
+// by the equal per-lane aid.
+template <class T>
+__device__ __forceinline__ void aniso_apply_wave(const double* table, int n, int aid, int lvl, const T* x,
+                                                 T* out) {
+  for (int j = 0; j < n; ++j) {
+    int hit = aid == j;
+    asm volatile("" : "+v"(hit));
+    if (hit) aniso_apply<T>(cnst(table) + (2L * j + lvl) * 81, x, out);
   }
 }
 

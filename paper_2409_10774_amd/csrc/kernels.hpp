@@ -76,7 +76,7 @@ struct XArgs {
   int first;        // TRANS: first step, start from the uniform mac
   int commit;       // TRANS: commit the converged state held in E
   int init;         // TRANS: open the next step
-  int pad;
+  int n_aniso;      // records in `aniso` (AN kernels)
   const T* fin;     // X_FWD_ONLY input (18 n)
   T* fout;          // X_INV_ONLY output (18 n)
   const T* eig;     // optional eigenstress (18 n): subtracted in every polarization
@@ -322,12 +322,9 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
     else
       cm = gread(&glob(a.params)[ph].m);
   }
-  // this lane's Eq. 5 row matrix (AN kernels), null for an Eq. 6 phase
-  const MP_GLOBAL double* an = nullptr;
-  if (AN && MODE != X_FWD_ONLY) {
-    const int aid = int(glob(&a.params[ph].t.aid)[0]);
-    if (aid >= 0) an = glob(a.aniso) + (2L * aid + lvl) * 81;
-  }
+  // this lane's Eq. 5 record (AN kernels), -1 for an Eq. 6 phase
+  int aid = -1;
+  if (AN && MODE != X_FWD_ONLY) aid = int(glob(&a.params[ph].t.aid)[0]);
 
   if (MODE == X_TRANS && a.commit) {
     // commit (end of the step loop): final return map at the converged
@@ -338,8 +335,8 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
     for (int c = 0; c < 9; ++c) tc[c] = T(0);
     if (own) {
       T r0[9];
-      if (AN && an) {
-        aniso_apply<T>(an, eo, r0);
+      if (AN && aid >= 0) {
+        aniso_apply_wave<T>(a.aniso, a.n_aniso, aid, lvl, eo, r0);
 #pragma unroll
         for (int c = 0; c < 9; ++c) tc[c] = r0[c] + bb[c];
         pc = hn;
@@ -420,8 +417,8 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
       for (int c = 0; c < 9; ++c) t[c] = T(0);
       double pnew;
       if (own) {
-        if (AN && an) {
-          aniso_apply<T>(an, e, t);
+        if (AN && aid >= 0) {
+          aniso_apply_wave<T>(a.aniso, a.n_aniso, aid, lvl, e, t);
 #pragma unroll
           for (int c = 0; c < 9; ++c) t[c] += bb[c];
           pnew = hn;
@@ -435,7 +432,7 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
         // verification, App. D.1)
         T r0[9];
         if (AN && a.refan)
-          aniso_apply<T>(glob(a.refan) + lvl * 81, e, r0);
+          aniso_apply<T>(cnst(a.refan) + lvl * 81, e, r0);
         else if (lvl == 0)
           apply_A<T>(T(a.ref.lam), T(a.ref.mu), T(a.ref.kap), e, r0);
         else
@@ -486,8 +483,8 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
         if (own) {
           T to[9];
           double pold;
-          if (AN && an) {
-            aniso_apply<T>(an, eo, to);
+          if (AN && aid >= 0) {
+            aniso_apply_wave<T>(a.aniso, a.n_aniso, aid, lvl, eo, to);
 #pragma unroll
             for (int c = 0; c < 9; ++c) to[c] += bb[c];
           } else if (lvl == 0) {

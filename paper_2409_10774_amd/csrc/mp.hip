@@ -155,6 +155,7 @@ struct Eng {
     a.ref = P->ref;
     a.eig = static_cast<const T*>(P->eig);
     a.aniso = P->aniso;
+    a.n_aniso = g.n_aniso;
     a.refan = P->refan;
     return a;
   }

@@ -238,6 +238,22 @@ def random_spheres_128(seed: int = 1, n_steps: int = 50) -> Workload:
                     info={"spheres": len(sp), "vf": float(ph.mean())})
 
 
+def anisotropic_spheres_128(seed: int = 1, n_steps: int = 50) -> Workload:
+    """The 128^3 cell of random_spheres_128 with Eq. 5 spheres: general
+    tensors of mean eigenvalue 17 (A) and 50 (B), about those of the
+    contrast-10 isotropic spheres, and the unweighted mean of the two phases'
+    tensors as the reference medium; same load path and tolerance."""
+    ph, sp = random_spheres(128, seed, 40, 6.0, 12.0)
+    mat = matrix_phase()
+    inc = anisotropic_phase(seed + 10, t_scale=17.0, m_scale=50.0)
+    S = 50
+    times, E, G = ramp_path(S, E_end=unit((0, 0), 0.02), G_end=unit((0, 1), 0.002),
+                            t_end=float(S))
+    times, E, G = times[: n_steps + 1], E[:n_steps], G[:n_steps]
+    return Workload("aniso128_fp64", ph, [mat, inc], times, E, G, tol=1e-8,
+                    ref_mode="tensor_phase_mean", info={"spheres": len(sp), "vf": float(ph.mean())})
+
+
 def random_spheres_256(seed: int = 2, n_steps: int = 20) -> Workload:
     """256^3 cell, spheres r ~ U[5, 15] added until the volume fraction is
     at least 0.25, contrast 10; E11 ramped to 0.01 over 20 steps; tol 1e-6."""

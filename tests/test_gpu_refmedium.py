@@ -9,7 +9,9 @@ with every phase's own law) on the HIP path, against the oracle:
     (the volume mean diverges there: a stiff phase in a small volume), FP64,
     to convergence: iteration counts and fields against the oracle, and
     fewer iterations than with the isotropic phase-mean reference;
-  - the same cell in mixed precision on a fixed schedule against FP64.
+  - the same cell in mixed precision on a fixed schedule against FP64;
+  - the 128^3 cell of Eq. 5 spheres (the benchmark's anisotropic workload)
+    at full size on a fixed schedule, against the oracle.
 """
 import numpy as np
 import pytest
@@ -137,3 +139,17 @@ def test_anisotropic_reference_mixed_vs_fp64(mp):
     errs = {k: rel(f["mixed"][k], f["fp64"][k]) for k in f["fp64"]}
     say("mixed vs fp64 field rel", errs)
     assert max(errs.values()) < 1e-5
+
+
+def test_aniso128_full_size_fixed_schedule(mp):
+    say("case: 128^3 Eq. 5 spheres, tensor phase-mean reference, step 1, fixed 2 iterations, FP64")
+    wl = W.anisotropic_spheres_128(n_steps=1)
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, ref_mode=wl.ref_mode)
+    plan.set_fixed_iterations(2)
+    plan.solve(wl.times, wl.E, wl.G)
+    out = O.Solver(wl.phase_map, wl.phases, tol=wl.tol, ref_mode=wl.ref_mode).solve(
+        wl.times, wl.E, wl.G, schedule=[2], fields_at=(1,))
+    f = out["fields"][1]
+    errs = {k: rel(plan.field(k), f[k]) for k in ("e", "g", "t", "m", "p", "q")}
+    say("field rel errors", errs)
+    assert max(errs.values()) < TOL

@@ -115,8 +115,7 @@ typedef struct {
                                when the error measure stops improving for 100
                                iterations (its FP32 rounding floor), which
                                mp_step_error_parts reports */
-  int32_t n_aniso;          /* phases with Eq. 5 tensors, 0..n_phases (plans
-                               only: a batch rejects n_aniso > 0) */
+  int32_t n_aniso;          /* phases with Eq. 5 tensors, 0..n_phases */
   const mp_aniso* aniso;    /* host, n_aniso records (unused when n_aniso = 0) */
 } mp_problem;
 

@@ -79,6 +79,7 @@ struct ClassInfo {
   Geometry g;
   PassSched pass[3];   // Y_FWD, Z_GREEN, Y_INV
   int xgrid;
+  bool an;             // an RVE with Eq. 5 phases was admitted: the x pass's Eq. 5 variant
 };
 
 struct RveHost {
@@ -168,12 +169,13 @@ bool axis_kernel(int L, int tx, const void** fn, int* nthr, size_t* shm) {
 }
 
 template <class T, int MODE>
-bool x_kernel(int n0, const void** fn, int* nthr) {
+bool x_kernel(int n0, bool an, const void** fn, int* nthr) {
   switch (n0) {
-#define MP_CASE(N)                                                 \
-  case N:                                                          \
-    *fn = reinterpret_cast<const void*>(&k_batch_x<T, MODE, N>);   \
-    *nthr = XShape<T, N>::NTHR;                                    \
+#define MP_CASE(N)                                                                            \
+  case N:                                                                                     \
+    *fn = an ? reinterpret_cast<const void*>(&k_batch_x<T, MODE, N, true>)                    \
+             : reinterpret_cast<const void*>(&k_batch_x<T, MODE, N, false>);                  \
+    *nthr = XShape<T, N>::NTHR;                                                               \
     return true;
     MP_SIZES(MP_CASE)
 #undef MP_CASE
@@ -211,8 +213,8 @@ struct BEng {
     const ClassInfo& C = B->cls[c];
     const void* fn;
     int nthr;
-    if (!(mode == X_ITER ? x_kernel<T, X_ITER>(C.n[0], &fn, &nthr)
-                         : x_kernel<T, X_TRANS>(C.n[0], &fn, &nthr)))
+    if (!(mode == X_ITER ? x_kernel<T, X_ITER>(C.n[0], C.an, &fn, &nthr)
+                         : x_kernel<T, X_TRANS>(C.n[0], C.an, &fn, &nthr)))
       return hipErrorInvalidValue;
     const Rve<T>* rvp = rv(B);
     const Lists* lsp = B->ls;
@@ -318,7 +320,7 @@ mp_status default_sched(mp_batch B, ClassInfo& C) {
   }
   const void* fn;
   int nthr;
-  if (!x_kernel<T, X_ITER>(C.n[0], &fn, &nthr)) return fail(MP_E_INVALID, "no x kernel");
+  if (!x_kernel<T, X_ITER>(C.n[0], C.an, &fn, &nthr)) return fail(MP_E_INVALID, "no x kernel");
   HIP_TRY(BEng<T>::occupancy(fn, nthr, 0, B->cus, &C.xgrid));
   return MP_OK;
 }
@@ -468,7 +470,6 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   Geometry g;
   mp_status st = validate(prob, &g);
   if (st != MP_OK) return st;
-  if (g.n_aniso > 0) return fail(MP_E_INVALID, "phases with Eq. 5 tensors are supported by plans only");
   if (g.ref_tensor) return fail(MP_E_INVALID, "tensor reference media are supported by plans only");
   int ci = -1;
   for (int c = 0; c < int(B->cls.size()); ++c)
@@ -496,6 +497,11 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
 
   std::vector<PhaseC> pc(256);
   for (int i = 0; i < prob->n_phases; ++i) pc[i] = derive(prob->phases[i]);
+  std::vector<double> arows(aniso_words(g), 0.0);
+  for (int j = 0; j < g.n_aniso; ++j) {
+    aniso_rows(prob->aniso[j], &arows[size_t(j) * 162]);
+    pc[prob->aniso[j].phase].t.aid = double(j);
+  }
   std::vector<cx<T>> tw;
   twiddles(g.n0, &tw);
   twiddles(g.n1, &tw);
@@ -521,6 +527,8 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   x.phase = b + L.phase;
   x.params = reinterpret_cast<const PhaseC*>(b + L.params);
   x.partials = reinterpret_cast<double*>(b + L.partials);
+  x.aniso = reinterpret_cast<const double*>(b + L.aniso);
+  x.n_aniso = g.n_aniso;
   x.ref = ref;
   for (int c = 0; c < 9; ++c) {
     x.mac[c] = E[c];
@@ -579,6 +587,8 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   ADMIT_TRY(hipMemcpyAsync(b + L.phase, prob->phase, g.nvox, hipMemcpyHostToDevice, B->stream));
   ADMIT_TRY(hipMemcpyAsync(b + L.params, pc.data(), pc.size() * sizeof(PhaseC), hipMemcpyHostToDevice,
                            B->stream));
+  ADMIT_TRY(hipMemcpyAsync(b + L.aniso, arows.data(), arows.size() * sizeof(double), hipMemcpyHostToDevice,
+                           B->stream));
   ADMIT_TRY(hipMemcpyAsync(b + L.tw, tw.data(), tw.size() * sizeof(cx<T>), hipMemcpyHostToDevice,
                            B->stream));
   ADMIT_TRY(hipMemcpyAsync(b + H.path_off, path.data(), path.size() * sizeof(double),
@@ -591,6 +601,18 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   *id = B->next_id++;
   B->slot_id[slot] = *id;
   B->rves[*id] = H;
+  if (g.n_aniso > 0 && !B->cls[ci].an) {
+    // the class's x passes switch to the Eq. 5 variant: the next run captures
+    // the graph again (the stream is idle, see above)
+    B->cls[ci].an = true;
+    if (B->captured) {
+      (void)hipGraphExecDestroy(B->exec);
+      (void)hipGraphDestroy(B->graph);
+      B->exec = nullptr;
+      B->graph = nullptr;
+      B->captured = false;
+    }
+  }
   return MP_OK;
 }
 
@@ -661,7 +683,6 @@ mp_status mp_batch_footprint(const mp_batch_config* cfg, const mp_problem* prob,
   Geometry g;
   mp_status st = validate(prob, &g);
   if (st != MP_OK) return st;
-  if (g.n_aniso > 0) return fail(MP_E_INVALID, "phases with Eq. 5 tensors are supported by plans only");
   if (g.ref_tensor) return fail(MP_E_INVALID, "tensor reference media are supported by plans only");
   size_t po, ro;
   *bytes = align256(rve_bytes(layout(g, cfg->precision == MP_MIXED ? sizeof(float) : sizeof(double)),

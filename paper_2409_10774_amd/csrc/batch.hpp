@@ -67,8 +67,10 @@ struct Lists {
 // in the common case a block takes a single item.  No atomics: a shared
 // work counter serialises across the chip's L2 domains.
 // x pass of one shape class: ITER over the RUN list, or TRANS over the
-// TRANS list (separate kernels, so each keeps its own register budget)
-template <class T, int MODE, int N0>
+// TRANS list (separate kernels, so each keeps its own register budget); AN:
+// the Eq. 5 variant of the pass body, for a class holding an RVE with Eq. 5
+// phases (an RVE without them takes the same arithmetic in either variant)
+template <class T, int MODE, int N0, bool AN>
 __global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE>())) k_batch_x(const Rve<T>* __restrict__ rv,
                                                               const Lists* __restrict__ ls, int cls,
                                                               int tiles) {
@@ -93,7 +95,7 @@ __global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE>()
     const int slot = list[u / tiles];
     const int tile = int(u % tiles);
     __syncthreads();   // the previous item is done with LDS
-    xpass_tile<T, MODE, N0>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid());
+    xpass_tile<T, MODE, N0, AN>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid());
   }
 }
 

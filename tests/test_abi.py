@@ -180,11 +180,18 @@ def test_rejects_bad_anisotropic_phase(change, msg):
     assert ei.value.status == mp.MP_E_INVALID and msg in str(ei.value)
 
 
-def test_batch_rejects_anisotropic_phase():
+def test_batch_footprint_of_anisotropic_phase():
+    """A batch takes Eq. 5 phases (the footprint grows by their row
+    matrices); it rejects the tensor reference media."""
     from paper_2409_10774_amd import mp
     cfg = mp.batch_config([(16, 16, 16)], precision="fp64")
     n = mp.C.c_size_t()
+    st = mp.lib.mp_batch_footprint(mp.C.byref(cfg), mp.C.byref(base_problem()), 3, mp.C.byref(n))
+    plain = n.value
     p = aniso_problem()
+    st = mp.lib.mp_batch_footprint(mp.C.byref(cfg), mp.C.byref(p), 3, mp.C.byref(n))
+    assert st == mp.MP_OK and n.value >= plain
+    p.ref_mode = mp.MP_REF_TENSOR_PHASE_MEAN
     st = mp.lib.mp_batch_footprint(mp.C.byref(cfg), mp.C.byref(p), 3, mp.C.byref(n))
     assert st == mp.MP_E_INVALID and b"plans only" in mp.lib.mp_last_error()
 

@@ -66,8 +66,7 @@ enum { MP_ERR_LOCAL = 0, MP_ERR_AVERAGE = 1 };      /* Eq. 38 | Eq. 37 */
  * when a stiff phase fills a small volume).  With a tensor reference the
  * Green operator factors the 6x6 Fourier symbol at every frequency (it is
  * positive definite whenever <A> is, which valid phases ensure; <B> may be
- * singular on skew tensors, gamma = beta).  Plans only: a batch rejects the
- * tensor modes. */
+ * singular on skew tensors, gamma = beta). */
 enum { MP_REF_PHASE_MEAN = 0, MP_REF_VOLUME_MEAN = 1, MP_REF_EXPLICIT = 2, MP_REF_TENSOR_MEAN = 3,
        MP_REF_TENSOR_PHASE_MEAN = 4 };
 enum { MP_FIELD_E = 0, MP_FIELD_GAMMA = 1, MP_FIELD_T = 2, MP_FIELD_M = 3,

@@ -79,7 +79,9 @@ struct ClassInfo {
   Geometry g;
   PassSched pass[3];   // Y_FWD, Z_GREEN, Y_INV
   int xgrid;
-  bool an;             // an RVE with Eq. 5 phases was admitted: the x pass's Eq. 5 variant
+  bool an;             // an RVE with Eq. 5 phases or a tensor reference was admitted:
+                       // the x pass's Eq. 5 variant
+  bool tensor;         // an RVE with a tensor reference medium was admitted: Z_GREEN_AN
 };
 
 struct RveHost {
@@ -202,6 +204,7 @@ struct BEng {
     const int L = mode == Z_GREEN ? C.n[2] : C.n[1];
     bool ok = mode == Y_FWD   ? axis_kernel<T, Y_FWD>(L, tx, &fn, &nthr, &shm)
               : mode == Y_INV ? axis_kernel<T, Y_INV>(L, tx, &fn, &nthr, &shm)
+              : C.tensor      ? axis_kernel<T, Z_GREEN_AN>(L, tx, &fn, &nthr, &shm)
                               : axis_kernel<T, Z_GREEN>(L, tx, &fn, &nthr, &shm);
     if (!ok) return hipErrorInvalidValue;
     int cls = c, gx = C.g.nh / tx, gy = mode == Z_GREEN ? C.n[1] : C.n[2];
@@ -277,12 +280,13 @@ struct BEng {
         cand[nc++] = tw > 1 ? tw / 2 : 1;
         cand[nc++] = tw;
         for (int k = 0; k < nc; ++k)
-          for (int p = 0; p < 3; ++p) {
+          for (int p = 0; p < 4; ++p) {
             const void* fn;
             int nthr;
             size_t shm;
             bool ok = p == 0   ? axis_kernel<T, Y_FWD>(L, cand[k], &fn, &nthr, &shm)
                       : p == 2 ? axis_kernel<T, Y_INV>(L, cand[k], &fn, &nthr, &shm)
+                      : p == 3 ? axis_kernel<T, Z_GREEN_AN>(L, cand[k], &fn, &nthr, &shm)
                                : axis_kernel<T, Z_GREEN>(L, cand[k], &fn, &nthr, &shm);
             if (!ok) continue;
             hipError_t e =
@@ -470,7 +474,6 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   Geometry g;
   mp_status st = validate(prob, &g);
   if (st != MP_OK) return st;
-  if (g.ref_tensor) return fail(MP_E_INVALID, "tensor reference media are supported by plans only");
   int ci = -1;
   for (int c = 0; c < int(B->cls.size()); ++c)
     if (B->cls[c].n[0] == g.n0 && B->cls[c].n[1] == g.n1 && B->cls[c].n[2] == g.n2) ci = c;
@@ -502,6 +505,17 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
     aniso_rows(prob->aniso[j], &arows[size_t(j) * 162]);
     pc[prob->aniso[j].phase].t.aid = double(j);
   }
+  if (g.ref_tensor) {
+    // tensor reference medium: rows after the phases' records, then the
+    // coefficients of its Fourier symbol (the plan's layout)
+    mp_aniso r;
+    if ((st = reference_tensors(prob, g.nvox, &r)) != MP_OK) {
+      B->arena.release(H.off, H.bytes);
+      return st;
+    }
+    aniso_rows(r, &arows[size_t(g.n_aniso) * 162]);
+    green_symbol(r, &arows[size_t(g.n_aniso + 1) * 162]);
+  }
   std::vector<cx<T>> tw;
   twiddles(g.n0, &tw);
   twiddles(g.n1, &tw);
@@ -529,6 +543,7 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   x.partials = reinterpret_cast<double*>(b + L.partials);
   x.aniso = reinterpret_cast<const double*>(b + L.aniso);
   x.n_aniso = g.n_aniso;
+  if (g.ref_tensor) x.refan = x.aniso + size_t(g.n_aniso) * 162;
   x.ref = ref;
   for (int c = 0; c < 9; ++c) {
     x.mac[c] = E[c];
@@ -554,6 +569,7 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   z.h = prob->h;
   z.scale = 1.0 / double(g.nvox);
   z.ref = ref;
+  if (g.ref_tensor) z.gsym = x.aniso + size_t(g.n_aniso + 1) * 162;
   const double* pth = reinterpret_cast<const double*>(b + H.path_off);
   R.times = pth;
   R.Ep = pth + n_steps + 1;
@@ -601,10 +617,13 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   *id = B->next_id++;
   B->slot_id[slot] = *id;
   B->rves[*id] = H;
-  if (g.n_aniso > 0 && !B->cls[ci].an) {
-    // the class's x passes switch to the Eq. 5 variant: the next run captures
-    // the graph again (the stream is idle, see above)
-    B->cls[ci].an = true;
+  const bool an = g.n_aniso > 0 || g.ref_tensor;
+  if ((an && !B->cls[ci].an) || (g.ref_tensor && !B->cls[ci].tensor)) {
+    // the class's x passes switch to the Eq. 5 variant, its z pass to the
+    // general Green step: the next run captures the graph again (the stream
+    // is idle, see above)
+    B->cls[ci].an = B->cls[ci].an || an;
+    B->cls[ci].tensor = B->cls[ci].tensor || g.ref_tensor;
     if (B->captured) {
       (void)hipGraphExecDestroy(B->exec);
       (void)hipGraphDestroy(B->graph);
@@ -683,7 +702,6 @@ mp_status mp_batch_footprint(const mp_batch_config* cfg, const mp_problem* prob,
   Geometry g;
   mp_status st = validate(prob, &g);
   if (st != MP_OK) return st;
-  if (g.ref_tensor) return fail(MP_E_INVALID, "tensor reference media are supported by plans only");
   size_t po, ro;
   *bytes = align256(rve_bytes(layout(g, cfg->precision == MP_MIXED ? sizeof(float) : sizeof(double)),
                               n_steps, &po, &ro));

@@ -660,7 +660,9 @@ __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, 
         const T x1 = T(tp * kx / (a.n0 * a.h));
         const T x2 = T(tp * my / (a.n1 * a.h));
         const T x3 = T(tp * mz / (a.n2 * a.h));
-        if constexpr (MODE == Z_GREEN_AN)
+        // Z_GREEN_AN also serves an isotropic reference (gsym null): a batch
+        // class may hold both kinds of RVE
+        if (MODE == Z_GREEN_AN && a.gsym)
           green_apply_gen<T>(glob(a.gsym), x1, x2, x3, T(a.scale), tau, mu);
         else
           green_apply<T>(a.ref, x1, x2, x3, T(a.scale), tau, mu);

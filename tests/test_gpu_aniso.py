@@ -6,8 +6,10 @@ HIP path (the x pass's Eq. 5 variant), against the oracle:
     iteration counts, fields and response curves within 1e-10;
   - the same cell in mixed precision on a fixed schedule, against the FP64
     path on that schedule;
-  - a resident batch holding Eq. 5 and isotropic RVEs: every RVE equals its
-    solo plan bit for bit (FP64 and mixed).
+  - a resident batch holding Eq. 5 and isotropic RVEs, with isotropic and
+    tensor reference media in one shape class, admitted after the first
+    graph capture: every RVE equals its solo plan bit for bit (FP64 and
+    mixed).
 """
 import numpy as np
 import pytest
@@ -114,25 +116,28 @@ def test_batch_with_anisotropic_phases_equals_solo(mp, precision):
     a1 = cell()
     a2 = cell(steps=2)
     a2.phases = [a2.phases[0], W.anisotropic_phase(9, t_scale=2.5, m_scale=3.0)]
+    a2.ref_mode = "tensor_phase_mean"
     iso = small_workload((16, 16, 16), seed=40, contrast=3.0, steps=3, G_end=0.002)
-    wls = [a1, iso, a2]
+    iso2 = small_workload((16, 16, 16), seed=45, contrast=4.0, steps=2, G_end=0.0)
+    iso2.ref_mode = "tensor_phase_mean"
+    wls = [a1, iso, a2, iso2]
     for w in wls:
         w.tol = 1e-8 if precision == "fp64" else 1e-6
     B = mp.Batch([(12, 6, 8), (16, 16, 16)], arena_bytes=128 << 20, precision=precision, max_rves=8,
                  iters_per_launch=8, autotune=False)
     # the isotropic RVE runs first (graph captured with the plain x passes);
     # admitting the Eq. 5 RVEs switches their class to the Eq. 5 variant
-    ids = [None, B.admit(iso.phase_map, iso.phases, iso.times, iso.E, iso.G, tol=iso.tol), None]
+    ids = [None, B.admit(iso.phase_map, iso.phases, iso.times, iso.E, iso.G, tol=iso.tol), None, None]
     for _ in range(3):
         B.run()
-    for k in (0, 2):
+    for k in (0, 2, 3):
         w = wls[k]
-        ids[k] = B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol)
+        ids[k] = B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol, ref_mode=w.ref_mode)
     B.drain()
     for rid, w in zip(ids, wls):
         b = batched(B, rid)
         assert b["state"] == mp.MP_RVE_DONE
-        s = solo(mp, w, precision)
+        s = solo(mp, w, precision, ref_mode=w.ref_mode)
         say(f"  rve {rid} n={w.phase_map.shape} iters {b['iters']} solo {s['iters']}")
         assert_same(b, s, rid)
     B.close()

@@ -617,6 +617,47 @@ __device__ __forceinline__ void axis_fetch(const AxisArgs<T>& a, int bx, int by,
   }
 }
 
+// Green operator at the L * TX frequencies of z-pass tile (bx, by), in LDS
+// (GEN: the factored symbol of a tensor reference medium, else the closed
+// form of an isotropic one)
+template <class T, int L, int TX, bool GEN>
+__device__ __forceinline__ void green_tile(const AxisArgs<T>& a, int bx, int by, cx<T>* lds, int tid) {
+  using A = AShape<L, TX>;
+  constexpr int NB = A::NB, NTHR = A::NTHR;
+  for (int f = tid; f < L * TX; f += NTHR) {
+    const int kz = f / TX, xl = f % TX;
+    const int kx = bx * TX + xl, ky = by;
+    cx<T>* p = lds + kz * NB + xl * 18;
+    const bool zero = (kx == 0 && ky == 0 && kz == 0) || (2 * ky == a.n1) || (2 * kz == a.n2);
+    if (zero) {
+#pragma unroll
+      for (int c = 0; c < 18; ++c) p[c] = cx<T>{T(0), T(0)};
+    } else {
+      cx<T> tau[9], mu[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        tau[c] = p[c];
+        mu[c] = p[9 + c];
+      }
+      const double tp = 6.283185307179586476925286766559;
+      const int my = (2 * ky < a.n1) ? ky : ky - a.n1;
+      const int mz = (2 * kz < a.n2) ? kz : kz - a.n2;
+      const T x1 = T(tp * kx / (a.n0 * a.h));
+      const T x2 = T(tp * my / (a.n1 * a.h));
+      const T x3 = T(tp * mz / (a.n2 * a.h));
+      if constexpr (GEN)
+        green_apply_gen<T>(glob(a.gsym), x1, x2, x3, T(a.scale), tau, mu);
+      else
+        green_apply<T>(a.ref, x1, x2, x3, T(a.scale), tau, mu);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        p[c] = tau[c];
+        p[9 + c] = mu[c];
+      }
+    }
+  }
+}
+
 // tile (bx, by): kx in [bx TX, bx TX + TX), kz = by (y pass) or ky = by (z
 // pass); tw: the L-entry twiddle table in LDS.  The caller has synchronised
 // the block since LDS was last read.
@@ -638,41 +679,14 @@ __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, 
   constexpr bool INV = MODE == Y_INV;
   fft_ct<T, INV, L, 1, NB, NB, 1, true, NTHR>(lds, tw, tid);
   if (MODE == Z_GREEN || MODE == Z_GREEN_AN) {
-    // Green operator at the L * TX frequencies of the tile
-    for (int f = tid; f < L * TX; f += NTHR) {
-      const int kz = f / TX, xl = f % TX;
-      const int kx = bx * TX + xl, ky = by;
-      cx<T>* p = lds + kz * NB + xl * 18;
-      const bool zero = (kx == 0 && ky == 0 && kz == 0) || (2 * ky == a.n1) || (2 * kz == a.n2);
-      if (zero) {
-#pragma unroll
-        for (int c = 0; c < 18; ++c) p[c] = cx<T>{T(0), T(0)};
-      } else {
-        cx<T> tau[9], mu[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          tau[c] = p[c];
-          mu[c] = p[9 + c];
-        }
-        const double tp = 6.283185307179586476925286766559;
-        const int my = (2 * ky < a.n1) ? ky : ky - a.n1;
-        const int mz = (2 * kz < a.n2) ? kz : kz - a.n2;
-        const T x1 = T(tp * kx / (a.n0 * a.h));
-        const T x2 = T(tp * my / (a.n1 * a.h));
-        const T x3 = T(tp * mz / (a.n2 * a.h));
-        // Z_GREEN_AN also serves an isotropic reference (gsym null): a batch
-        // class may hold both kinds of RVE
-        if (MODE == Z_GREEN_AN && a.gsym)
-          green_apply_gen<T>(glob(a.gsym), x1, x2, x3, T(a.scale), tau, mu);
-        else
-          green_apply<T>(a.ref, x1, x2, x3, T(a.scale), tau, mu);
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          p[c] = tau[c];
-          p[9 + c] = mu[c];
-        }
-      }
-    }
+    // Green operator at the L * TX frequencies of the tile.  Z_GREEN_AN also
+    // serves an isotropic reference (gsym null: a batch class may hold both
+    // kinds of RVE); the choice is made per tile, around the whole loop, so
+    // that the two solves never share one loop body's registers
+    if (MODE == Z_GREEN_AN && a.gsym)
+      green_tile<T, L, TX, true>(a, bx, by, lds, tid);
+    else
+      green_tile<T, L, TX, false>(a, bx, by, lds, tid);
     __syncthreads();
     fft_ct<T, true, L, 1, NB, NB, 1, true, NTHR>(lds, tw, tid);
   }

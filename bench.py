@@ -39,11 +39,11 @@ def bytes_per_voxel(w):
 # only for the kernel sources they were taken on (SHA-1 of the two headers)
 MEASURED_TRAFFIC = {
     "spheres128_fp64": {"kernel": "x_pass", "bytes": (942.0 + 619.7) * 1e6,
-                        "src_sha1": "96bb65c6c40e1970db8c16a6dbdf0a4366520440"},
-    "spheres256_mixed": {"kernel": "x_pass", "bytes": (3909.4 + 2479.8) * 1e6,
-                         "src_sha1": "96bb65c6c40e1970db8c16a6dbdf0a4366520440"},
+                        "src_sha1": "bcdf79083ade8cab15659828111ae7f889b7ed72"},
+    "spheres256_mixed": {"kernel": "x_pass", "bytes": (3909.4 + 2479.9) * 1e6,
+                         "src_sha1": "bcdf79083ade8cab15659828111ae7f889b7ed72"},
     "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.1 + 619.8) * 1e6,
-                      "src_sha1": "96bb65c6c40e1970db8c16a6dbdf0a4366520440"},
+                      "src_sha1": "bcdf79083ade8cab15659828111ae7f889b7ed72"},
 }
 
 

@@ -9,7 +9,9 @@ HIP path (the x pass's Eq. 5 variant), against the oracle:
   - a resident batch holding Eq. 5 and isotropic RVEs, with isotropic and
     tensor reference media in one shape class, admitted after the first
     graph capture: every RVE equals its solo plan bit for bit (FP64 and
-    mixed).
+    mixed);
+  - the continuous-batching server with Eq. 5 and tensor-reference requests
+    arriving mid-run: every request served with the solo iteration counts.
 """
 import numpy as np
 import pytest
@@ -140,4 +142,30 @@ def test_batch_with_anisotropic_phases_equals_solo(mp, precision):
         s = solo(mp, w, precision, ref_mode=w.ref_mode)
         say(f"  rve {rid} n={w.phase_map.shape} iters {b['iters']} solo {s['iters']}")
         assert_same(b, s, rid)
+    B.close()
+
+
+def test_serving_with_anisotropic_requests(mp):
+    say("case: serving loop with Eq. 5 and tensor-reference requests arriving mid-run")
+    import numpy as np
+    from tests.test_gpu_batch import solo
+    from tests.test_gpu_parity import small_workload
+    iso = small_workload((16, 16, 16), seed=40, contrast=3.0, steps=3, G_end=0.002)
+    a1 = cell()
+    a2 = cell(steps=2)
+    a2.phases = [a2.phases[0], W.anisotropic_phase(9, t_scale=2.5, m_scale=3.0)]
+    kw = [dict(), dict(), dict(ref_mode="tensor_phase_mean")]
+    wls = [iso, a1, a2]
+    for w in wls:
+        w.tol = 1e-6
+    arrivals = np.array([0.0, 0.01, 0.02])
+    items = [(t, w.phase_map, w.phases, w.times, w.E, w.G, dict(tol=w.tol, **k))
+             for t, w, k in zip(arrivals, wls, kw)]
+    B = mp.Batch([(12, 6, 8), (16, 16, 16)], arena_bytes=128 << 20, precision="mixed", max_rves=8,
+                 iters_per_launch=8)
+    ta, td, st, it = mp.serve_batched(B, mp.Requests(items, precision="mixed"))
+    say("admit", np.round(ta, 3), "done", np.round(td, 3), "iters", it)
+    assert (st == mp.MP_OK).all()
+    for i, (w, k) in enumerate(zip(wls, kw)):
+        assert it[i] == sum(solo(mp, w, "mixed", **k)["iters"]), i
     B.close()

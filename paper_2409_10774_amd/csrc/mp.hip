@@ -127,9 +127,12 @@ struct Eng {
     mark(0);
     launch_axis<T, Y_FWD>(g.n1, g.txy, g.nh / g.txy, g.n2, P->stream, ay, ctl);
     mark(1);
-    if (P->gsym)
-      launch_axis<T, Z_GREEN_AN>(g.n2, g.txz, g.nh / g.txz, g.n1, P->stream, az, ctl);
-    else
+    if (P->gsym) {
+      // FP64: one-wide tiles, whose kernels hold the per-frequency
+      // factorisation without spilling (0.149 against 0.162 ms at 128^3)
+      const int tx = sizeof(T) == 8 ? 1 : g.txz;
+      launch_axis<T, Z_GREEN_AN>(g.n2, tx, g.nh / tx, g.n1, P->stream, az, ctl);
+    } else
       launch_axis<T, Z_GREEN>(g.n2, g.txz, g.nh / g.txz, g.n1, P->stream, az, ctl);
     mark(2);
     launch_axis<T, Y_INV>(g.n1, g.txy, g.nh / g.txy, g.n2, P->stream, ay, ctl);

@@ -11,7 +11,8 @@ with every phase's own law) on the HIP path, against the oracle:
     fewer iterations than with the isotropic phase-mean reference;
   - the same cell in mixed precision on a fixed schedule against FP64;
   - the 128^3 cell of Eq. 5 spheres (the benchmark's anisotropic workload)
-    at full size on a fixed schedule, against the oracle.
+    at full size on a fixed schedule, against the oracle;
+  - the paper's manufactured solution (App. D.1) with a tensor reference.
 """
 import numpy as np
 import pytest
@@ -153,3 +154,43 @@ def test_aniso128_full_size_fixed_schedule(mp):
     errs = {k: rel(plan.field(k), f[k]) for k in ("e", "g", "t", "m", "p", "q")}
     say("field rel errors", errs)
     assert max(errs.values()) < TOL
+
+
+def test_manufactured_solution_with_tensor_reference(mp):
+    """The paper's code verification (App. D.1) with a tensor reference
+    medium: the manufactured fields do not depend on the reference, so the
+    general Green step and the row-matrix polarization must reproduce them
+    within the same bound, and the oracle's fields (same reference) within
+    1e-10."""
+    from tests.mnms_case import case
+    say("case: App. D.1 manufactured solution, 4^3, 25 steps, tensor phase-mean reference")
+    n_steps = 25
+    c = case(n_steps)
+    times, Em, Gm, tm, mm = c["times"], c["Em"], c["Gm"], c["tm"], c["mm"]
+    E = times[1:, None] * Em.reshape(1, 9)
+    G = times[1:, None] * Gm.reshape(1, 9)
+    check = (n_steps // 2, n_steps)
+    plan = mp.Plan(c["pm"], c["phases"], h=c["h"], tol=c["eps"], ref_mode="tensor_phase_mean")
+    it_gpu, got = [], {}
+    for s in range(1, n_steps + 1):
+        plan.set_eigenstress(np.concatenate([O.to_f9(tm[s - 1]), O.to_f9(mm[s - 1])]))
+        it_gpu += plan.solve(times[s - 1: s + 1], E[s - 1: s], G[s - 1: s])
+        if s in check:
+            got[s] = {k: plan.field(k) for k in ("e", "g", "t", "m")}
+    eig = lambda s: (tm[s - 1], mm[s - 1])
+    solver = lambda: O.Solver(c["pm"], c["phases"], h=c["h"], tol=c["eps"], ref_mode="tensor_phase_mean")
+    out = solver().solve(times, E, G, eig=eig, fields_at=check)
+    say("iterations gpu", it_gpu, "oracle", out["iters"])
+    if it_gpu != out["iters"]:
+        out = solver().solve(times, E, G, schedule=it_gpu, eig=eig, fields_at=check)
+    for s in check:
+        tt = times[s]
+        man = {"e": O.to_f9(tt * c["De"]), "g": O.to_f9(tt * c["Dg"]),
+               "t": O.to_f9(tm[s - 1]), "m": O.to_f9(mm[s - 1])}
+        for k, ref in man.items():
+            err_man = np.abs(got[s][k] - ref).max()
+            err_orc = rel(got[s][k], out["fields"][s][k])
+            say(f"step {s} {k}: |gpu - manufactured| {err_man:.2e}, rel vs oracle {err_orc:.2e}")
+            assert err_man < c["bound"], (s, k, err_man)
+            assert err_orc < TOL, (s, k, err_orc)
+    plan.set_eigenstress(None)

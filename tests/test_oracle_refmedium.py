@@ -114,14 +114,15 @@ def test_tensor_mean_of_isotropic_phases():
         assert np.abs(x - y).max() < 1e-12 * np.abs(x).max()
 
 
-def test_fixed_point_does_not_depend_on_the_reference():
+@pytest.mark.parametrize("mode", ["tensor_mean", "tensor_phase_mean"])
+def test_fixed_point_does_not_depend_on_the_reference(mode):
     pm = W.centred_sphere(6, 0.2)
     mat = W.matrix_phase(kappa=0.5, tY=0.004)
     inc = W.anisotropic_phase(5, t_scale=3.0, m_scale=4.0)
     times, E, G = W.ramp_path(2, E_end=W.unit((0, 0), 0.01) + W.unit((1, 2), 0.004),
                               G_end=W.unit((0, 1), 0.002))
     tol = 1e-11
-    a = O.Solver(pm, [mat, inc], tol=tol, ref_mode="tensor_mean").solve(times, E, G, fields_at=(2,))
+    a = O.Solver(pm, [mat, inc], tol=tol, ref_mode=mode).solve(times, E, G, fields_at=(2,))
     b = O.Solver(pm, [mat, inc], tol=tol).solve(times, E, G, fields_at=(2,))
     assert a["fields"][2]["p"].max() > 0
     for k in ("e", "g", "t", "m", "p", "q"):

@@ -176,6 +176,36 @@ def test_full_path_small_grids(torch, mp, n):
     compare_run(mp, plan, wl, len(wl.E))
 
 
+def long_axis_workload(n, seed, count=4):
+    """Thin cell with one axis of 256 points: periodic spheres (r in [1.5, 3])
+    placed from the seed, so the inclusions cross the short axes' periodic
+    boundaries and lie along the long one."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(*(np.arange(k) + 0.5 for k in n[::-1]), indexing="ij")
+    ph = np.zeros(n[::-1], np.uint8)
+    for _ in range(count):
+        c = [rng.uniform(0, k) for k in n]
+        r = rng.uniform(1.5, 3.0)
+        d2 = np.zeros(ph.shape)
+        for coord, ck, k in zip((x, y, z), c, n):
+            d = np.abs(coord - ck)
+            d2 += np.minimum(d, k - d) ** 2
+        ph[d2 < r * r] = 1
+    assert 0 < ph.sum() < ph.size
+    wl = small_workload((4, 4, 4), seed)
+    return W.Workload("long", ph, wl.phases, wl.times, wl.E, wl.G, tol=wl.tol)
+
+
+@pytest.mark.parametrize("n", [(256, 6, 4), (4, 6, 256)])
+def test_full_path_long_axis(torch, mp, n):
+    """The 256-point x pass (one Alg. 1 level per block) and z pass in FP64,
+    full Alg. 2 against the oracle on a ragged thin cell."""
+    say(f"case: Alg. 2 long-axis grid n={n}")
+    wl = long_axis_workload(n, seed=sum(n))
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol)
+    compare_run(mp, plan, wl, len(wl.E))
+
+
 def test_full_path_sphere16_all_steps(torch, mp):
     say("case: 16^3 centred sphere, 10 steps, FP64")
     wl = W.single_sphere_16()

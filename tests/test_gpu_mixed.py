@@ -25,7 +25,7 @@ import pytest
 
 from oracle import micropolar as O
 from paper_2409_10774_amd import workloads as W
-from tests.test_gpu_parity import rel, say, small_workload
+from tests.test_gpu_parity import long_axis_workload, rel, say, small_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -86,6 +86,24 @@ def test_mixed_vs_oracle_same_schedule(mp, n):
     say("oracle converged on its own schedule", conv["iters"], "field rel (information)",
         {k: "%.1e" % rel(plan.field(k), fc[k]) for k in ("e", "t", "m")},
         "curve rel %.1e" % curve_rel(plan.responses()[:, :40], conv["resp"]))
+
+
+@pytest.mark.parametrize("n", [(256, 6, 4), (4, 6, 256)])
+def test_mixed_long_axis_vs_oracle(mp, n):
+    """The FP32 x pass and z pass at 256 points (one-wide z tiles) on thin
+    cells: mixed precision against the oracle on the mixed schedule."""
+    say(f"case: mixed precision vs oracle on a long-axis cell, n={n}")
+    wl = long_axis_workload(n, seed=sum(n))
+    wl.tol = 1e-6
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision="mixed")
+    it = plan.solve(wl.times, wl.E, wl.G)
+    ref = O.Solver(wl.phase_map, wl.phases, tol=wl.tol)
+    out = ref.solve(wl.times, wl.E, wl.G, schedule=it, fields_at=(len(wl.E),))
+    f = out["fields"][len(wl.E)]
+    errs = {k: rel(plan.field(k), f[k]) for k in ("e", "g", "t", "m", "p", "q")}
+    c = response_rel(plan.responses()[:, :40], out["resp"], f)
+    say("mixed iterations", it, "field rel", errs, "response rel %.2e" % c)
+    assert max(errs.values()) < BOUND and c < BOUND
 
 
 def test_mixed_vs_fp64_gpu_256(mp):

@@ -177,8 +177,8 @@ def test_full_path_small_grids(torch, mp, n):
 
 
 def long_axis_workload(n, seed, count=4):
-    """Thin cell with one axis of 256 points: periodic spheres (r in [1.5, 3])
-    placed from the seed, so the inclusions cross the short axes' periodic
+    """Thin cell with one long axis: periodic spheres (r in [1.5, 3]) placed
+    from the seed, so the inclusions cross the short axes' periodic
     boundaries and lie along the long one."""
     rng = np.random.default_rng(seed)
     z, y, x = np.meshgrid(*(np.arange(k) + 0.5 for k in n[::-1]), indexing="ij")
@@ -196,10 +196,11 @@ def long_axis_workload(n, seed, count=4):
     return W.Workload("long", ph, wl.phases, wl.times, wl.E, wl.G, tol=wl.tol)
 
 
-@pytest.mark.parametrize("n", [(256, 6, 4), (4, 6, 256)])
+@pytest.mark.parametrize("n", [(256, 6, 4), (4, 6, 256), (192, 4, 6), (6, 4, 192), (48, 8, 6)])
 def test_full_path_long_axis(torch, mp, n):
-    """The 256-point x pass (one Alg. 1 level per block) and z pass in FP64,
-    full Alg. 2 against the oracle on a ragged thin cell."""
+    """x passes and z passes of 256, 192 and 48 points in FP64 (one Alg. 1
+    level per block above 128), full Alg. 2 against the oracle on a ragged
+    thin cell."""
     say(f"case: Alg. 2 long-axis grid n={n}")
     wl = long_axis_workload(n, seed=sum(n))
     plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol)

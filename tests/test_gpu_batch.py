@@ -15,7 +15,7 @@ import pytest
 
 from oracle import micropolar as O
 from paper_2409_10774_amd import workloads as W
-from tests.test_gpu_parity import rel, say, small_workload
+from tests.test_gpu_parity import long_axis_workload, rel, say, small_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -89,6 +89,32 @@ def test_batch_equals_solo(mp, precision, tol):
     ids = [B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol) for w in wls]
     launches = B.drain()
     say("graph launches", launches, B.stats())
+    for rid, w in zip(ids, wls):
+        b = batched(B, rid)
+        assert b["state"] == mp.MP_RVE_DONE
+        s = solo(mp, w, precision)
+        say(f"  rve {rid} n={w.phase_map.shape} iters {b['iters']} solo {s['iters']}")
+        assert_same(b, s, rid)
+        assert b["total"] == sum(s["iters"])
+    B.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
+def test_batch_long_axis_equals_solo(mp, precision, tol):
+    """Classes with 256- and 192-point axes (x passes with one Alg. 1 level
+    per block, one-wide z tiles) in one batch: bit for bit the solo plans."""
+    shapes = [(256, 6, 4), (4, 6, 256), (192, 4, 6)]
+    say(f"case: batch of thin long-axis RVEs {shapes} vs solo plans, {precision}")
+    wls = []
+    for n in shapes:
+        w = long_axis_workload(n, seed=sum(n))
+        w.tol = tol
+        wls.append(w)
+    B = mp.Batch(shapes, arena_bytes=256 << 20, precision=precision, max_rves=8,
+                 iters_per_launch=8, autotune=True)
+    ids = [B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol) for w in wls]
+    launches = B.drain()
+    say("graph launches", launches)
     for rid, w in zip(ids, wls):
         b = batched(B, rid)
         assert b["state"] == mp.MP_RVE_DONE

@@ -88,10 +88,10 @@ def test_mixed_vs_oracle_same_schedule(mp, n):
         "curve rel %.1e" % curve_rel(plan.responses()[:, :40], conv["resp"]))
 
 
-@pytest.mark.parametrize("n", [(256, 6, 4), (4, 6, 256)])
+@pytest.mark.parametrize("n", [(256, 6, 4), (4, 6, 256), (192, 4, 6), (6, 4, 192)])
 def test_mixed_long_axis_vs_oracle(mp, n):
-    """The FP32 x pass and z pass at 256 points (one-wide z tiles) on thin
-    cells: mixed precision against the oracle on the mixed schedule."""
+    """The FP32 x pass and z pass at 256 and 192 points (one-wide z tiles) on
+    thin cells: mixed precision against the oracle on the mixed schedule."""
     say(f"case: mixed precision vs oracle on a long-axis cell, n={n}")
     wl = long_axis_workload(n, seed=sum(n))
     wl.tol = 1e-6

@@ -27,8 +27,9 @@
  *     index.
  *   - All work is enqueued on the caller's HIP stream (hipStream_t passed as
  *     void*; NULL = default stream).  Device memory comes from the caller: the
- *     library allocates none.  Host arrays are copied during the call and
- *     never retained.
+ *     library allocates none (its one static device buffer, that of
+ *     mp_green_apply_noalloc, aside).  Host arrays are copied during the call
+ *     and never retained.
  *   - Errors are returned as mp_status; mp_last_error() gives a thread-local
  *     message.  No C++ exception crosses this boundary.
  */
@@ -189,6 +190,31 @@ mp_status mp_plan_steps(mp_plan plan, int32_t* steps);
 mp_status mp_green_apply(mp_plan plan, const void* dev_in, void* dev_out);
 /* (mp_green_apply, mp_spectrum_forward and mp_radial_return accept FP64
  * plans only and return MP_E_INVALID for MP_MIXED plans.) */
+
+/* Allocation-free variant of mp_green_apply, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Applies rows b-d above to 18 real FP64
+ * fields without a plan: forward transform, the Green operator of the
+ * isotropic reference medium ref = {lambda0, mu0, kappa0, alpha0, beta0,
+ * gamma0} (Eq. 6 constants) on the grid n[0] x n[1] x n[2] of voxel size h,
+ * inverse transform.  dev_in: 18*n device doubles (tau then mu, SoA,
+ * component 3k + l); dev_out: 18*n device doubles receiving the fluctuating
+ * strain then curvature (no averages added); they must not overlap; both
+ * stay owned by the caller.  The half spectra and the twiddle tables live in
+ * a static device buffer of the library, 48 MiB on every device it runs on,
+ * held until the process ends: 18 * n[2] * n[1] * (n[0]/2) * 16 bytes plus
+ * the twiddles must fit (every grid up to 64^3 does); a larger grid, an
+ * unsupported size, h <= 0 or a reference that is not positive definite
+ * gives MP_E_INVALID before any device work.  The call allocates nothing and
+ * does not synchronise: the work is enqueued on hip_stream and the buffer is
+ * in use until it has run.  Every call on one device shares that device's
+ * buffer, which keeps the last call's contents: calls that overlap in time on
+ * one device (different streams or threads) race and corrupt each other's
+ * results; calls ordered on one stream are safe.  The results equal
+ * mp_green_apply's on an FP64 plan with the same grid, h and reference
+ * medium, up to the rounding of the twiddles (computed on the device here). */
+mp_status mp_green_apply_noalloc(const int32_t n[3], double h, const double ref[6],
+                                 const void* dev_in, void* dev_out, void* hip_stream);
 
 /* Forward transform of 18 real fields (device, 18*n doubles, SoA) to their
  * half spectra: dev_out receives n[2] * n[1] * (n[0]/2) * 18 complex doubles

@@ -768,19 +768,7 @@ mp_status mp_batch_create(const mp_batch_config* cfg, void* dev_workspace, size_
   for (int c = 0; c < cfg->n_shapes; ++c) {
     ClassInfo& C = B->cls[c];
     for (int i = 0; i < 3; ++i) C.n[i] = cfg->shapes[c][i];
-    // geometry of the class (validated with a one-voxel-phase dummy problem)
-    Geometry& g = C.g;
-    g.n0 = C.n[0];
-    g.n1 = C.n[1];
-    g.n2 = C.n[2];
-    g.nh = g.n0 / 2;
-    g.nvox = long(g.n0) * g.n1 * g.n2;
-    g.nspec = long(g.n2) * g.n1 * g.nh;
-    g.nrows = long(g.n1) * g.n2;
-    const int rows = x_rows(g.n0);
-    g.xblocks = int((g.nrows + rows - 1) / rows);
-    g.txy = (g.nh % tx_wide(g.n1) == 0) ? tx_wide(g.n1) : 1;
-    g.txz = (g.nh % tx_wide(g.n2) == 0) ? tx_wide(g.n2) : 1;
+    C.g = grid_geometry(C.n[0], C.n[1], C.n[2]);
     mp_status st = mixed ? BEng<float>::setup_class(B, C) : BEng<double>::setup_class(B, C);
     if (st != MP_OK) return bail(st);
   }

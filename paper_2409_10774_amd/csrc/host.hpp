@@ -234,6 +234,21 @@ inline mp_status reference_tensors(const mp_problem* prob, long nvox, mp_aniso* 
   return MP_OK;
 }
 
+// Sizes, x-pass tiles and y / z tile widths of an n0 x n1 x n2 grid (every
+// n a supported length); no phases and no tensor reference
+inline Geometry grid_geometry(int n0, int n1, int n2) {
+  Geometry G{};
+  G.n0 = n0; G.n1 = n1; G.n2 = n2; G.nh = n0 / 2;
+  G.nvox = long(n0) * n1 * n2;
+  G.nspec = long(n2) * n1 * G.nh;
+  G.nrows = long(n1) * n2;
+  const int rows = x_rows(n0);
+  G.xblocks = int((G.nrows + rows - 1) / rows);
+  G.txy = (G.nh % tx_wide(n1) == 0) ? tx_wide(n1) : 1;
+  G.txz = (G.nh % tx_wide(n2) == 0) ? tx_wide(n2) : 1;
+  return G;
+}
+
 inline mp_status validate(const mp_problem* p, Geometry* g) {
   if (!p) return fail(MP_E_INVALID, "problem is NULL");
   for (int i = 0; i < 3; ++i)
@@ -290,15 +305,7 @@ inline mp_status validate(const mp_problem* p, Geometry* g) {
   for (long i = 0; i < nvox; ++i)
     if (p->phase[i] >= p->n_phases) return fail(MP_E_INVALID, "phase id out of range");
 
-  Geometry G{};
-  G.n0 = p->n[0]; G.n1 = p->n[1]; G.n2 = p->n[2]; G.nh = G.n0 / 2;
-  G.nvox = nvox;
-  G.nspec = long(G.n2) * G.n1 * G.nh;
-  G.nrows = long(G.n1) * G.n2;
-  const int rows = x_rows(G.n0);
-  G.xblocks = int((G.nrows + rows - 1) / rows);
-  G.txy = (G.nh % tx_wide(G.n1) == 0) ? tx_wide(G.n1) : 1;
-  G.txz = (G.nh % tx_wide(G.n2) == 0) ? tx_wide(G.n2) : 1;
+  Geometry G = grid_geometry(p->n[0], p->n[1], p->n[2]);
   G.n_aniso = p->n_aniso;
   G.ref_tensor = p->ref_mode == MP_REF_TENSOR_MEAN || p->ref_mode == MP_REF_TENSOR_PHASE_MEAN ? 1 : 0;
   if (G.ref_tensor) {

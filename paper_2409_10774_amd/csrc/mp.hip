@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,18 @@ __global__ void k_err_final(const double* tot, long nvox, Ctl* ctl, ErrMacro mac
 
 __global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm, int window) {
   ctl_reset(ctl, fixed, max_iter, tol, norm, window);
+}
+
+// FFT twiddle tables exp(-2 pi i m / n) of the three axes, one after the
+// other (n0, then n1, then n2 entries), for the allocation-free spectral step
+__global__ void k_twiddles(cx<double>* tw, int n0, int n1, int n2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n0 + n1 + n2) return;
+  const int n = i < n0 ? n0 : i < n0 + n1 ? n1 : n2;
+  const int m = i < n0 ? i : i < n0 + n1 ? i - n0 : i - n0 - n1;
+  double sn, cs;
+  sincospi(-2.0 * double(m) / double(n), &sn, &cs);
+  tw[i] = cx<double>{cs, sn};
 }
 
 }  // namespace mp
@@ -310,6 +323,43 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     if (r != MP_OK) return r;
   }
   if (st != MP_OK) return fail(st, msg);
+  return MP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free spectral step (mp_green_apply_noalloc): the
+// half spectra and the twiddle tables live in this file-scope device array,
+// of which every device holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel: on the host it is a
+// stand-in, not a device address.  It uses the address hipGetSymbolAddress
+// gives for the current device.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(48) << 20;   // 48 MiB: an FP64 64^3 grid fits
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices];   // scratch's device address per device (null: not set up)
+
+// Device address of `scratch` on the current device; the first call on a
+// device also raises the axis kernels' LDS limits there.
+mp_status scratch_address(unsigned char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MP_E_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(MP_E_DEVICE, "hipGetSymbolAddress gave a null scratch address");
+    HIP_TRY(Eng<double>::prepare());
+    g_scratch_dev[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
   return MP_OK;
 }
 
@@ -617,6 +667,67 @@ mp_status mp_radial_return(mp_plan P, int64_t n, const void* phase, const void* 
                      static_cast<double*>(q));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(P->stream));
+  return MP_OK;
+}
+
+mp_status mp_green_apply_noalloc(const int32_t n[3], double h, const double ref[6], const void* dev_in,
+                                 void* dev_out, void* hip_stream) {
+  if (!n || !ref || !dev_in || !dev_out) return fail(MP_E_INVALID, "NULL argument");
+  for (int i = 0; i < 3; ++i)
+    if (!supported(n[i]))
+      return fail(MP_E_INVALID, "grid size n[" + std::to_string(i) + "] = " + std::to_string(n[i]) +
+                                    " unsupported (4 6 8 12 16 24 32 48 64 96 128 192 256)");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(MP_E_INVALID, "h must be > 0");
+  const RefC r{ref[0], ref[1], ref[2], ref[3], ref[4], ref[5]};
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(ref[k])) return fail(MP_E_INVALID, "reference constants must be finite");
+  if (!(r.lam + 2 * r.mu > 0) || !(r.mu > 0) || !(r.kap > 0) || !(r.gam > 0) || !(r.alp + r.bet + r.gam > 0))
+    return fail(MP_E_INVALID, "reference medium is not positive definite");
+  const Geometry g = grid_geometry(n[0], n[1], n[2]);
+  const size_t spec = align256(size_t(18) * g.nspec * sizeof(cx<double>));
+  const size_t need = spec + size_t(g.n0 + g.n1 + g.n2) * sizeof(cx<double>);
+  if (need > kScratchBytes)
+    return fail(MP_E_INVALID, "grid needs " + std::to_string(need) + " bytes of scratch; the limit is " +
+                                  std::to_string(kScratchBytes) + " (48 MiB)");
+  unsigned char* ptr = nullptr;
+  const mp_status st = scratch_address(&ptr);
+  if (st != MP_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  cx<double>* S = reinterpret_cast<cx<double>*>(ptr);
+  cx<double>* tw = reinterpret_cast<cx<double>*>(ptr + spec);
+  const int ntw = g.n0 + g.n1 + g.n2;
+  hipLaunchKernelGGL(k_twiddles, dim3(unsigned((ntw + 255) / 256)), dim3(256), 0, s, tw, g.n0, g.n1, g.n2);
+  XArgs<double> xa{};
+  xa.nrows = g.nrows;
+  xa.tw = tw;
+  xa.S = S;
+  xa.nvox = g.nvox;
+  xa.fin = static_cast<const double*>(dev_in);
+  xa.fout = static_cast<double*>(dev_out);
+  AxisArgs<double> ay{};
+  ay.S = S;
+  ay.ostride = long(g.n1) * g.nh * 18;
+  ay.pstride = long(g.nh) * 18;
+  ay.tw = tw + g.n0;
+  AxisArgs<double> az{};
+  az.S = S;
+  az.ostride = long(g.nh) * 18;
+  az.pstride = long(g.n1) * g.nh * 18;
+  az.tw = tw + g.n0 + g.n1;
+  az.n0 = g.n0;
+  az.n1 = g.n1;
+  az.n2 = g.n2;
+  az.h = h;
+  az.scale = 1.0 / double(g.nvox);
+  az.ref = r;
+  az.gsym = nullptr;
+  // the kernels and tile widths of mp_green_apply on an FP64 plan
+  launch_x<double, X_FWD_ONLY>(g.n0, g.xblocks, s, xa, nullptr);
+  launch_axis<double, Y_FWD>(g.n1, g.txy, g.nh / g.txy, g.n2, s, ay, nullptr);
+  launch_axis<double, Z_GREEN>(g.n2, g.txz, g.nh / g.txz, g.n1, s, az, nullptr);
+  launch_axis<double, Y_INV>(g.n1, g.txy, g.nh / g.txy, g.n2, s, ay, nullptr);
+  launch_x<double, X_INV_ONLY>(g.n0, g.xblocks, s, xa, nullptr);
+  HIP_TRY(hipGetLastError());
   return MP_OK;
 }
 

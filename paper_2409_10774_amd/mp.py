@@ -82,6 +82,7 @@ def _load():
         "mp_set_eigenstress": (C.c_int, [vp, vp]),
         "mp_plan_steps": (C.c_int, [vp, C.POINTER(i32)]),
         "mp_green_apply": (C.c_int, [vp, vp, vp]),
+        "mp_green_apply_noalloc": (C.c_int, [C.POINTER(i32), C.c_double, dp, vp, vp, vp]),
         "mp_spectrum_forward": (C.c_int, [vp, vp, vp]),
         "mp_radial_return": (C.c_int, [vp, i64] + [vp] * 13),
         "mp_profile": (C.c_int, [vp, i32]),
@@ -505,6 +506,24 @@ def serve_sequential(reqs, workspace, stream=None, progress_s=0.0):
                                   C.c_void_p(s.cuda_stream), float(progress_s), a, d, st, it))
     n = reqs.n
     return np.array(a[:n]), np.array(d[:n]), np.array(st[:n]), np.array(it[:n])
+
+
+def green_apply_noalloc(n, h, ref, tau_mu, out=None, stream=None):
+    """mp_green_apply_noalloc: the spectral step of one iteration on 18 FP64
+    fields without a plan (the library's static scratch, nothing allocated
+    by the call).  n = (n0, n1, n2); ref = six Eq. 6 constants of the
+    reference medium; tau_mu, out: torch float64 (18, n2, n1, n0) on the
+    current device.  Returns `out` (allocated here when not given)."""
+    import torch
+    x = tau_mu
+    assert x.dtype == torch.float64 and x.is_contiguous() and x.numel() == 18 * int(np.prod(n))
+    if out is None:
+        out = torch.empty_like(x)
+    nn = (C.c_int32 * 3)(*[int(v) for v in n])
+    rr = (C.c_double * 6)(*[float(v) for v in ref])
+    s = stream if stream is not None else torch.cuda.current_stream(x.device)
+    check(lib.mp_green_apply_noalloc(nn, float(h), rr, _ptr(x), _ptr(out), C.c_void_p(s.cuda_stream)))
+    return out
 
 
 mp_version = lambda: lib.mp_version().decode()

@@ -258,6 +258,8 @@ def reference_medium(phase_map, phases, mode="phase_mean"):
     "volume_mean": <A(x)>, <B(x)> over the cell (Alg. 2).  For isotropic
     phases this is the volume average of each modulus.
     "phase_mean": unweighted mean of each modulus over the phases present.
+    "geometric_mean": unweighted geometric mean of each modulus over the
+    phases present (the augmented-Lagrangian scheme's penalty).
     "tensor_mean", "tensor_phase_mean": the same two means taken over every
     phase's own tensors; they return the pair (A0, B0) of tensors instead of
     constants (see reference_tensors).
@@ -273,6 +275,12 @@ def reference_medium(phase_map, phases, mode="phase_mean"):
     if mode == "phase_mean":
         present = np.unique(pm)
         return tuple(float(v) for v in tab[present].mean(axis=0))
+    if mode == "geometric_mean":
+        # the penalty of the augmented-Lagrangian scheme: the unweighted
+        # geometric mean of each modulus over the phases present (0 where a
+        # phase has a zero modulus)
+        present = np.unique(pm)
+        return tuple(float(np.prod(tab[present, k]) ** (1.0 / len(present))) for k in range(6))
     raise ValueError(mode)
 
 

@@ -22,15 +22,15 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 
-# algorithmic HBM bytes per voxel per launch, FP64 (8-byte words)
-#   x pass : read 18 half spectra (18 w), e/gamma old (18 w), history base
-#            (18 w), p_n, q_n (2 x 8 B), phase id (1 B); write e/gamma (18 w)
-#            and 18 half spectra (18 w)
+# algorithmic HBM bytes per voxel per launch (w = bytes per bulk word: 8 FP64,
+# 4 mixed; the strain state and p_n, q_n are FP64 in both)
+#   x pass : read 18 half spectra (18 w), e/gamma old (18 x 8 B), history
+#            base (18 w), p_n, q_n (2 x 8 B), phase id (1 B); write e/gamma
+#            (18 x 8 B) and 18 half spectra (18 w)
 #   y passes, fused z pass (z forward + Green operator + z inverse):
 #            read + write 18 half spectra (36 w)
 def bytes_per_voxel(w):
-    """w = bytes per bulk word (8 FP64, 4 mixed); p_n, q_n stay FP64."""
-    return {"x_pass": 90 * w + 16 + 1, "y_fwd": 36 * w, "z_green": 36 * w, "y_inv": 36 * w,
+    return {"x_pass": 54 * w + 36 * 8 + 16 + 1, "y_fwd": 36 * w, "z_green": 36 * w, "y_inv": 36 * w,
             "err_reduce": 0}
 
 

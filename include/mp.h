@@ -50,7 +50,8 @@ typedef enum {
   MP_E_DEVICE = 3,         /* a HIP call failed */
   MP_E_NOT_CONVERGED = 4,  /* max_iter reached in a step; that step is committed */
   MP_E_DIVERGED = 5,       /* non-finite error measure, or one grown 1e6 x above the
-                              step's smallest; step committed */
+                              step's smallest; that step is not committed and the
+                              plan (or batched RVE) takes no further steps */
   MP_E_STATE = 6           /* call not valid in the plan's current state */
 } mp_status;
 
@@ -69,7 +70,24 @@ enum { MP_ERR_LOCAL = 0, MP_ERR_AVERAGE = 1 };      /* Eq. 38 | Eq. 37 */
  * positive definite whenever <A> is, which valid phases ensure; <B> may be
  * singular on skew tensors, gamma = beta). */
 enum { MP_REF_PHASE_MEAN = 0, MP_REF_VOLUME_MEAN = 1, MP_REF_EXPLICIT = 2, MP_REF_TENSOR_MEAN = 3,
-       MP_REF_TENSOR_PHASE_MEAN = 4 };
+       MP_REF_TENSOR_PHASE_MEAN = 4, MP_REF_GEOMETRIC_MEAN = 5 };
+/* MP_REF_GEOMETRIC_MEAN: the unweighted geometric mean of each Eq. 6 modulus
+ * over the phases present (0 where a phase has a zero modulus), the penalty
+ * Michel, Moulinec and Suquet give for the augmented-Lagrangian scheme. */
+/* Fixed-point scheme of every load step.  BASIC: Alg. 2's loop.  AL: the
+ * augmented-Lagrangian scheme the paper's conclusion names for high phase
+ * contrast, in its alternating-direction form with the reference medium as
+ * the penalty C0.  Each iteration forms the compatible field e = E + G0
+ * (s(d) - C0 d) from the local strain d (the Green operator of Eqs. 33-35 on
+ * the polarization of Eq. 34 at d), over-relaxes it, e^ = w e + (1 - w) d,
+ * and solves the local step s(d') + C0 d' = s(d) + C0 e^ voxel by voxel, s
+ * the stress of Alg. 1 (the multiplier equals s(d) after every step and is
+ * not stored).  Its fixed point is Alg. 2's; the error measure (Eqs. 36-38)
+ * is taken on d and s(d), with the prescribed E, Gamma in the strain
+ * denominators.  AL needs MP_FP64, phases without Eq. 5 tensors, an
+ * isotropic reference medium with gamma0 > beta0 unless every phase present
+ * has gamma = beta, and 0 < relax < 2; it runs in plans (not in batches). */
+enum { MP_SCHEME_BASIC = 0, MP_SCHEME_AL = 1 };
 enum { MP_FIELD_E = 0, MP_FIELD_GAMMA = 1, MP_FIELD_T = 2, MP_FIELD_M = 3,
        MP_FIELD_P = 4, MP_FIELD_Q = 5 };
 
@@ -108,15 +126,21 @@ typedef struct {
   double tol;               /* epsilon of Alg. 2 (> 0) */
   int32_t max_iter;         /* loop cap per step (>= 1) */
   int32_t err_norm;         /* MP_ERR_LOCAL | MP_ERR_AVERAGE */
-  int32_t precision;        /* MP_FP64, or MP_MIXED: spectra, strain, history
-                               base and the FFT / Green / Alg. 1 arithmetic in
-                               FP32; p, q, the error measure (Eqs. 36-38) and
-                               every volume average in FP64; a step also ends
-                               when the error measure stops improving for 100
-                               iterations (its FP32 rounding floor), which
-                               mp_step_error_parts reports */
+  int32_t precision;        /* MP_FP64, or MP_MIXED: the spectra, the history
+                               base and the committed stresses are stored in
+                               FP32 and the transforms and the Green operator
+                               run in FP32; the strain state, the return map
+                               (Alg. 1), the polarization, p, q, the error
+                               measure (Eqs. 36-38) and every volume average
+                               stay FP64.  After a step's first iteration the
+                               transforms carry the polarization's increment
+                               (the Green operator is linear), so their
+                               rounding shrinks with it and every step ends at
+                               tol like FP64 */
   int32_t n_aniso;          /* phases with Eq. 5 tensors, 0..n_phases */
   const mp_aniso* aniso;    /* host, n_aniso records (unused when n_aniso = 0) */
+  int32_t scheme;           /* MP_SCHEME_BASIC (0) | MP_SCHEME_AL */
+  double relax;             /* MP_SCHEME_AL: over-relaxation w, 0 < w < 2 (1: none) */
 } mp_problem;
 
 typedef struct mp_plan_s* mp_plan;
@@ -143,8 +167,9 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
  * iters: optional [n_steps] output of loop iterations per step.
  * The first step of a fresh plan starts from the uniform E; later steps start
  * from the linear extrapolation of the last two committed states.  Returns
- * at the first step that does not converge (MP_E_NOT_CONVERGED,
- * MP_E_DIVERGED) after committing it.  Blocks until the work is done. */
+ * at the first step that does not converge: MP_E_NOT_CONVERGED after
+ * committing it, MP_E_DIVERGED without committing it (the plan then returns
+ * MP_E_STATE to later calls).  Blocks until the work is done. */
 mp_status mp_solve_load_path(mp_plan plan, int32_t n_steps, const double* times,
                              const double* E, const double* Gam, int32_t* iters);
 
@@ -154,15 +179,23 @@ mp_status mp_solve_load_path(mp_plan plan, int32_t n_steps, const double* times,
 mp_status mp_homogenized_response(mp_plan plan, int32_t step, double out[42]);
 
 /* The four terms of the error measure (Eq. 36) at the end of committed step
- * `step`: out[5] = err_e, err_t, err_gamma, err_m (Eq. 38 or Eq. 37), and
- * 1.0 when the step ended at the rounding floor of the MP_MIXED form (no
- * new smallest error for 100 iterations while above tol), else 0.0. */
+ * `step`: out[5] = err_e, err_t, err_gamma, err_m (Eq. 38 or Eq. 37), and a
+ * reserved 0.0. */
 mp_status mp_step_error_parts(mp_plan plan, int32_t step, double out[5]);
 
-/* Copy one field of the current state (after the last committed step) to
- * host memory as FP64: MP_FIELD_E/GAMMA/T/M write 9*n doubles (SoA),
- * MP_FIELD_P/Q write n doubles.  Blocks. */
-mp_status mp_get_fields(mp_plan plan, int32_t field, double* host_dst);
+/* Copy fields of the state after the last committed step as FP64 values (the
+ * outputs of Alg. 2): bit f of `mask` (1 << MP_FIELD_*) selects field f,
+ * written to dst[f] (dst holds 6 pointers indexed by field id; unselected
+ * entries are not read).  MP_FIELD_E/GAMMA/T/M receive 9*n doubles (SoA,
+ * component 3k + l), MP_FIELD_P/Q n doubles.  dst_is_device = 0: host
+ * destinations, the call returns when they are written; 1: device
+ * destinations, the copies (FP32 stresses of MP_MIXED widened on the device)
+ * are enqueued on the plan's stream and the call returns without waiting.
+ * e and gamma are the last iterate, the committed one unless a step diverged
+ * (MP_E_DIVERGED leaves its iterate there and the stresses of the last
+ * committed step).  MP_E_INVALID for mask bits beyond MP_FIELD_Q or a NULL
+ * selected destination. */
+mp_status mp_get_fields(mp_plan plan, uint32_t mask, void* const* dst, int32_t dst_is_device);
 
 /* Test hook: when n_fixed > 0 every later step runs exactly n_fixed loop
  * iterations regardless of the tolerance (0 restores the tolerance test).
@@ -318,11 +351,13 @@ mp_status mp_batch_query(mp_batch batch, int32_t id, int32_t* state, int32_t* st
                          int32_t* steps_done, int64_t* iters_total);
 
 /* Record of committed step `step` (1-based) of RVE `id`: out[0..41] as
- * mp_homogenized_response, out[42..46] as mp_step_error_parts. */
+ * mp_homogenized_response, out[42..46] as mp_step_error_parts, out[47] 0. */
 mp_status mp_batch_response(mp_batch batch, int32_t id, int32_t step, double out[48]);
 
-/* One field of RVE `id` (after its last committed step), as mp_get_fields. */
-mp_status mp_batch_get_field(mp_batch batch, int32_t id, int32_t field, double* host_dst);
+/* Fields of RVE `id` (after its last committed step), as mp_get_fields (device
+ * copies go to the batch's stream). */
+mp_status mp_batch_get_fields(mp_batch batch, int32_t id, uint32_t mask, void* const* dst,
+                              int32_t dst_is_device);
 
 /* Test hook, as mp_set_fixed_iterations for RVE `id`: with n_fixed > 0
  * every step of it runs exactly n_fixed loop iterations (0 restores the
@@ -355,15 +390,24 @@ typedef struct {
   const double* times;       /* n_steps + 1 */
   const double* E;           /* [n_steps][9] */
   const double* Gam;         /* [n_steps][9] */
+  /* the reply, written before the request counts as done (caller-owned): */
+  double* records;           /* [n_steps][48] host doubles, the step records as
+                                mp_batch_response gives them; rows of steps not
+                                committed (the request failed) are NaN; NULL: none */
+  uint32_t field_mask;       /* fields of the final state (1 << MP_FIELD_*), 0: none */
+  void* fields[6];           /* their destinations by field id, as mp_get_fields */
+  int32_t fields_on_device;  /* 1: fields[] are device pointers (the copies are
+                                complete when the request is done) */
 } mp_request;
 
 /* Continuous batching on an empty batch: arrived requests are admitted in
  * arrival order while their footprint fits in the free arena (a later
  * request may pass a head that does not fit, until the head has been passed
  * max_bypass times); resident RVEs keep their state across launches;
- * finished ones are retired after every graph launch, which frees their
- * region for the queue.  Requests are solved in the batch's precision.
- * Per request: t_admit, t_done (seconds), status, loop iterations.  With
+ * finished ones are retired after every graph launch: their replies (step
+ * records, fields) are read back, then their region is freed for the queue.
+ * Requests are solved in the batch's precision.  Per request: t_admit,
+ * t_done (seconds, after the reply is written), status, loop iterations.  With
  * progress_s > 0 a progress line goes to stderr every progress_s seconds. */
 mp_status mp_serve_batched(mp_batch batch, int32_t n, const mp_request* req, int32_t max_bypass,
                            double progress_s, double* t_admit, double* t_done, int32_t* status,
@@ -371,7 +415,8 @@ mp_status mp_serve_batched(mp_batch batch, int32_t n, const mp_request* req, int
 
 /* The same requests served one at a time in arrival order with FP64 plans
  * (mp_plan_create / mp_solve_load_path / mp_plan_destroy) on a workspace of
- * `bytes`.  Per request: t_start, t_done (seconds), status, iterations.
+ * `bytes`, each reply written as above.  Per request: t_start, t_done
+ * (seconds, after the reply), status, iterations.
  * With progress_s > 0 a line goes to stderr after every request (and
  * while waiting, at least every progress_s seconds the call returns to its
  * clock). */

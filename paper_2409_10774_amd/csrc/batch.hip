@@ -532,8 +532,8 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   x.tw = reinterpret_cast<const cx<T>*>(b + L.tw);
   x.S = reinterpret_cast<cx<T>*>(b + L.S);
   x.nvox = g.nvox;
-  x.E = reinterpret_cast<T*>(b + L.E);
-  x.Eprev = reinterpret_cast<T*>(b + L.Eprev);
+  x.E = reinterpret_cast<double*>(b + L.E);
+  x.Eprev = reinterpret_cast<double*>(b + L.Eprev);
   x.base = reinterpret_cast<T*>(b + L.base);
   x.pq = reinterpret_cast<double*>(b + L.pq);
   x.out_tm = reinterpret_cast<T*>(b + L.out_tm);
@@ -585,7 +585,6 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   R.fixed = 0;
   R.max_iter = prob->max_iter;
   R.norm = prob->err_norm;
-  R.window = sizeof(T) < sizeof(double) ? kFloorWindow : 0;
 
   auto undo = [&](mp_status s) {
     B->arena.release(H.off, H.bytes);
@@ -661,6 +660,23 @@ mp_status read_desc(mp_batch B, const RveHost& H, int* state, int* status, int* 
 mp_status query(mp_batch B, const RveHost& H, int* state, int* status, int* committed, long* iters) {
   return B->w == sizeof(float) ? read_desc<float>(B, H, state, status, committed, iters)
                                : read_desc<double>(B, H, state, status, committed, iters);
+}
+
+// The records of RVE H's committed steps as mp_batch_response gives them
+// (averages, error measure, iterations), rows past the committed ones NaN.
+mp_status read_records(mp_batch B, const RveHost& H, int committed, double* out) {
+  const size_t bytes = size_t(H.n_steps) * kRec * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(out, B->ws + H.off + H.rec_off, bytes, hipMemcpyDeviceToHost, B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  for (int s = 0; s < H.n_steps; ++s) {
+    double* r = out + size_t(s) * kRec;
+    if (s >= committed) {
+      for (int j = 0; j < kRec; ++j) r[j] = std::nan("");
+      continue;
+    }
+    for (int j = 0; j < kNAvg; ++j) r[j] /= double(H.nvox);
+  }
+  return MP_OK;
 }
 
 int status_code(int s) {
@@ -785,6 +801,8 @@ mp_status mp_batch_admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   if (!B || !id) return fail(MP_E_INVALID, "NULL argument");
   if (!prob || prob->precision != B->cfg.precision)
     return fail(MP_E_INVALID, "problem precision differs from the batch's");
+  if (prob->scheme != MP_SCHEME_BASIC)
+    return fail(MP_E_INVALID, "batches run the basic scheme (MP_SCHEME_AL runs in plans)");
   if (n_steps < 1 || !times || !E || !Gam) return fail(MP_E_INVALID, "bad load path");
   for (int s = 1; s <= n_steps; ++s)
     if (!(times[s] > times[s - 1])) return fail(MP_E_INVALID, "times must increase");
@@ -851,37 +869,13 @@ mp_status mp_batch_response(mp_batch B, int32_t id, int32_t step, double out[48]
   return MP_OK;
 }
 
-mp_status mp_batch_get_field(mp_batch B, int32_t id, int32_t field, double* dst) {
+mp_status mp_batch_get_fields(mp_batch B, int32_t id, uint32_t mask, void* const* dst, int32_t dst_is_device) {
   RveHost* H;
   mp_status st = find(B, id, &H);
   if (st != MP_OK) return st;
-  if (!dst) return fail(MP_E_INVALID, "NULL argument");
-  const long n = H->nvox;
   const unsigned char* b = B->ws + H->off;
-  const Layout& L = H->L;
-  const size_t w = B->w;
-  const unsigned char* src = nullptr;
-  long count = 9 * n;
-  bool bulk = true;
-  switch (field) {
-    case MP_FIELD_E: src = b + L.E; break;
-    case MP_FIELD_GAMMA: src = b + L.E + 9 * n * w; break;
-    case MP_FIELD_T: src = b + L.out_tm; break;
-    case MP_FIELD_M: src = b + L.out_tm + 9 * n * w; break;
-    case MP_FIELD_P: src = b + L.out_pq; count = n; bulk = false; break;
-    case MP_FIELD_Q: src = b + L.out_pq + n * sizeof(double); count = n; bulk = false; break;
-    default: return fail(MP_E_INVALID, "unknown field");
-  }
-  if (bulk && w == sizeof(float)) {
-    std::vector<float> tmp(count);
-    HIP_TRY(hipMemcpyAsync(tmp.data(), src, count * sizeof(float), hipMemcpyDeviceToHost, B->stream));
-    HIP_TRY(hipStreamSynchronize(B->stream));
-    for (long i = 0; i < count; ++i) dst[i] = double(tmp[i]);
-    return MP_OK;
-  }
-  HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToHost, B->stream));
-  HIP_TRY(hipStreamSynchronize(B->stream));
-  return MP_OK;
+  return copy_fields(b + H->L.E, b + H->L.out_tm, b + H->L.out_pq, H->nvox, B->w, mask, dst, dst_is_device,
+                     B->stream);
 }
 
 mp_status mp_batch_set_fixed_iterations(mp_batch B, int32_t id, int32_t n_fixed) {
@@ -1033,6 +1027,14 @@ mp_status mp_serve_batched(mp_batch B, int32_t n, const mp_request* req, int32_t
       long itn;
       if ((st = query(B, H, &s, &sc, &c, &itn)) != MP_OK) return st;
       const int i = it->second;
+      // the reply: the step records and the requested fields of the final
+      // state, read back before the RVE's region is released
+      if (req[i].records && (st = read_records(B, H, c, req[i].records)) != MP_OK) return st;
+      if (req[i].field_mask &&
+          (st = mp_batch_get_fields(B, it->first, req[i].field_mask, req[i].fields, req[i].fields_on_device)) !=
+              MP_OK)
+        return st;
+      if (req[i].field_mask && req[i].fields_on_device) HIP_TRY(hipStreamSynchronize(B->stream));
       t_done[i] = now_s() - t0;
       status[i] = status_code(sc);
       iters[i] = itn;
@@ -1078,6 +1080,28 @@ mp_status mp_serve_sequential(int32_t n, const mp_request* req, void* dev_worksp
         std::fprintf(stderr, "# sequential t=%.1f s: request %d of %d, step %d of %d\n", last_note - t0,
                      i + 1, n, k + 1, req[i].n_steps);
         std::fflush(stderr);
+      }
+    }
+    // the reply: step records and requested fields, before the plan goes
+    if (P && st != MP_E_DEVICE) {
+      int32_t done_steps = 0;
+      mp_plan_steps(P, &done_steps);
+      if (req[i].records) {
+        for (int k = 0; k < req[i].n_steps; ++k) {
+          double* r = req[i].records + size_t(k) * kRec;
+          if (k >= done_steps) {
+            for (int j = 0; j < kRec; ++j) r[j] = std::nan("");
+            continue;
+          }
+          mp_homogenized_response(P, k + 1, r);
+          mp_step_error_parts(P, k + 1, r + 42);
+          r[47] = 0.0;
+        }
+      }
+      if (req[i].field_mask) {
+        const mp_status fs = mp_get_fields(P, req[i].field_mask, req[i].fields, req[i].fields_on_device);
+        if (fs == MP_OK && req[i].fields_on_device) (void)hipStreamSynchronize(reinterpret_cast<hipStream_t>(hip_stream));
+        if (fs != MP_OK && st == MP_OK) st = fs;
       }
     }
     if (P) mp_plan_destroy(P);

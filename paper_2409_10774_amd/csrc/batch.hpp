@@ -16,7 +16,8 @@
 //   TRANS  the next x pass commits the converged step (if commit) and opens
 //          the next one (if init); spectral passes skip the RVE
 //   RUN    a loop iteration of the current step
-//   DONE   last step committed (or failed); results are readable
+//   DONE   last step committed, or a step failed (max_iter: committed;
+//          diverged: not committed); results are readable
 // An admitted RVE starts in TRANS with init only.
 #pragma once
 
@@ -39,14 +40,14 @@ struct Rve {
   const double* times;   // n_steps + 1: times[0] start state, step s ends at times[s + 1]
   const double* Ep;      // [n_steps][9] prescribed E
   const double* Gp;      // [n_steps][9] prescribed Gamma
-  double* rec;           // [n_steps][kRec]: 40 average sums, err, iters, 4 err parts, floor flag
+  double* rec;           // [n_steps][kRec]: 40 average sums, err, iters, 4 err parts, reserved
   double tot[kNAvg];     // reduced rows of the last x pass
-  double pend[8];        // err, iters, err parts, floor flag of the step awaiting commit
+  double pend[8];        // err, iters, err parts, reserved of the step awaiting commit
   double tol;
   long nvox;
   int xblocks;
   int state, cls, step, n_steps, committed, status;
-  int fixed, max_iter, norm, window;
+  int fixed, max_iter, norm;
   long iters_total;
 };
 
@@ -95,7 +96,8 @@ __global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE>()
     const int slot = list[u / tiles];
     const int tile = int(u % tiles);
     __syncthreads();   // the previous item is done with LDS
-    xpass_tile<T, MODE, N0, AN>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid());
+    xpass_tile<T, MODE, N0, AN>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid(),
+                                rv[slot].ctl.rd_incr, rv[slot].ctl.wr_incr);
   }
 }
 
@@ -177,13 +179,17 @@ __global__ void __launch_bounds__(kMaxSlots) k_batch_ctl(Rve<T>* rv, Lists* ls, 
     err_finalize(R.tot, R.nvox, &R.ctl, R.x.mac);
     R.iters_total += 1;
     const int d = R.ctl.done;
-    if (d) {
+    if (d == 3) {
+      // diverged: the step is not committed and the RVE takes no further steps
+      R.status = RVS_DIVERGED;
+      state = RV_DONE;
+    } else if (d) {
       R.pend[0] = R.ctl.err;
       R.pend[1] = R.ctl.iters;
       for (int f = 0; f < 4; ++f) R.pend[2 + f] = R.ctl.err_parts[f];
-      R.pend[6] = d == 4 ? 1.0 : 0.0;
-      const bool failed = d == 2 || d == 3;
-      if (failed) R.status = d == 2 ? RVS_NOT_CONVERGED : RVS_DIVERGED;
+      R.pend[6] = 0.0;
+      const bool failed = d == 2;
+      if (failed) R.status = RVS_NOT_CONVERGED;
       const int next = R.step + 1;
       const bool last = failed || next >= R.n_steps;
       R.x.commit = 1;
@@ -208,7 +214,7 @@ __global__ void __launch_bounds__(kMaxSlots) k_batch_ctl(Rve<T>* rv, Lists* ls, 
       R.committed += 1;
     }
     if (R.x.init) {
-      ctl_reset(&R.ctl, R.fixed, R.max_iter, R.tol, R.norm, R.window);
+      ctl_reset(&R.ctl, R.fixed, R.max_iter, R.tol, R.norm);
       state = RV_RUN;
     } else {
       state = RV_DONE;

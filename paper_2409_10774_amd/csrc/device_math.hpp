@@ -495,6 +495,166 @@ __device__ __forceinline__ double micro_equivalent(const MicroC& c, const T* m) 
   return sqrt(c.b1 * m_sym + c.b2 * m_skw);
 }
 
+// Eq. 6 constants of an isotropic reference medium (the Green operator's
+// A0, B0; the augmented-Lagrangian scheme's penalty)
+struct RefC {
+  double lam, mu, kap, alp, bet, gam;
+};
+
+// ---------------------------------------------------------------------------
+// Local step of the augmented-Lagrangian scheme (the high-contrast scheme of
+// Michel, Moulinec and Suquet that the paper's conclusion names), at one voxel
+// and level: the strain d with  s(d) + C0 d = r,  s(d) the stress Alg. 1
+// returns for d from the history base b, C0 the penalty (the reference
+// medium).  Alg. 1 scales the deviator of the trial stress (macro level) or
+// the whole trial couple stress (micro level) by one factor f, and with the
+// isotropic laws of Eq. 6 the equation splits into the volumetric part
+// tr(V) I / 3, the symmetric deviator and the skew part of each tensor, on
+// which the law and the penalty act as scalars a_j, a0_j.  For a given f
+//   d_j = (r_j - f b_j) / (f a_j + a0_j),  trial part T_j = u_j / (f a_j + a0_j),
+//   u_j = a0_j b_j + a_j r_j,
+// and f is the root in (0, 1] of the consistency condition of Alg. 1,
+//   F(f) = (f - c1) X(f) - c0,  X = equivalent trial stress (Eq. 14 / 17),
+//   c1 = H / (H + c),  c0 = R_n c / (H + c),
+// which is increasing in f: safeguarded Newton steps inside a bracket.
+// ---------------------------------------------------------------------------
+// parts of a 3 x 3 tensor: volumetric scalar v (V = v I + D + K), symmetric
+// deviator D, skew part K
+__device__ __forceinline__ void tensor_parts(const double* V, double& v, double* D, double* K) {
+  v = (V[0] + V[4] + V[8]) / 3.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      D[3 * k + l] = 0.5 * (V[3 * k + l] + V[3 * l + k]) - (k == l ? v : 0.0);
+      K[3 * k + l] = 0.5 * (V[3 * k + l] - V[3 * l + k]);
+    }
+}
+
+__device__ __forceinline__ double norm2_9(const double* V) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s += V[i] * V[i];
+  return s;
+}
+
+// root in (0, 1] of F(f) = (f - c1) sqrt(w0 Q0 / (f p0 + q0)^2 + w1 Q1 /
+// (f p1 + q1)^2 + w2 Q2 / (f p2 + q2)^2 + W) - c0 (F increasing, F(1) >= 0):
+// Newton steps kept inside the bracket, bisection where a step leaves it
+__device__ __forceinline__ double al_factor(const double (&w)[3], const double (&Q)[3], const double (&p)[3],
+                                            const double (&q)[3], double W, double c0, double c1) {
+  double lo = 0.0, hi = 1.0, f = 1.0;
+  for (int it = 0; it < 100; ++it) {
+    double X2 = W, dX2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double den = f * p[j] + q[j];
+      const double t = w[j] * Q[j] / (den * den);
+      X2 += t;
+      dX2 -= 2.0 * t * p[j] / den;
+    }
+    const double X = sqrt(X2);
+    const double F = (f - c1) * X - c0;
+    if (F > 0.0) hi = f; else lo = f;
+    if (F == 0.0) break;
+    const double dF = X + (f - c1) * 0.5 * dX2 / X;
+    double nf = f - F / dF;
+    if (!(nf > lo && nf < hi)) nf = 0.5 * (lo + hi);
+    if (fabs(nf - f) <= 1e-16 * f || hi - lo <= 1e-16 * hi) {
+      f = nf;
+      break;
+    }
+    f = nf;
+  }
+  return f;
+}
+
+// macro level: strain d of  t(d) + A0 d = r  (history base bt, p_n)
+__device__ __forceinline__ void al_macro_local(const MacroC& c, const RefC& r0, const double* r,
+                                               const double* bt, double pn, double* d) {
+  const double a[3] = {3.0 * c.lam + 2.0 * c.mu, 2.0 * c.mu, 2.0 * c.kap};
+  const double a0[3] = {3.0 * r0.lam + 2.0 * r0.mu, 2.0 * r0.mu, 2.0 * r0.kap};
+  double rv, rD[9], rK[9], bv, bD[9], bK[9];
+  tensor_parts(r, rv, rD, rK);
+  tensor_parts(bt, bv, bD, bK);
+  // the volumetric part is never scaled
+  const double dv = (rv - bv) / (a[0] + a0[0]);
+  double uD[9], uK[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    uD[i] = a0[1] * bD[i] + a[1] * rD[i];
+    uK[i] = a0[2] * bK[i] + a[2] * rK[i];
+  }
+  const double QD = norm2_9(uD), QK = norm2_9(uK);
+  // elastic trial (f = 1): Eq. 14 on the deviator
+  const double sD = a[1] + a0[1], sK = a[2] + a0[2];
+  const double X1 = sqrt(c.a1 * QD / (sD * sD) + c.a2 * QK / (sK * sK));
+  const double Rn = c.tY + c.tH * pn;
+  double f = 1.0;
+  if (!(X1 < Rn)) {
+    const double den = c.tH + 2.0 * c.a1 * c.mu;
+    const double w[3] = {c.a1, c.a2, 0.0}, Q[3] = {QD, QK, 0.0};
+    const double p[3] = {a[1], a[2], 0.0}, q[3] = {a0[1], a0[2], 1.0};
+    f = al_factor(w, Q, p, q, 0.0, Rn * 2.0 * c.a1 * c.mu / den, c.tH / den);
+  }
+  const double eD = f * a[1] + a0[1], eK = f * a[2] + a0[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const int i = 3 * k + l;
+      d[i] = (rD[i] - f * bD[i]) / eD + (rK[i] - f * bK[i]) / eK + (k == l ? dv : 0.0);
+    }
+}
+
+// micro level: curvature d of  m(d) + B0 d = r  (history base bm, q_n); a part
+// without stiffness in the phase and the penalty (the skew curvature when
+// gamma = beta and gamma0 = beta0) takes the compatible field's part, comp
+__device__ __forceinline__ void al_micro_local(const MicroC& c, const RefC& r0, const double* r,
+                                               const double* bm, const double* comp, double qn, double* d) {
+  const double a[3] = {3.0 * c.alp + c.bet + c.gam, c.bet + c.gam, c.bet - c.gam};
+  const double a0[3] = {3.0 * r0.alp + r0.bet + r0.gam, r0.bet + r0.gam, r0.bet - r0.gam};
+  const bool inert = a[2] == 0.0 && a0[2] == 0.0;
+  double rv, rD[9], rK[9], bv, bD[9], bK[9];
+  tensor_parts(r, rv, rD, rK);
+  tensor_parts(bm, bv, bD, bK);
+  double uD[9], uK[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    uD[i] = a0[1] * bD[i] + a[1] * rD[i];
+    uK[i] = a0[2] * bK[i] + a[2] * rK[i];
+  }
+  const double uv = a0[0] * bv + a[0] * rv;
+  // Eq. 17 on the whole couple stress: b1 (|vol|^2 + |D|^2) + b2 |K|^2, the
+  // volumetric part contributing 3 v^2
+  const double Qv = 3.0 * uv * uv, QD = norm2_9(uD), QK = norm2_9(uK);
+  const double W = inert ? c.b2 * norm2_9(bK) : 0.0;   // inert part: constant trial stress b
+  const double s0 = a[0] + a0[0], s1 = a[1] + a0[1], s2 = a[2] + a0[2];
+  const double Y1 = sqrt(c.b1 * Qv / (s0 * s0) + c.b1 * QD / (s1 * s1) + (inert ? W : c.b2 * QK / (s2 * s2)));
+  const double Rn = c.mY + c.mH * qn;
+  double g = 1.0;
+  if (!(Y1 < Rn)) {
+    const double bgb = c.b1 * (c.gam + c.bet);
+    const double den = c.mH + bgb;
+    const double w[3] = {c.b1, c.b1, inert ? 0.0 : c.b2};
+    const double Q[3] = {Qv, QD, inert ? 0.0 : QK};
+    const double p[3] = {a[0], a[1], inert ? 0.0 : a[2]}, q[3] = {a0[0], a0[1], inert ? 1.0 : a0[2]};
+    g = al_factor(w, Q, p, q, W, Rn * bgb / den, c.mH / den);
+  }
+  const double ev = g * a[0] + a0[0], eD = g * a[1] + a0[1], eK = g * a[2] + a0[2];
+  double cv = 0.0, cD[9], cK[9];
+  if (inert) tensor_parts(comp, cv, cD, cK);
+  const double dv = (rv - g * bv) / ev;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const int i = 3 * k + l;
+      const double dk = inert ? cK[i] : (rK[i] - g * bK[i]) / eK;
+      d[i] = (rD[i] - g * bD[i]) / eD + dk + (k == l ? dv : 0.0);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Green operator at one frequency.
 //   Sources of the reference-medium balance equations (Eq. 2 with the
@@ -553,9 +713,6 @@ __device__ __forceinline__ void green_strains(const T (&xi)[3], const cx<T> (&u)
 //        [-2 i k0 W, (g0 s^2 + 4 k0) I + (a0 + b0) xi xi^T]],  W v = xi x v,
 // which splits into a longitudinal part along n = xi/s and a 2x2 transverse
 // block, solved in closed form.
-struct RefC {
-  double lam, mu, kap, alp, bet, gam;
-};
 
 template <class T>
 __device__ __forceinline__ void green_apply(const RefC& r, T x1, T x2, T x3, T scale,

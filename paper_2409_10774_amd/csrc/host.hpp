@@ -55,21 +55,26 @@ constexpr int tx_wide(int L) {
 
 inline int x_rows(int n0) { return n0 >= 128 ? 1 : 128 / n0; }
 
-// an: the problem has phases with Eq. 5 tensors (ITER and TRANS passes)
+// an: the problem has phases with Eq. 5 tensors (ITER and TRANS passes);
+// al: augmented-Lagrangian iterations (FP64 ITER passes)
 template <class T, int MODE>
-void launch_x(int n0, int blocks, hipStream_t s, const XArgs<T>& a, const Ctl* ctl, bool an = false) {
+void launch_x(int n0, int blocks, hipStream_t s, const XArgs<T>& a, const Ctl* ctl, bool an = false,
+              bool al = false) {
   constexpr bool LAW = MODE == X_ITER || MODE == X_TRANS;
+  constexpr bool ALX = MODE == X_ITER && sizeof(T) == sizeof(double);
   // blocks = row tiles; x_grid gives the blocks that run their levels
   switch (n0) {
-#define MP_CASE(N)                                                                              \
-  case N: {                                                                                     \
-    using X = XShape<T, N>;                                                                     \
-    const dim3 grid(unsigned(x_grid<X::LPB>(blocks)));                                          \
-    if (LAW && an)                                                                              \
-      hipLaunchKernelGGL((k_xpass<T, MODE, N, LAW>), grid, dim3(X::NTHR), 0, s, a, ctl, blocks); \
-    else                                                                                        \
-      hipLaunchKernelGGL((k_xpass<T, MODE, N>), grid, dim3(X::NTHR), 0, s, a, ctl, blocks);      \
-    break;                                                                                      \
+#define MP_CASE(N)                                                                                    \
+  case N: {                                                                                           \
+    using X = XShape<T, N>;                                                                           \
+    const dim3 grid(unsigned(x_grid<X::LPB>(blocks)));                                                \
+    if (LAW && an)                                                                                    \
+      hipLaunchKernelGGL((k_xpass<T, MODE, N, LAW>), grid, dim3(X::NTHR), 0, s, a, ctl, blocks);       \
+    else if (ALX && al)                                                                               \
+      hipLaunchKernelGGL((k_xpass<T, MODE, N, false, ALX>), grid, dim3(X::NTHR), 0, s, a, ctl, blocks); \
+    else                                                                                              \
+      hipLaunchKernelGGL((k_xpass<T, MODE, N>), grid, dim3(X::NTHR), 0, s, a, ctl, blocks);            \
+    break;                                                                                            \
   }
     MP_SIZES(MP_CASE)
 #undef MP_CASE
@@ -121,10 +126,6 @@ hipError_t allow_lds(int L) {
   }
   return e;
 }
-
-// the low-precision form may stop at its rounding floor: no new best error
-// for this many iterations (flagged in the step record)
-constexpr int kFloorWindow = 100;
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -249,6 +250,8 @@ inline Geometry grid_geometry(int n0, int n1, int n2) {
   return G;
 }
 
+inline mp_status reference_medium(const mp_problem* prob, long nvox, RefC* out);
+
 inline mp_status validate(const mp_problem* p, Geometry* g) {
   if (!p) return fail(MP_E_INVALID, "problem is NULL");
   for (int i = 0; i < 3; ++i)
@@ -263,7 +266,8 @@ inline mp_status validate(const mp_problem* p, Geometry* g) {
   if (p->err_norm != MP_ERR_LOCAL && p->err_norm != MP_ERR_AVERAGE)
     return fail(MP_E_INVALID, "err_norm");
   if (p->precision != MP_FP64 && p->precision != MP_MIXED) return fail(MP_E_INVALID, "precision");
-  if (p->ref_mode < 0 || p->ref_mode > 4) return fail(MP_E_INVALID, "ref_mode");
+  if (p->ref_mode < 0 || p->ref_mode > 5) return fail(MP_E_INVALID, "ref_mode");
+  if (p->scheme != MP_SCHEME_BASIC && p->scheme != MP_SCHEME_AL) return fail(MP_E_INVALID, "scheme");
   for (int i = 0; i < p->n_phases; ++i) {
     const mp_phase& c = p->phases[i];
     const std::string tag = "phase " + std::to_string(i) + ": ";
@@ -313,6 +317,25 @@ inline mp_status validate(const mp_problem* p, Geometry* g) {
     const mp_status rs = reference_tensors(p, nvox, &r);
     if (rs != MP_OK) return rs;
   }
+  if (p->scheme == MP_SCHEME_AL) {
+    if (p->precision != MP_FP64) return fail(MP_E_INVALID, "the augmented-Lagrangian scheme runs in FP64");
+    if (p->n_aniso > 0 || G.ref_tensor)
+      return fail(MP_E_INVALID, "the augmented-Lagrangian scheme takes Eq. 6 phases and an isotropic reference");
+    if (!(p->relax > 0.0 && p->relax < 2.0)) return fail(MP_E_INVALID, "relax must lie in (0, 2)");
+    RefC r;
+    const mp_status rs = reference_medium(p, nvox, &r);
+    if (rs != MP_OK) return rs;
+    // the penalty must be positive definite on every part that carries
+    // stress; the skew curvature carries none only where gamma = beta
+    bool all_eq = true;
+    std::vector<char> present(size_t(p->n_phases), 0);
+    for (long i = 0; i < nvox; ++i) present[p->phase[i]] = 1;
+    for (int i = 0; i < p->n_phases; ++i)
+      if (present[i] && p->phases[i].gamma != p->phases[i].beta) all_eq = false;
+    if (!(r.gam - r.bet > 0.0) && !all_eq)
+      return fail(MP_E_INVALID, "the augmented-Lagrangian penalty needs gamma0 > beta0 unless every phase has "
+                                "gamma = beta");
+  }
   *g = G;
   return MP_OK;
 }
@@ -322,8 +345,8 @@ inline Layout layout(const Geometry& g, size_t w /* bytes per bulk word */) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
   L.S = take(18 * g.nspec * 2 * w);
-  L.E = take(18 * g.nvox * w);
-  L.Eprev = take(18 * g.nvox * w);
+  L.E = take(18 * g.nvox * sizeof(double));       // the strain state is FP64 in both precisions
+  L.Eprev = take(18 * g.nvox * sizeof(double));
   L.base = take(18 * g.nvox * w);
   L.pq = take(2 * g.nvox * sizeof(double));
   L.out_tm = take(18 * g.nvox * w);
@@ -337,6 +360,74 @@ inline Layout layout(const Geometry& g, size_t w /* bytes per bulk word */) {
   L.tot = take(64 * sizeof(double));
   L.total = o;
   return L;
+}
+
+// ---------------------------------------------------------------------------
+// Field read-back (mp_get_fields, mp_batch_get_fields, served requests)
+// ---------------------------------------------------------------------------
+// Where field f of a state lives: e, gamma in the FP64 strain buffer, t, m in
+// the committed stresses (bulk type, w bytes), p, q in the FP64 p, q buffer.
+struct FieldSrc {
+  const unsigned char* p;
+  long count;   // values
+  bool f32;     // stored as float
+};
+
+inline FieldSrc field_source(const unsigned char* E, const unsigned char* out_tm, const unsigned char* out_pq,
+                             long n, size_t w, int field) {
+  switch (field) {
+    case MP_FIELD_E: return {E, 9 * n, false};
+    case MP_FIELD_GAMMA: return {E + 9 * n * sizeof(double), 9 * n, false};
+    case MP_FIELD_T: return {out_tm, 9 * n, w == sizeof(float)};
+    case MP_FIELD_M: return {out_tm + 9 * n * w, 9 * n, w == sizeof(float)};
+    case MP_FIELD_P: return {out_pq, n, false};
+    default: return {out_pq + n * sizeof(double), n, false};
+  }
+}
+
+constexpr uint32_t kFieldMask = (1u << 6) - 1;
+
+inline mp_status check_field_args(uint32_t mask, void* const* dst) {
+  if (mask & ~kFieldMask) return fail(MP_E_INVALID, "field mask has bits beyond MP_FIELD_Q");
+  if (!mask) return MP_OK;
+  if (!dst) return fail(MP_E_INVALID, "dst is NULL");
+  for (int f = 0; f < 6; ++f)
+    if ((mask >> f) & 1u && !dst[f]) return fail(MP_E_INVALID, "dst[" + std::to_string(f) + "] is NULL");
+  return MP_OK;
+}
+
+// Copy the fields of `mask` into dst[field] as FP64 values.  Device
+// destinations: enqueued on s (a float source is widened by k_widen), no
+// wait; host destinations: the call waits for the copies.
+inline mp_status copy_fields(const unsigned char* E, const unsigned char* out_tm, const unsigned char* out_pq,
+                             long n, size_t w, uint32_t mask, void* const* dst, int dst_is_device,
+                             hipStream_t s) {
+  mp_status st = check_field_args(mask, dst);
+  if (st != MP_OK || !mask) return st;
+  std::vector<float> tmp;
+  for (int f = 0; f < 6; ++f) {
+    if (!((mask >> f) & 1u)) continue;
+    const FieldSrc src = field_source(E, out_tm, out_pq, n, w, f);
+    double* out = static_cast<double*>(dst[f]);
+    if (dst_is_device) {
+      if (src.f32) {
+        hipLaunchKernelGGL(k_widen<float>, dim3(unsigned((src.count + 255) / 256)), dim3(256), 0, s,
+                           reinterpret_cast<const float*>(src.p), out, src.count);
+        HIP_TRY(hipGetLastError());
+      } else {
+        HIP_TRY(hipMemcpyAsync(out, src.p, src.count * sizeof(double), hipMemcpyDeviceToDevice, s));
+      }
+    } else if (src.f32) {
+      tmp.resize(src.count);
+      HIP_TRY(hipMemcpyAsync(tmp.data(), src.p, src.count * sizeof(float), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (long i = 0; i < src.count; ++i) out[i] = double(tmp[i]);
+    } else {
+      HIP_TRY(hipMemcpyAsync(out, src.p, src.count * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+  }
+  if (!dst_is_device) HIP_TRY(hipStreamSynchronize(s));
+  return MP_OK;
 }
 
 inline PhaseC derive(const mp_phase& c) {
@@ -377,6 +468,19 @@ inline mp_status reference_medium(const mp_problem* prob, long nvox, RefC* out) 
     const mp_phase& r = prob->ref;
     const double v[6] = {r.lambda, r.mu, r.kappa, r.alpha, r.beta, r.gamma};
     std::memcpy(refv, v, sizeof v);
+  } else if (prob->ref_mode == MP_REF_GEOMETRIC_MEAN) {
+    std::vector<long> count(prob->n_phases, 0);
+    for (long i = 0; i < nvox; ++i) count[prob->phase[i]]++;
+    double prod[6] = {1, 1, 1, 1, 1, 1};
+    int present = 0;
+    for (int i = 0; i < prob->n_phases; ++i) {
+      if (!count[i]) continue;
+      const mp_phase& c = prob->phases[i];
+      const double v[6] = {c.lambda, c.mu, c.kappa, c.alpha, c.beta, c.gamma};
+      for (int k = 0; k < 6; ++k) prod[k] *= v[k];
+      ++present;
+    }
+    for (int k = 0; k < 6; ++k) refv[k] = std::pow(prod[k], 1.0 / present);
   } else {
     std::vector<long> count(prob->n_phases, 0);
     for (long i = 0; i < nvox; ++i) count[prob->phase[i]]++;

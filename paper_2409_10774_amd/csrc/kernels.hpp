@@ -7,8 +7,9 @@
 //          Green operator zeroes it), complex T.  A spectral row (kz, ky) is
 //          one contiguous run of n0/2 * 18 values; a y or z tile of TX
 //          consecutive kx is a contiguous run of TX * 18 values per point.
-//   E      current strain e (c = 0..8) and curvature gamma (c = 9..17), SoA, T
-//   Eprev  the same fields one converged step earlier (extrapolation)
+//   E      current strain e (c = 0..8) and curvature gamma (c = 9..17), SoA,
+//          FP64 in both precisions
+//   Eprev  the same fields one converged step earlier (extrapolation), FP64
 //   base   history base t_n - A e_n (0..8), m_n - B gamma_n (9..17), T
 //   pq     p_n, q_n of the last committed step, FP64
 //
@@ -36,20 +37,28 @@ constexpr int kNAvg = 40;         // step-average rows of a TRANS x pass
 constexpr int kRed = 32;          // per-wave LDS reduction slots
 
 struct Ctl {
-  int done;       // 0 running, 1 converged / fixed count reached, 2 max_iter, 3 diverged,
-                  // 4 stopped at the rounding floor of the low-precision form
+  int done;       // 0 running, 1 converged / fixed count reached, 2 max_iter, 3 diverged
   int iters;      // loop iterations of the current step
   int fixed;      // > 0: run exactly this many iterations
   int max_iter;
   double err;
   double tol;
   int norm;       // 0 local (Eq. 38), 1 average (Eq. 37)
-  int window;     // > 0: floor stop after this many iterations without a new best err
+  int best_it;    // iteration that set `best`
   double err_parts[4];
-  double best;    // smallest err of the step so far
-  int best_it;    // iteration that reached it
-  int pad;
+  double best;    // smallest err of the step so far (divergence test)
+  // low precision: the spectrum the next x pass reads carries the whole
+  // polarization (0) or its increment (1); the pass writes the next one as
+  // wr_incr says
+  int rd_incr;
+  int wr_incr;
 };
+
+// Low precision: a step starts with whole-polarization iterations and turns
+// to increments once the error measure is below this, or has not improved
+// for kIncrStall iterations (the rounding floor of the whole form).
+constexpr double kIncrFrom = 1e-3;
+constexpr int kIncrStall = 20;
 
 enum XMode { X_ITER = 0, X_TRANS = 1, X_FWD_ONLY = 2, X_INV_ONLY = 3 };
 // Z_GREEN_AN: Z_GREEN with a general (Eq. 5) reference medium
@@ -61,8 +70,8 @@ struct XArgs {
   const cx<T>* tw;  // n0-entry twiddles
   cx<T>* S;
   long nvox;
-  T* E;
-  T* Eprev;
+  double* E;        // current iterate e (0..8), gamma (9..17): FP64 in both precisions
+  double* Eprev;    // the same one committed step earlier (extrapolation)
   T* base;
   double* pq;
   T* out_tm;        // committed t (0..8), m (9..17)
@@ -80,6 +89,7 @@ struct XArgs {
   const T* fin;     // X_FWD_ONLY input (18 n)
   T* fout;          // X_INV_ONLY output (18 n)
   const T* eig;     // optional eigenstress (18 n): subtracted in every polarization
+  double relax;     // augmented-Lagrangian ITER passes: over-relaxation of the compatible field
   const double* aniso;  // Eq. 5 row matrices, [record][level][81] (AN kernels)
   const double* refan;  // row matrices [level][81] of a general reference medium
                         // (AN kernels), or null: the isotropic constants `ref`
@@ -206,9 +216,27 @@ __device__ __forceinline__ int avg_row(int L, int j) {
 //   the N0-entry twiddle table in LDS;  tid: the thread index.
 //   AN: some phases have the general tensors of Eq. 5 (elastic phases: their
 //   stresses are the elastic law from the history base, no return map).
-template <class T, int MODE, int N0, bool AN = false>
+//   ALG (ITER, FP64): an iteration of the augmented-Lagrangian scheme in
+//   place of the basic one.  E holds the local strain d, and the spectrum
+//   the Green operator's response to the polarization s(d) - C0 d; the pass
+//   forms the compatible field e = E + that response, over-relaxes it (e^ =
+//   w e + (1 - w) d_old), solves the local step s(d) + C0 d = s(d_old) +
+//   C0 e^ (al_macro_local, al_micro_local), and goes on with d as the new
+//   iterate (return map, error measure and polarization as in the basic pass).
+//   rd_incr, wr_incr (ITER, low precision only): in low precision (T =
+//   float) the strain state, the return map and the polarization stay FP64
+//   and only the transforms run in T.  A step opens (TRANS) with the whole
+//   polarization of its first iterate; an ITER pass reads a spectrum of the
+//   whole polarization (rd_incr = 0: e = E + G tau) or of its increment
+//   (rd_incr = 1: e = e_old + G (tau_i - tau_{i-1}), the Green operator being
+//   linear), and writes the whole polarization or the increment
+//   (wr_incr).  The loop control turns a step to increments once the error
+//   measure is small: then the transforms' rounding scales with the
+//   increment, not with the field, and the step reaches its tolerance.
+template <class T, int MODE, int N0, bool AN = false, bool ALG = false>
 __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl0, int ntiles, cx<T>* lds,
-                                           cx<T>* lds2, double (*red)[kRed], const cx<T>* tw, int tid) {
+                                           cx<T>* lds2, double (*red)[kRed], const cx<T>* tw, int tid,
+                                           bool rd_incr, bool wr_incr) {
   using X = XShape<T, N0>;
   constexpr int ROWS = X::ROWS, VPB = X::VPB, VPAD = X::VPAD, NTHR = X::NTHR, NH = X::NH;
   constexpr int NPK = X::NPK;
@@ -232,24 +260,25 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
   const int gi = own ? int((row0 + vr) * N0 + vx) : 0;
   const long nv = a.nvox;
   MP_GLOBAL cx<T>* const S = glob(a.S);
-  MP_GLOBAL T* const Elv = glob(a.E) + (long)lvl * 9 * nv;
-  MP_GLOBAL T* const Eprev = glob(a.Eprev);
+  MP_GLOBAL double* const Elv = glob(a.E) + (long)lvl * 9 * nv;
+  MP_GLOBAL double* const Eprev = glob(a.Eprev);
   MP_GLOBAL T* const Blv = glob(a.base) + (long)lvl * 9 * nv;
   MP_GLOBAL double* const pq = glob(a.pq);
   MP_GLOBAL double* const partials = glob(a.partials);
   const int rows_here = int(a.nrows - row0 < ROWS ? a.nrows - row0 : ROWS);
 
-  // prefetch this lane's history (ITER, TRANS)
-  T eo[9], bb[9];
+  // prefetch this lane's history (ITER, TRANS); the return map, the
+  // polarization and the error measure run in FP64 in both precisions
+  double eo[9], bb[9];
   double hn = 0.0;
   int ph = 0;
 #pragma unroll
-  for (int c = 0; c < 9; ++c) eo[c] = bb[c] = T(0);
+  for (int c = 0; c < 9; ++c) eo[c] = bb[c] = 0.0;
   if ((MODE == X_ITER || MODE == X_TRANS) && own) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       eo[c] = Elv[c * nv + gi];
-      bb[c] = Blv[c * nv + gi];
+      bb[c] = double(Blv[c * nv + gi]);
     }
     hn = pq[lvl * nv + gi];
     ph = glob(a.phase)[gi];
@@ -329,33 +358,36 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
   if (MODE == X_TRANS && a.commit) {
     // commit (end of the step loop): final return map at the converged
     // iterate, new history base, output fields, step-average partials
-    T tc[9];
+    double tc[9];
     double pc = 0.0, eq = 0.0;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) tc[c] = T(0);
+    for (int c = 0; c < 9; ++c) tc[c] = 0.0;
     if (own) {
-      T r0[9];
+      double r0[9];
       if (AN && aid >= 0) {
-        aniso_apply_wave<T>(a.aniso, a.n_aniso, aid, lvl, eo, r0);
+        aniso_apply_wave<double>(a.aniso, a.n_aniso, aid, lvl, eo, r0);
 #pragma unroll
         for (int c = 0; c < 9; ++c) tc[c] = r0[c] + bb[c];
         pc = hn;
-        eq = lvl == 0 ? macro_equivalent<T>(ct, tc) : micro_equivalent<T>(cm, tc);
+        eq = lvl == 0 ? macro_equivalent<double>(ct, tc) : micro_equivalent<double>(cm, tc);
       } else if (lvl == 0) {
-        macro_return<T>(ct, eo, bb, hn, tc, pc);
-        apply_A<T>(T(ct.lam), T(ct.mu), T(ct.kap), eo, r0);
-        eq = macro_equivalent<T>(ct, tc);
+        macro_return<double>(ct, eo, bb, hn, tc, pc);
+        apply_A<double>(ct.lam, ct.mu, ct.kap, eo, r0);
+        eq = macro_equivalent<double>(ct, tc);
       } else {
-        micro_return<T>(cm, eo, bb, hn, tc, pc);
-        apply_B<T>(T(cm.alp), T(cm.bet), T(cm.gam), eo, r0);
-        eq = micro_equivalent<T>(cm, tc);
+        micro_return<double>(cm, eo, bb, hn, tc, pc);
+        apply_B<double>(cm.alp, cm.bet, cm.gam, eo, r0);
+        eq = micro_equivalent<double>(cm, tc);
       }
       MP_GLOBAL T* const Olv = glob(a.out_tm) + (long)lvl * 9 * nv;
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
-        bb[c] = tc[c] - r0[c];
-        Blv[c * nv + gi] = bb[c];
-        Olv[c * nv + gi] = tc[c];
+        // the base as stored (rounded to T), also for the next step's
+        // first return map below
+        const T b = T(tc[c] - r0[c]);
+        bb[c] = double(b);
+        Blv[c * nv + gi] = b;
+        Olv[c * nv + gi] = T(tc[c]);
       }
       hn = pc;
       pq[lvl * nv + gi] = pc;
@@ -384,22 +416,32 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
   }
 
   {
-    T e[9];
+    double e[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) e[c] = T(0);
+    for (int c = 0; c < 9; ++c) e[c] = 0.0;
     if (own) {
       if (MODE == X_FWD_ONLY) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) e[c] = glob(a.fin)[(lvl * 9 + c) * nv + gi];
+        for (int c = 0; c < 9; ++c) e[c] = double(glob(a.fin)[(lvl * 9 + c) * nv + gi]);
       } else if (MODE == X_ITER) {
+        if (sizeof(T) == 8 || !rd_incr) {
+          // e = E + the fluctuation the Green operator returned (Alg. 2)
 #pragma unroll
-        for (int c = 0; c < 9; ++c) e[c] = ldr[slot(lvl * 9 + c)] + T(a.mac[lvl * 9 + c]);
+          for (int c = 0; c < 9; ++c) e[c] = double(ldr[slot(lvl * 9 + c)]) + a.mac[lvl * 9 + c];
+        } else {
+          // low precision: the transforms carried the polarization
+          // increment, e = e_old + G(tau_i - tau_{i-1}) (the Green operator
+          // is linear), so their rounding scales with the increment, not
+          // with the field
+#pragma unroll
+          for (int c = 0; c < 9; ++c) e[c] = eo[c] + double(ldr[slot(lvl * 9 + c)]);
+        }
       } else {  // X_TRANS: first iterate of the step (Alg. 2)
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
           const long at = (lvl * 9 + c) * nv + gi;
-          const T old = Eprev[at];
-          e[c] = a.first ? T(a.mac[lvl * 9 + c]) : T(eo[c] + T(a.r) * (eo[c] - old));
+          const double old = Eprev[at];
+          e[c] = a.first ? a.mac[lvl * 9 + c] : eo[c] + a.r * (eo[c] - old);
           Eprev[at] = eo[c];
         }
       }
@@ -410,43 +452,83 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
     if (MODE == X_FWD_ONLY) {
       if (own)
 #pragma unroll
-        for (int c = 0; c < 9; ++c) ldr[slot(lvl * 9 + c)] = e[c];
+        for (int c = 0; c < 9; ++c) ldr[slot(lvl * 9 + c)] = T(e[c]);
     } else {
-      T t[9];
+      // stresses of a strain by this lane's law: Alg. 1 from the history
+      // base, or the elastic law of an Eq. 5 phase
+      auto law = [&](const double* x, double* out, double& pout) {
+        if (AN && aid >= 0) {
+          aniso_apply_wave<double>(a.aniso, a.n_aniso, aid, lvl, x, out);
 #pragma unroll
-      for (int c = 0; c < 9; ++c) t[c] = T(0);
+          for (int c = 0; c < 9; ++c) out[c] += bb[c];
+          pout = hn;
+        } else if (lvl == 0) {
+          macro_return<double>(ct, x, bb, hn, out, pout);
+        } else {
+          micro_return<double>(cm, x, bb, hn, out, pout);
+        }
+      };
+      // the reference medium's stresses A0 e (B0 gamma) of the polarization
+      auto ref_law = [&](const double* x, double* out) {
+        if (AN && a.refan)
+          aniso_apply<double>(cnst(a.refan) + lvl * 81, x, out);
+        else if (lvl == 0)
+          apply_A<double>(a.ref.lam, a.ref.mu, a.ref.kap, x, out);
+        else
+          apply_B<double>(a.ref.alp, a.ref.bet, a.ref.gam, x, out);
+      };
+      // low-precision loop iterations compute the old iterate's stresses
+      // first (the polarization increment needs them); the FP64 pass
+      // recomputes them later, for the error measure only
+      constexpr bool LOWP = sizeof(T) < sizeof(double) && MODE == X_ITER;
+      double t[9], to[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) t[c] = to[c] = 0.0;
       double pnew;
       if (own) {
-        if (AN && aid >= 0) {
-          aniso_apply_wave<T>(a.aniso, a.n_aniso, aid, lvl, e, t);
+        if constexpr (ALG) {
+          // e holds the compatible field: the local step turns it into d
+          double pold, eh[9], rr[9];
+          law(eo, to, pold);
 #pragma unroll
-          for (int c = 0; c < 9; ++c) t[c] += bb[c];
-          pnew = hn;
-        } else if (lvl == 0) {
-          macro_return<T>(ct, e, bb, hn, t, pnew);
-        } else {
-          micro_return<T>(cm, e, bb, hn, t, pnew);
+          for (int c = 0; c < 9; ++c) eh[c] = a.relax * e[c] + (1.0 - a.relax) * eo[c];
+          ref_law(eh, rr);
+#pragma unroll
+          for (int c = 0; c < 9; ++c) rr[c] += to[c];
+          if (lvl == 0)
+            al_macro_local(ct, a.ref, rr, bb, hn, e);
+          else
+            al_micro_local(cm, a.ref, rr, bb, eh, hn, e);
         }
+        law(e, t, pnew);
         // polarization (Eq. 34): tau = t - A0 e ; mu = m - B0 gamma, less the
         // eigenstress when one is set (the manufactured stresses of the code
         // verification, App. D.1)
-        T r0[9];
-        if (AN && a.refan)
-          aniso_apply<T>(cnst(a.refan) + lvl * 81, e, r0);
-        else if (lvl == 0)
-          apply_A<T>(T(a.ref.lam), T(a.ref.mu), T(a.ref.kap), e, r0);
-        else
-          apply_B<T>(T(a.ref.alp), T(a.ref.bet), T(a.ref.gam), e, r0);
+        double r0[9];
+        ref_law(e, r0);
 #pragma unroll
         for (int c = 0; c < 9; ++c) r0[c] = t[c] - r0[c];
-        if (a.eig) {
+        bool whole = true;
+        if constexpr (LOWP) {
+          double pold;
+          law(eo, to, pold);
+          if (wr_incr) {
+            // the increment tau(e) - tau(e_old); the eigenstress cancels
+            double q0[9];
+            ref_law(eo, q0);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) r0[c] -= to[c] - q0[c];
+            whole = false;
+          }
+        }
+        if (whole && a.eig) {
           const MP_GLOBAL T* const eg = glob(a.eig) + (long)lvl * 9 * nv;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) r0[c] -= eg[c * nv + gi];
+          for (int c = 0; c < 9; ++c) r0[c] -= double(eg[c * nv + gi]);
         }
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
-          ldr[slot(lvl * 9 + c)] = r0[c];
+          ldr[slot(lvl * 9 + c)] = T(r0[c]);
           Elv[c * nv + gi] = e[c];
         }
       }
@@ -457,10 +539,10 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
         double da = 0, sa = 0, sb = 0;
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
-          const double x = double(e[c]) - double(eo[c]);
+          const double x = e[c] - eo[c];
           da += x * x;
-          sa += double(e[c]) * double(e[c]);
-          sb += double(t[c]) * double(t[c]);
+          sa += e[c] * e[c];
+          sb += t[c] * t[c];
         }
         da = sqrt(da);
         {
@@ -474,27 +556,20 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
           v[4] = own ? sa : 0.0;
           v[5] = own ? sb : 0.0;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) v[6 + c] = own ? double(t[c]) : 0.0;
+          for (int c = 0; c < 9; ++c) v[6 + c] = own ? t[c] : 0.0;
           v[15] = 0.0;
           wave_reduce<16>(v, 0x1u, lane, red[wv]);
         }
         // the old iterate's stresses, recomputed from the old strain (Alg. 1)
         double db = 0;
         if (own) {
-          T to[9];
-          double pold;
-          if (AN && aid >= 0) {
-            aniso_apply_wave<T>(a.aniso, a.n_aniso, aid, lvl, eo, to);
-#pragma unroll
-            for (int c = 0; c < 9; ++c) to[c] += bb[c];
-          } else if (lvl == 0) {
-            macro_return<T>(ct, eo, bb, hn, to, pold);
-          } else {
-            micro_return<T>(cm, eo, bb, hn, to, pold);
+          if constexpr (!LOWP && !ALG) {
+            double pold;
+            law(eo, to, pold);
           }
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
-            const double y = double(t[c]) - double(to[c]);
+            const double y = t[c] - to[c];
             db += y * y;
           }
         }
@@ -531,34 +606,37 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
   }
 }
 
-// The ITER pass is held to 3 waves per SIMD in FP64 and 4 in FP32 (at most
-// 168 / 128 VGPRs).
-template <class T, int MODE>
-constexpr int x_min_waves() { return MODE != X_ITER ? 1 : sizeof(T) == 8 ? 3 : 4; }
+// The ITER pass is held to 3 waves per SIMD (at most 168 VGPRs); its return
+// map and polarization are FP64 in both precisions.  The augmented-Lagrangian
+// ITER pass (a local solve per level on top) is held to 2 (256 VGPRs).
+template <class T, int MODE, bool ALG = false>
+constexpr int x_min_waves() { return MODE != X_ITER ? 1 : ALG ? 2 : 3; }
 
 // the levels of one tile per block (x_item; grid x_grid(ntiles)); every
 // kernel of the step loop returns at once when the step's control block says
 // the loop is finished
-template <class T, int MODE, int N0, bool AN = false>
-__global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE>())) k_xpass(XArgs<T> a,
+template <class T, int MODE, int N0, bool AN = false, bool ALG = false>
+__global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE, ALG>())) k_xpass(XArgs<T> a,
                                                                                        const Ctl* ctl,
                                                                                        int ntiles) {
   using X = XShape<T, N0>;
   if (ctl && ctl->done) return;
+  // whole polarization or its increment (low precision, ITER)
+  const bool rd = ctl && ctl->rd_incr, wr = ctl && ctl->wr_incr;
   __shared__ cx<T> lds[X::NPK * N0];
   __shared__ cx<T> lds2[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
   __shared__ cx<T> twl[N0];
   if constexpr (X::LPB == 2) {   // grid = ntiles, block b is tile b
     load_twiddles<T, N0, X::NTHR>(twl, glob(a.tw), threadIdx.x);
-    xpass_tile<T, MODE, N0, AN>(a, blockIdx.x, 0, gridDim.x, lds, lds2, red, twl, threadIdx.x);
+    xpass_tile<T, MODE, N0, AN, ALG>(a, blockIdx.x, 0, gridDim.x, lds, lds2, red, twl, threadIdx.x, rd, wr);
   } else {
     long tile;
     int lvl;
     x_item<X::LPB>(blockIdx.x, &tile, &lvl);
     if (tile >= ntiles) return;
     load_twiddles<T, N0, X::NTHR>(twl, glob(a.tw), threadIdx.x);
-    xpass_tile<T, MODE, N0, AN>(a, tile, lvl, ntiles, lds, lds2, red, twl, threadIdx.x);
+    xpass_tile<T, MODE, N0, AN, ALG>(a, tile, lvl, ntiles, lds, lds2, red, twl, threadIdx.x, rd, wr);
   }
 }
 
@@ -803,10 +881,13 @@ __device__ __forceinline__ void err_finalize(const double* tot, long nvox, Ctl* 
   ctl->err = err;
   const int it = ctl->iters + 1;
   ctl->iters = it;
-  if (err < ctl->best * (1.0 - 1e-3)) {
+  if (err < ctl->best) {
     ctl->best = err;
     ctl->best_it = it;
   }
+  // the x pass that follows reads what the last one wrote
+  ctl->rd_incr = ctl->wr_incr;
+  if (!ctl->wr_incr && (err <= kIncrFrom || it - ctl->best_it >= kIncrStall)) ctl->wr_incr = 1;
   // divergence: a non-finite measure, or growth far above the step's best
   // (a large err alone is legitimate when a field's mean is nearly zero)
   const bool diverged = !(err <= 1e300) || (it > 5 && err > 1e6 * ctl->best);
@@ -819,8 +900,6 @@ __device__ __forceinline__ void err_finalize(const double* tot, long nvox, Ctl* 
     done = 1;
   } else if (it >= ctl->max_iter) {
     done = 2;
-  } else if (ctl->window > 0 && it - ctl->best_it >= ctl->window) {
-    done = 4;
   }
   ctl->done = done;
 }
@@ -829,8 +908,7 @@ struct ErrMacro {
   double v[18];   // prescribed E then Gamma of the step
 };
 
-__device__ __forceinline__ void ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm,
-                                          int window) {
+__device__ __forceinline__ void ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm) {
   ctl->done = 0;
   ctl->iters = 0;
   ctl->fixed = fixed;
@@ -838,9 +916,17 @@ __device__ __forceinline__ void ctl_reset(Ctl* ctl, int fixed, int max_iter, dou
   ctl->err = 2.0 * tol;
   ctl->tol = tol;
   ctl->norm = norm;
-  ctl->window = window;
   ctl->best = 1e300;
   ctl->best_it = 0;
+  ctl->rd_incr = 0;
+  ctl->wr_incr = 0;
+}
+
+// widen n values to FP64 (field read-back into device memory)
+template <class S>
+__global__ void __launch_bounds__(256) k_widen(const S* in, double* out, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = double(in[i]);
 }
 
 // pointwise Alg. 1 on independent points (same device code as the solver)

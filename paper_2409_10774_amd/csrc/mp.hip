@@ -32,8 +32,8 @@ __global__ void k_err_final(const double* tot, long nvox, Ctl* ctl, ErrMacro mac
   err_finalize(tot, nvox, ctl, mac.v);
 }
 
-__global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm, int window) {
-  ctl_reset(ctl, fixed, max_iter, tol, norm, window);
+__global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int norm) {
+  ctl_reset(ctl, fixed, max_iter, tol, norm);
 }
 
 // FFT twiddle tables exp(-2 pi i m / n) of the three axes, one after the
@@ -53,7 +53,7 @@ __global__ void k_twiddles(cx<double>* tw, int n0, int n1, int n2) {
 namespace {
 
 constexpr int kProfEv = 6;     // boundaries around the 5 loop kernels of one iteration
-constexpr int kRecord = 47;    // step record: 40 averages, err, iters, 4 err parts, floor flag
+constexpr int kRecord = 47;    // step record: 40 averages, err, iters, 4 err parts, reserved (0)
 
 }  // namespace
 
@@ -83,8 +83,11 @@ struct mp_plan_s {
   RefC ref;
   double tol;
   int max_iter, norm, fixed;
+  bool al;        // augmented-Lagrangian iterations (MP_SCHEME_AL)
+  double relax;   // their over-relaxation
   int n_phases;
   int steps;
+  bool failed;            // a step diverged: no further steps
   double t_prev, t_cur;   // times of the last two committed states
   std::vector<std::vector<double>> resp_hist;
   // optional per-kernel timing of loop iterations (hipEvents on the plan's stream)
@@ -163,8 +166,8 @@ struct Eng {
     a.tw = tw(P, 0);
     a.S = S(P);
     a.nvox = g.nvox;
-    a.E = static_cast<T*>(P->E);
-    a.Eprev = static_cast<T*>(P->Eprev);
+    a.E = static_cast<double*>(P->E);
+    a.Eprev = static_cast<double*>(P->Eprev);
     a.base = static_cast<T*>(P->base);
     a.pq = P->pq;
     a.out_tm = static_cast<T*>(P->out_tm);
@@ -177,6 +180,7 @@ struct Eng {
     a.aniso = P->aniso;
     a.n_aniso = g.n_aniso;
     a.refan = P->refan;
+    a.relax = P->relax;
     return a;
   }
 
@@ -236,10 +240,8 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     xa.r = xa.first ? 0.0 : (times[s] - P->t_cur) / (P->t_cur - P->t_prev);
     xa.commit = pending;
     xa.init = 1;
-    // the low-precision form may stop at its rounding floor: no new best
-    // error for kFloorWindow iterations (flagged in the step record)
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(1), 0, P->stream, P->ctl, P->fixed, P->max_iter,
-                       P->tol, P->norm, sizeof(T) < sizeof(double) ? kFloorWindow : 0);
+                       P->tol, P->norm);
     P->ctl_host->iters = 0;
     P->ctl_host->done = 0;
     // commit of the previous step, first iterate of this one (extrapolated
@@ -272,7 +274,7 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
         hipEvent_t* ev = P->prof ? &P->ev[size_t(k) * kProfEv] : nullptr;
         spectral(P, S(P), P->ctl, P->prof == 1 ? ev : nullptr);
         if (P->prof == 2) HIP_TRY(hipEventRecord(ev[3], P->stream));
-        launch_x<T, X_ITER>(g.n0, g.xblocks, P->stream, xa, P->ctl, g.n_aniso > 0 || g.ref_tensor);
+        launch_x<T, X_ITER>(g.n0, g.xblocks, P->stream, xa, P->ctl, g.n_aniso > 0 || g.ref_tensor, P->al);
         if (ev) HIP_TRY(hipEventRecord(ev[4], P->stream));
         hipLaunchKernelGGL(k_rows, dim3(kNPart), dim3(256), 0, P->stream, P->partials, g.xblocks, 0,
                            P->tot, P->ctl);
@@ -299,18 +301,26 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
       batch = std::min(batch * 2, 64);
     }
     const Ctl c = *P->ctl_host;
+    if (iters) iters[s - 1] = c.iters;
+    if (c.done == 3) {
+      // a diverged iterate is no converged state: the step is not committed,
+      // and the plan takes no further steps
+      P->failed = true;
+      st = MP_E_DIVERGED;
+      msg = "step " + std::to_string(P->steps + 1) + " diverged (not committed)";
+      break;
+    }
     std::fill(rec.begin(), rec.end(), 0.0);
     rec[40] = c.err;
     rec[41] = c.iters;
     for (int f = 0; f < 4; ++f) rec[42 + f] = c.err_parts[f];
-    rec[46] = c.done == 4 ? 1.0 : 0.0;
+    rec[46] = 0.0;
     pending = true;
     P->t_prev = P->t_cur;
     P->t_cur = times[s];
-    if (iters) iters[s - 1] = c.iters;
-    if (c.done == 2 || c.done == 3) {
-      st = c.done == 2 ? MP_E_NOT_CONVERGED : MP_E_DIVERGED;
-      msg = "step " + std::to_string(P->steps + 1) + (c.done == 2 ? " hit max_iter" : " diverged");
+    if (c.done == 2) {
+      st = MP_E_NOT_CONVERGED;
+      msg = "step " + std::to_string(P->steps + 1) + " hit max_iter (committed)";
       break;
     }
   }
@@ -422,10 +432,13 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   P->max_iter = prob->max_iter;
   P->norm = prob->err_norm;
   P->fixed = 0;
+  P->al = prob->scheme == MP_SCHEME_AL;
+  P->relax = P->al ? prob->relax : 1.0;
   P->prof = 0;
   for (int j = 0; j < 8; ++j) { P->prof_ms[j] = 0.0; P->prof_n[j] = 0; }
   P->n_phases = prob->n_phases;
   P->steps = 0;
+  P->failed = false;
   P->t_prev = P->t_cur = 0.0;
 
   // reference medium (Alg. 2: A0 = <A>, B0 = <B>); phase mean by default
@@ -559,6 +572,7 @@ mp_status mp_solve_load_path(mp_plan P, int32_t n_steps, const double* times, co
   if (!P) return fail(MP_E_INVALID, "plan is NULL");
   if (n_steps < 0 || (n_steps > 0 && (!times || !E || !Gam)))
     return fail(MP_E_INVALID, "bad load path");
+  if (P->failed) return fail(MP_E_STATE, "a step of this plan diverged; it takes no further steps");
   if (n_steps == 0) return MP_OK;
   if (P->steps > 0 && times[0] != P->t_cur)
     return fail(MP_E_STATE, "times[0] must equal the time of the last committed step");
@@ -584,32 +598,12 @@ mp_status mp_step_error_parts(mp_plan P, int32_t step, double out[5]) {
   return MP_OK;
 }
 
-mp_status mp_get_fields(mp_plan P, int32_t field, double* dst) {
-  if (!P || !dst) return fail(MP_E_INVALID, "NULL argument");
-  const long n = P->g.nvox;
+mp_status mp_get_fields(mp_plan P, uint32_t mask, void* const* dst, int32_t dst_is_device) {
+  if (!P) return fail(MP_E_INVALID, "plan is NULL");
   const size_t w = P->precision == MP_MIXED ? sizeof(float) : sizeof(double);
-  const unsigned char* src = nullptr;
-  long count = 9 * n;
-  bool bulk = true;   // stored in the bulk type (else FP64)
-  switch (field) {
-    case MP_FIELD_E: src = static_cast<const unsigned char*>(P->E); break;
-    case MP_FIELD_GAMMA: src = static_cast<const unsigned char*>(P->E) + 9 * n * w; break;
-    case MP_FIELD_T: src = static_cast<const unsigned char*>(P->out_tm); break;
-    case MP_FIELD_M: src = static_cast<const unsigned char*>(P->out_tm) + 9 * n * w; break;
-    case MP_FIELD_P: src = reinterpret_cast<const unsigned char*>(P->out_pq); count = n; bulk = false; break;
-    case MP_FIELD_Q: src = reinterpret_cast<const unsigned char*>(P->out_pq + n); count = n; bulk = false; break;
-    default: return fail(MP_E_INVALID, "unknown field");
-  }
-  if (bulk && w == sizeof(float)) {
-    std::vector<float> tmp(count);
-    HIP_TRY(hipMemcpyAsync(tmp.data(), src, count * sizeof(float), hipMemcpyDeviceToHost, P->stream));
-    HIP_TRY(hipStreamSynchronize(P->stream));
-    for (long i = 0; i < count; ++i) dst[i] = double(tmp[i]);
-    return MP_OK;
-  }
-  HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-  HIP_TRY(hipStreamSynchronize(P->stream));
-  return MP_OK;
+  return copy_fields(static_cast<const unsigned char*>(P->E), static_cast<const unsigned char*>(P->out_tm),
+                     reinterpret_cast<const unsigned char*>(P->out_pq), P->g.nvox, w, mask, dst,
+                     dst_is_device, P->stream);
 }
 
 mp_status mp_spectrum_forward(mp_plan P, const void* dev_in, void* dev_out) {

@@ -24,7 +24,9 @@ STATUS_NAMES = {0: "MP_OK", 1: "MP_E_INVALID", 2: "MP_E_NOMEM", 3: "MP_E_DEVICE"
                 4: "MP_E_NOT_CONVERGED", 5: "MP_E_DIVERGED", 6: "MP_E_STATE"}
 MP_FP64, MP_MIXED = 0, 1
 MP_ERR_LOCAL, MP_ERR_AVERAGE = 0, 1
-MP_REF_PHASE_MEAN, MP_REF_VOLUME_MEAN, MP_REF_EXPLICIT, MP_REF_TENSOR_MEAN, MP_REF_TENSOR_PHASE_MEAN = range(5)
+MP_REF_PHASE_MEAN, MP_REF_VOLUME_MEAN, MP_REF_EXPLICIT, MP_REF_TENSOR_MEAN, MP_REF_TENSOR_PHASE_MEAN, \
+    MP_REF_GEOMETRIC_MEAN = range(6)
+MP_SCHEME_BASIC, MP_SCHEME_AL = 0, 1
 FIELDS = {"e": 0, "g": 1, "t": 2, "m": 3, "p": 4, "q": 5}
 
 
@@ -42,7 +44,7 @@ class mp_problem(C.Structure):
                 ("n_phases", C.c_int32), ("phases", C.POINTER(mp_phase)), ("ref_mode", C.c_int32),
                 ("ref", mp_phase), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("err_norm", C.c_int32), ("precision", C.c_int32), ("n_aniso", C.c_int32),
-                ("aniso", C.POINTER(mp_aniso))]
+                ("aniso", C.POINTER(mp_aniso)), ("scheme", C.c_int32), ("relax", C.c_double)]
 
 
 class mp_batch_config(C.Structure):
@@ -53,7 +55,8 @@ class mp_batch_config(C.Structure):
 class mp_request(C.Structure):
     _fields_ = [("arrival", C.c_double), ("prob", C.POINTER(mp_problem)), ("n_steps", C.c_int32),
                 ("times", C.POINTER(C.c_double)), ("E", C.POINTER(C.c_double)),
-                ("Gam", C.POINTER(C.c_double))]
+                ("Gam", C.POINTER(C.c_double)), ("records", C.POINTER(C.c_double)),
+                ("field_mask", C.c_uint32), ("fields", C.c_void_p * 6), ("fields_on_device", C.c_int32)]
 
 
 MP_RVE_RUNNING, MP_RVE_DONE = 0, 1
@@ -76,7 +79,7 @@ def _load():
         "mp_plan_create": (C.c_int, [C.POINTER(mp_problem), vp, C.c_size_t, vp, C.POINTER(vp)]),
         "mp_solve_load_path": (C.c_int, [vp, i32, dp, dp, dp, C.POINTER(i32)]),
         "mp_homogenized_response": (C.c_int, [vp, i32, dp]),
-        "mp_get_fields": (C.c_int, [vp, i32, dp]),
+        "mp_get_fields": (C.c_int, [vp, C.c_uint32, C.POINTER(vp), i32]),
         "mp_step_error_parts": (C.c_int, [vp, i32, dp]),
         "mp_set_fixed_iterations": (C.c_int, [vp, i32]),
         "mp_set_eigenstress": (C.c_int, [vp, vp]),
@@ -97,7 +100,7 @@ def _load():
         "mp_batch_query": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                      C.POINTER(i64)]),
         "mp_batch_response": (C.c_int, [vp, i32, i32, dp]),
-        "mp_batch_get_field": (C.c_int, [vp, i32, i32, dp]),
+        "mp_batch_get_fields": (C.c_int, [vp, i32, C.c_uint32, C.POINTER(vp), i32]),
         "mp_batch_release": (C.c_int, [vp, i32]),
         "mp_batch_set_fixed_iterations": (C.c_int, [vp, i32, i32]),
         "mp_batch_schedule": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(C.c_float)]),
@@ -138,7 +141,7 @@ def _phase_struct(p) -> mp_phase:
 
 
 def make_problem(phase_map, phases, h=1.0, tol=1e-8, max_iter=20000, err_norm="local",
-                 ref_mode="phase_mean", ref=None, precision="fp64"):
+                 ref_mode="phase_mean", ref=None, precision="fp64", scheme="basic", relax=1.7):
     """Build an mp_problem (and keep its host arrays alive on the returned object)."""
     pm = np.ascontiguousarray(phase_map, dtype=np.uint8)
     if pm.ndim != 3:
@@ -153,13 +156,16 @@ def make_problem(phase_map, phases, h=1.0, tol=1e-8, max_iter=20000, err_norm="l
     prob.phases = C.cast(arr, C.POINTER(mp_phase))
     prob.ref_mode = {"phase_mean": MP_REF_PHASE_MEAN, "volume_mean": MP_REF_VOLUME_MEAN,
                      "explicit": MP_REF_EXPLICIT, "tensor_mean": MP_REF_TENSOR_MEAN,
-                     "tensor_phase_mean": MP_REF_TENSOR_PHASE_MEAN}[ref_mode]
+                     "tensor_phase_mean": MP_REF_TENSOR_PHASE_MEAN,
+                     "geometric_mean": MP_REF_GEOMETRIC_MEAN}[ref_mode]
     if ref is not None:
         prob.ref = mp_phase(*(list(float(v) for v in ref) + [0.0] * (12 - len(ref))))
     prob.tol = float(tol)
     prob.max_iter = int(max_iter)
     prob.err_norm = {"local": MP_ERR_LOCAL, "average": MP_ERR_AVERAGE}[err_norm]
     prob.precision = {"fp64": MP_FP64, "mixed": MP_MIXED}[precision]
+    prob.scheme = {"basic": MP_SCHEME_BASIC, "al": MP_SCHEME_AL}[scheme]
+    prob.relax = float(relax)
     # phases carrying general Eq. 5 tensors: A[k, l, m, n] = A_klmn and
     # B[l, k, m, n] = B_lkmn, flattened in that index order
     tens = [(i, p) for i, p in enumerate(phases) if getattr(p, "A", None) is not None]
@@ -230,23 +236,23 @@ class Plan:
         return np.array(out[:])
 
     def error_parts(self, step):
-        """(err_e, err_t, err_gamma, err_m, floor_stop) of a committed step."""
+        """(err_e, err_t, err_gamma, err_m, 0) of a committed step."""
         out = (C.c_double * 5)()
         check(lib.mp_step_error_parts(self.handle, int(step), out))
         return np.array(out[:])
 
     def responses(self):
-        return np.array([self.response(s) for s in range(1, self.steps() + 1)])
+        n = self.steps()
+        return np.array([self.response(s) for s in range(1, n + 1)]).reshape(n, 42)
 
     def field(self, name):
-        n = self.nvox
-        count = 9 * n if name in ("e", "g", "t", "m") else n
-        out = np.empty(count, np.float64)
-        check(lib.mp_get_fields(self.handle, FIELDS[name],
-                                out.ctypes.data_as(C.POINTER(C.c_double))))
-        if count == n:
-            return out.reshape(self.shape)
-        return out.reshape((9,) + self.shape)
+        return self.fields((name,))[name]
+
+    def fields(self, names=FIELDS, device=False):
+        """{name: FP64 array} of the committed state (mp_get_fields): numpy
+        arrays, or torch tensors on the plan's device when device=True."""
+        return _read_fields(lambda mask, dst, dev: lib.mp_get_fields(self.handle, mask, dst, dev),
+                            self.shape, names, device, self.device)
 
     def set_fixed_iterations(self, n):
         check(lib.mp_set_fixed_iterations(self.handle, int(n)))
@@ -327,6 +333,30 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _read_fields(call, shape, names, device, dev):
+    """Marshal a field read-back through `call(mask, dst, dst_is_device)`."""
+    nvox = int(np.prod(shape))
+    dst = (C.c_void_p * 6)()
+    out, mask = {}, 0
+    for name in names:
+        f = FIELDS[name]
+        full = (9,) + tuple(shape) if name in ("e", "g", "t", "m") else tuple(shape)
+        if device:
+            import torch
+            a = torch.empty(full, dtype=torch.float64, device=dev)
+            dst[f] = a.data_ptr()
+        else:
+            a = np.empty(full, np.float64)
+            dst[f] = a.ctypes.data
+        out[name] = a
+        mask |= 1 << f
+    check(call(mask, dst, 1 if device else 0))
+    if device:
+        import torch
+        torch.cuda.current_stream(dev).synchronize()
+    return out
 
 
 def _path(times, E, G):
@@ -416,17 +446,17 @@ class Batch:
         return np.array(out[:])
 
     def responses(self, rid):
-        """[steps, 47]: response (42) then error parts and floor flag (5)"""
+        """[steps, 47]: response (42) then error parts and a reserved 0 (5)"""
         n = self.query(rid)[2]
-        return np.array([self.record(rid, s)[:47] for s in range(1, n + 1)])
+        return np.array([self.record(rid, s)[:47] for s in range(1, n + 1)]).reshape(n, 47)
 
     def field(self, rid, name):
-        shape = self._shape[rid]
-        nvox = int(np.prod(shape))
-        count = 9 * nvox if name in ("e", "g", "t", "m") else nvox
-        out = np.empty(count, np.float64)
-        check(lib.mp_batch_get_field(self.handle, int(rid), FIELDS[name], _dp(out)))
-        return out.reshape(shape) if count == nvox else out.reshape((9,) + shape)
+        return self.fields(rid, (name,))[name]
+
+    def fields(self, rid, names=FIELDS, device=False):
+        """{name: FP64 array} of RVE rid's committed state (mp_batch_get_fields)."""
+        return _read_fields(lambda mask, dst, dev: lib.mp_batch_get_fields(self.handle, int(rid), mask, dst, dev),
+                            self._shape[rid], names, device, self.device)
 
     def set_fixed_iterations(self, rid, n):
         check(lib.mp_batch_set_fixed_iterations(self.handle, int(rid), int(n)))
@@ -464,11 +494,16 @@ class Batch:
 
 
 class Requests:
-    """Marshalled request trace: items (arrival, phase_map, phases, times, E, G, kw)."""
+    """Marshalled request trace: items (arrival, phase_map, phases, times, E, G, kw).
 
-    def __init__(self, items, precision="mixed"):
+    The replies land in self.records[i] ([n_steps, 48] host array, when
+    records=True) and self.fields[i] ({name: array} for the names in
+    `fields`; torch tensors on `device` when given, else numpy arrays)."""
+
+    def __init__(self, items, precision="mixed", records=True, fields=(), device=None):
         self.arr = (mp_request * max(1, len(items)))()
         self._keep = []
+        self.records, self.fields = [], []
         for i, (arrival, pm, phases, times, E, G, kw) in enumerate(items):
             prob = make_problem(pm, phases, precision=precision, **kw)
             S, times, E, G = _path(times, E, G)
@@ -478,6 +513,26 @@ class Requests:
             r.prob = C.pointer(prob)
             r.n_steps = S
             r.times, r.E, r.Gam = _dp(times), _dp(E), _dp(G)
+            rec = np.full((S, 48), np.nan) if records else None
+            self.records.append(rec)
+            r.records = _dp(rec) if records else C.POINTER(C.c_double)()
+            out, mask = {}, 0
+            shape = np.asarray(pm).shape
+            for name in fields:
+                f = FIELDS[name]
+                full = (9,) + tuple(shape) if name in ("e", "g", "t", "m") else tuple(shape)
+                if device is not None:
+                    import torch
+                    a = torch.full(full, float("nan"), dtype=torch.float64, device=device)
+                    r.fields[f] = a.data_ptr()
+                else:
+                    a = np.full(full, np.nan)
+                    r.fields[f] = a.ctypes.data
+                out[name] = a
+                mask |= 1 << f
+            r.field_mask = mask
+            r.fields_on_device = 1 if device is not None else 0
+            self.fields.append(out)
         self.n = len(items)
 
 

@@ -163,9 +163,13 @@ def test_serving_with_anisotropic_requests(mp):
              for t, w, k in zip(arrivals, wls, kw)]
     B = mp.Batch([(12, 6, 8), (16, 16, 16)], arena_bytes=128 << 20, precision="mixed", max_rves=8,
                  iters_per_launch=8)
-    ta, td, st, it = mp.serve_batched(B, mp.Requests(items, precision="mixed"))
+    from tests.test_gpu_batch import FIELDS, assert_reply
+    reqs = mp.Requests(items, precision="mixed", fields=FIELDS)
+    ta, td, st, it = mp.serve_batched(B, reqs)
     say("admit", np.round(ta, 3), "done", np.round(td, 3), "iters", it)
     assert (st == mp.MP_OK).all()
     for i, (w, k) in enumerate(zip(wls, kw)):
-        assert it[i] == sum(solo(mp, w, "mixed", **k)["iters"]), i
+        ref = solo(mp, w, "mixed", **k)
+        assert it[i] == sum(ref["iters"]), i
+        assert_reply(reqs, i, ref, i)
     B.close()

@@ -36,7 +36,8 @@ def solo(mp, wl, precision, **kw):
     plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision=precision, **kw)
     st, it = plan.solve(wl.times, wl.E, wl.G, raise_on_error=False)
     n = plan.steps()
-    rec = np.array([np.concatenate([plan.response(s), plan.error_parts(s)]) for s in range(1, n + 1)])
+    rec = np.array([np.concatenate([plan.response(s), plan.error_parts(s)])
+                    for s in range(1, n + 1)]).reshape(n, 47)
     out = dict(status=st, iters=it[:n], rec=rec, fields={k: plan.field(k) for k in FIELDS})
     plan.close()
     return out
@@ -166,6 +167,7 @@ def test_batch_alone_vs_mix_with_failures(mp):
         assert_same(b, s, rid)
     assert batched(B, ids[0])["status"] == mp.MP_E_NOT_CONVERGED
     assert batched(B, ids[1])["status"] == mp.MP_E_DIVERGED
+    assert B.query(ids[1])[2] == 0          # the diverged step is not committed
     B.close()
 
 
@@ -215,10 +217,25 @@ def test_batch_admission_by_footprint(mp):
     B.close()
 
 
+def assert_reply(reqs, i, ref, tag):
+    """A served request's reply (step records, final fields) equals the solo
+    solve of the same precision bit for bit."""
+    rec = reqs.records[i]
+    n = len(ref["iters"])
+    assert np.array_equal(rec[:n, :47], ref["rec"]), (tag, np.abs(rec[:n, :47] - ref["rec"]).max())
+    assert np.isnan(rec[n:]).all()
+    for k in FIELDS:
+        got = reqs.fields[i][k]
+        got = got.cpu().numpy() if hasattr(got, "cpu") else got
+        assert np.array_equal(got, ref["fields"][k]), (tag, k)
+
+
 def test_serving_loops(mp):
-    """A short Poisson trace through continuous batching (mixed) and through
-    the sequential FP64 server: every request answered, iteration totals equal
-    to the solo solves of the same precision."""
+    """A short Poisson trace through continuous batching (mixed, fields
+    delivered into device memory) and through the sequential FP64 server
+    (host memory): every request answered, and every reply (step records and
+    final fields) equal to the solo solve of the same precision bit for bit,
+    alone against in the mix."""
     say("case: serving loops on a 6-request trace")
     rng = np.random.default_rng(5)
     wls = mixed_set(1e-6)
@@ -226,22 +243,50 @@ def test_serving_loops(mp):
     import torch
     items = [(a, w.phase_map, w.phases, w.times, w.E, w.G, dict(tol=w.tol)) for a, w in zip(arrivals, wls)]
     B = mp.Batch(SHAPES, arena_bytes=256 << 20, precision="mixed", max_rves=16, iters_per_launch=8)
-    reqs = mp.Requests(items, precision="mixed")
+    reqs = mp.Requests(items, precision="mixed", fields=FIELDS, device="cuda:0")
     ta, td, st, it = mp.serve_batched(B, reqs)
     say("batched admit", np.round(ta, 3), "done", np.round(td, 3), "iters", it)
     assert (st == mp.MP_OK).all()
     assert (ta >= arrivals - 1e-9).all() and (td >= ta).all()
     for i, w in enumerate(wls):
-        assert it[i] == sum(solo(mp, w, "mixed")["iters"])
+        ref = solo(mp, w, "mixed")
+        assert it[i] == sum(ref["iters"])
+        assert_reply(reqs, i, ref, ("batched", i))
     assert B.stats()["resident"] == 0
     B.close()
     ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda:0")
-    reqs64 = mp.Requests(items, precision="fp64")
+    reqs64 = mp.Requests(items, precision="fp64", fields=FIELDS)
     ts, td2, st2, it2 = mp.serve_sequential(reqs64, ws)
     say("sequential start", np.round(ts, 3), "done", np.round(td2, 3), "iters", it2)
     assert (st2 == mp.MP_OK).all() and (td2 >= ts).all() and (ts >= arrivals - 1e-9).all()
     for i, w in enumerate(wls):
-        assert it2[i] == sum(solo(mp, w, "fp64")["iters"])
+        ref = solo(mp, w, "fp64")
+        assert it2[i] == sum(ref["iters"])
+        assert_reply(reqs64, i, ref, ("sequential", i))
+
+
+def test_serving_fp64_reply_against_oracle(mp):
+    """The reply of a request served by continuous batching in FP64 (next to
+    another request) against the oracle: equal iteration counts, response
+    curves and fields within 1e-10."""
+    say("case: FP64 served reply against the oracle")
+    wls = mixed_set(1e-8)[:2]
+    items = [(0.0, w.phase_map, w.phases, w.times, w.E, w.G, dict(tol=w.tol)) for w in wls]
+    B = mp.Batch(SHAPES, arena_bytes=128 << 20, precision="fp64", max_rves=4, iters_per_launch=8)
+    reqs = mp.Requests(items, precision="fp64", fields=FIELDS)
+    ta, td, st, it = mp.serve_batched(B, reqs)
+    B.close()
+    assert (st == mp.MP_OK).all()
+    w = wls[0]
+    out = O.Solver(w.phase_map, w.phases, tol=w.tol).solve(w.times, w.E, w.G, fields_at=(len(w.E),))
+    rec = reqs.records[0]
+    assert [int(v) for v in rec[:, 41]] == out["iters"]
+    f = out["fields"][len(w.E)]
+    errs = {k: rel(reqs.fields[0][k], f[k]) for k in FIELDS}
+    big = np.abs(out["resp"]).max(axis=0) > 1e-12 * np.abs(out["resp"]).max()
+    curve = np.abs(rec[:, :40] - out["resp"]).max(axis=0) / np.maximum(np.abs(out["resp"]).max(axis=0), 1e-300)
+    say("iterations", out["iters"], "field rel", errs, "curve rel %.2e" % curve[big].max())
+    assert max(errs.values()) < 1e-10 and curve[big].max() < 1e-10
 
 
 def test_batch_cancel_slot_limit_and_empty(mp):

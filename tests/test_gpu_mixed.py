@@ -1,24 +1,30 @@
-"""GPU parity of the mixed-precision form: FP32 spectra, strain, history base
-and FFT / Green / Alg. 1 arithmetic; FP64 error measure, averages and p, q.
+"""GPU parity of the mixed-precision form (MP_MIXED).
 
-The mixed form targets the strain-driven workloads (macroscopic curvature
-Gamma = 0, tolerance 1e-6).  Its FP32 return map leaves a few ulps of
-rounding in every converged field, so the local error measure (Eq. 38)
-bottoms out near a few 1e-8 * max|a| / |<a>|; a step then ends at that floor
-(no new smallest error for 100 iterations) and says so.
+FP32: the stored spectra, history base and committed stresses, and the
+arithmetic of the transforms and the Green operator.  FP64: the strain state,
+Alg. 1, the polarization, p and q, the error measure (Eqs. 36-38) and every
+volume average.  After a step's first iteration the transforms carry the
+polarization increment, so the rounding of the FP32 transforms shrinks with
+it and every step ends at the tolerance of Alg. 2, like FP64.
 
-Stated bound: relative error <= 1e-4 against FP64 on the same iteration
-schedule (the arithmetic error of the form), for every field,
-rel = max_x |a - a_ref| / max_x |a_ref|, and for every component of the
-homogenized response relative to the magnitude of the field it averages,
-|<a> - <a>_ref| / max(|<a>_ref|, max_x |a_ref|): the error of a volume
-average is bounded by the largest error of the field, so an average that is
-small against its field's fluctuation (the couple stress under pure strain
-loading, |<m>| ~ 6e-3 rms m) keeps only the field's absolute precision.
-The per-component relative error of the response is printed as well.  The
-gap to an FP64 run converged on its own schedule is printed: at tolerance
-1e-6 it is dominated by the convergence error eps / (1 - rho) of the slowly
-contracting iteration, not by precision.
+Stated bound: 1e-4 relative against FP64 converged on its own schedule at the
+same tolerance (the oracle on small grids, the FP64 GPU path on the 256^3
+cell):
+  - fields: rel = max_x |a - a_ref| / max_x |a_ref| (Frobenius norm over the
+    nine components of a tensor field);
+  - homogenized response, per component: max_n |<a>_n - <a>_ref,n| /
+    max_n |<a>_ref,n| for every column whose average reaches 1 % of its
+    field's scale F = max_x |a_ref|; a smaller average (zero by symmetry or
+    by the loading, or the couple stress under strain loading, |<m>| ~ 6e-3
+    rms m) is only as precise as its field, and its error is bounded by
+    1e-5 F instead.
+Every step must end with its error measure at or below the tolerance.
+
+What limits the precision: a transform of a whole field in FP32 rounds at
+about 6e-8 of the field, and the fixed point of the slowly contracting
+iteration moves by that rounding times 1 / (1 - rho) (about 40 on these
+cells): fields land a few 1e-6 from FP64 (measured on fixed schedules:
+1e-7 after one iteration, 2e-6 after 100).
 """
 import numpy as np
 import pytest
@@ -30,6 +36,10 @@ from tests.test_gpu_parity import long_axis_workload, rel, say, small_workload
 pytestmark = pytest.mark.gpu
 
 BOUND = 1e-4
+FIELDS = ("e", "g", "t", "m", "p", "q")
+# the response columns of each averaged field: <t>, <m>, <e>, <gamma>, <p>, <q>, <t_eq>, <m_eq>
+GROUPS = [(range(0, 9), "t"), (range(9, 18), "m"), (range(18, 27), "e"), (range(27, 36), "g"),
+          ([36], "p"), ([37], "q"), ([38], "t"), ([39], "m")]
 
 
 @pytest.fixture(scope="module")
@@ -41,99 +51,115 @@ def mp():
     return _mp
 
 
-def curve_rel(a, b):
-    big = np.abs(b).max(axis=0) > 1e-9 * np.abs(b).max()
-    return (np.abs(a - b).max(axis=0)[big] / np.abs(b).max(axis=0)[big]).max()
+def curve_rel(a, b, fields_ref):
+    """Response curves (n, 40) against the reference's (see the module doc):
+    the largest per-component relative error over the columns whose average
+    reaches 1 % of the field's scale, divided by 1e-4, and the largest error
+    of the other columns on the field's scale, divided by 1e-5 -- the worse
+    of the two, so that 1 is the bound."""
+    worst, col, big_rel, small_rel = 0.0, -1, 0.0, 0.0
+    for cols, name in GROUPS:
+        scale = np.abs(np.asarray(fields_ref[name], float)).max()
+        if scale == 0:
+            continue
+        for c in cols:
+            d = np.abs(a[:, c] - b[:, c]).max()
+            ref = np.abs(b[:, c]).max()
+            if ref >= 1e-2 * scale:
+                big_rel = max(big_rel, d / ref)
+                v = d / ref / 1e-4
+            else:
+                small_rel = max(small_rel, d / scale)
+                v = d / scale / 1e-5
+            if v > worst:
+                worst, col = v, c
+    say(f"  response: per-component rel {big_rel:.2e} (bound 1e-4), small averages "
+        f"{small_rel:.2e} of their field (bound 1e-5); worst column {col}")
+    return worst
 
 
-# field averaged by each of the 40 response columns: <t>, <m>, <e>, <gamma>,
-# <p>, <q>, <t_eq>, <m_eq>
-RESP_FIELD = ["t"] * 9 + ["m"] * 9 + ["e"] * 9 + ["g"] * 9 + ["p", "q", "t", "m"]
+def check_steps(plan, its, tol):
+    recs = plan.responses()
+    errs = recs[:, 40]
+    say("mixed iterations", its, "final error measure per step", np.array2string(errs, precision=2))
+    assert (errs <= tol).all(), errs
+    for s in range(1, len(its) + 1):
+        assert plan.error_parts(s)[4] == 0.0
+    return recs
 
 
-def field_scale(f, k):
-    return np.abs(np.asarray(f[k], float)).max()
+def iters_close(a, b):
+    """Per-step iteration counts within 10 % (plus 2) of the reference's."""
+    return all(abs(x - y) <= 2 + 0.1 * y for x, y in zip(a, b))
 
 
-def response_rel(a, b, fields_ref):
-    """max over columns of |a - b| / max(|b|, field scale) (see module doc)"""
-    den = np.maximum(np.abs(b).max(axis=0),
-                     np.array([field_scale(fields_ref, k) for k in RESP_FIELD]))
-    ok = den > 0
-    return (np.abs(a - b).max(axis=0)[ok] / den[ok]).max()
+def against_oracle(mp, wl):
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision="mixed")
+    it = plan.solve(wl.times, wl.E, wl.G)
+    recs = check_steps(plan, it, wl.tol)
+    ref = O.Solver(wl.phase_map, wl.phases, tol=wl.tol).solve(wl.times, wl.E, wl.G,
+                                                              fields_at=(len(wl.E),))
+    f = ref["fields"][len(wl.E)]
+    errs = {k: rel(plan.field(k), f[k]) for k in FIELDS}
+    c = curve_rel(recs[:, :40], ref["resp"], f)
+    say("oracle iterations", ref["iters"], "field rel", {k: "%.1e" % v for k, v in errs.items()},
+        "curve measure %.2f of the bound" % c)
+    assert max(errs.values()) < BOUND and c < 1.0
+    assert iters_close(it, ref["iters"]), (it, ref["iters"])
 
 
 @pytest.mark.parametrize("n", [(16, 16, 16), (24, 12, 32)])
-def test_mixed_vs_oracle_same_schedule(mp, n):
-    say(f"case: mixed precision vs oracle on the mixed schedule, n={n}")
+def test_mixed_vs_oracle_converged(mp, n):
+    say(f"case: mixed precision vs the oracle, each converged on its own schedule, n={n}")
     wl = small_workload(n, seed=sum(n), contrast=10.0, steps=4, G_end=0.0)
     wl.tol = 1e-6
-    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision="mixed")
-    it = plan.solve(wl.times, wl.E, wl.G)
-    say("mixed iterations", it, "error parts / floor flag",
-        [np.round(plan.error_parts(s), 9).tolist() for s in range(1, len(it) + 1)])
-    ref = O.Solver(wl.phase_map, wl.phases, tol=wl.tol)
-    out = ref.solve(wl.times, wl.E, wl.G, schedule=it, fields_at=(len(wl.E),))
-    f = out["fields"][len(wl.E)]
-    errs = {k: rel(plan.field(k), f[k]) for k in ("e", "g", "t", "m", "p", "q")}
-    c = response_rel(plan.responses()[:, :40], out["resp"], f)
-    say("same schedule: field rel", errs, "response rel %.2e" % c,
-        "(per-component %.2e)" % curve_rel(plan.responses()[:, :40], out["resp"]))
-    assert max(errs.values()) < BOUND and c < BOUND
-    conv = O.Solver(wl.phase_map, wl.phases, tol=wl.tol).solve(wl.times, wl.E, wl.G,
-                                                              fields_at=(len(wl.E),))
-    fc = conv["fields"][len(wl.E)]
-    say("oracle converged on its own schedule", conv["iters"], "field rel (information)",
-        {k: "%.1e" % rel(plan.field(k), fc[k]) for k in ("e", "t", "m")},
-        "curve rel %.1e" % curve_rel(plan.responses()[:, :40], conv["resp"]))
+    against_oracle(mp, wl)
+
+
+def test_mixed_sphere_cell_with_curvature(mp):
+    """The 16^3 sphere cell under strain and curvature at tolerance 1e-8, a
+    tolerance the FP32 form could not reach by the direct update."""
+    say("case: mixed precision, 16^3 sphere cell, E11 and Gamma12, tol 1e-8")
+    wl = W.single_sphere_16()
+    wl.times, wl.E = wl.times[:5], wl.E[:4]
+    wl.G = np.zeros_like(wl.E)
+    wl.G[:, 1] = 0.2 * wl.E[:, 0]
+    against_oracle(mp, wl)
 
 
 @pytest.mark.parametrize("n", [(256, 6, 4), (4, 6, 256), (192, 4, 6), (6, 4, 192)])
 def test_mixed_long_axis_vs_oracle(mp, n):
-    """The FP32 x pass and z pass at 256 and 192 points (one-wide z tiles) on
-    thin cells: mixed precision against the oracle on the mixed schedule."""
-    say(f"case: mixed precision vs oracle on a long-axis cell, n={n}")
+    """The FP32 transforms at 256 and 192 points (x pass with one Alg. 1 level
+    per block, one-wide z tiles) on thin cells."""
+    say(f"case: mixed precision vs the oracle on a long-axis cell, n={n}")
     wl = long_axis_workload(n, seed=sum(n))
     wl.tol = 1e-6
-    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision="mixed")
-    it = plan.solve(wl.times, wl.E, wl.G)
-    ref = O.Solver(wl.phase_map, wl.phases, tol=wl.tol)
-    out = ref.solve(wl.times, wl.E, wl.G, schedule=it, fields_at=(len(wl.E),))
-    f = out["fields"][len(wl.E)]
-    errs = {k: rel(plan.field(k), f[k]) for k in ("e", "g", "t", "m", "p", "q")}
-    c = response_rel(plan.responses()[:, :40], out["resp"], f)
-    say("mixed iterations", it, "field rel", errs, "response rel %.2e" % c)
-    assert max(errs.values()) < BOUND and c < BOUND
+    against_oracle(mp, wl)
 
 
 def test_mixed_vs_fp64_gpu_256(mp):
-    """Full-size 256^3 cell (random spheres to volume fraction 0.25, contrast
-    10, tolerance 1e-6), first load step: mixed vs FP64 on the mixed
-    schedule, and the FP64 run converged on its own (printed)."""
-    say("case: 256^3 mixed vs FP64 GPU path, step 1")
-    wl = W.random_spheres_256(n_steps=1)
+    """The 256^3 cell (random spheres to volume fraction 0.25, contrast 10,
+    tolerance 1e-6), first two load steps: mixed against the FP64 GPU path,
+    each converged on its own schedule."""
+    say("case: 256^3 mixed vs FP64 GPU path, steps 1-2")
+    wl = W.random_spheres_256(n_steps=2)
     say("spheres", wl.info)
 
-    def run(prec, fixed=0):
-        say("  run", prec, "fixed", fixed)
+    def run(prec):
+        say("  run", prec)
         plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision=prec)
-        if fixed:
-            plan.set_fixed_iterations(fixed)
         it = plan.solve(wl.times, wl.E, wl.G)
-        out = (it, {k: plan.field(k) for k in ("e", "g", "t", "m", "p", "q")}, plan.responses(),
-               plan.error_parts(1))
-        plan.close()
+        out = (it, plan.fields(FIELDS), plan.responses(), plan)
         return out
 
     mix = run("mixed")
-    say("mixed iterations", mix[0], "error parts / floor", mix[3])
-    ref = run("fp64", fixed=mix[0][0])
-    errs = {k: rel(mix[1][k], ref[1][k]) for k in ("e", "t", "m", "p")}
-    c = response_rel(mix[2][:, :40], ref[2][:, :40], ref[1])
-    say("same schedule: field rel", errs, "response rel %.2e" % c,
-        "(per-component %.2e)" % curve_rel(mix[2][:, :40], ref[2][:, :40]))
-    assert max(errs.values()) < BOUND and c < BOUND
-    conv = run("fp64")
-    say("fp64 converged iterations", conv[0], "field rel (information)",
-        {k: "%.1e" % rel(mix[1][k], conv[1][k]) for k in ("e", "t", "m", "p")},
-        "curve rel %.1e" % curve_rel(mix[2][:, :40], conv[2][:, :40]))
+    check_steps(mix[3], mix[0], wl.tol)
+    mix[3].close()
+    ref = run("fp64")
+    ref[3].close()
+    errs = {k: rel(mix[1][k], ref[1][k]) for k in FIELDS}
+    c = curve_rel(mix[2][:, :40], ref[2][:, :40], ref[1])
+    say("fp64 iterations", ref[0], "field rel", {k: "%.1e" % v for k, v in errs.items()},
+        "curve measure %.2f of the bound" % c)
+    assert max(errs.values()) < BOUND and c < 1.0
+    assert iters_close(mix[0], ref[0]), (mix[0], ref[0])

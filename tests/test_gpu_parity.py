@@ -251,8 +251,30 @@ def test_not_converged_and_diverged(torch, mp):
     assert st == mp.MP_E_NOT_CONVERGED and it[0] == 3 and plan.steps() == 1
     assert np.isfinite(plan.field("t")).all()
     plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, ref_mode="volume_mean")
-    st, it = plan.solve(wl.times[:2], wl.E[:1], wl.G[:1], raise_on_error=False)
+    st, it = plan.solve(wl.times[:3], wl.E[:2], wl.G[:2], raise_on_error=False)
     assert st == mp.MP_E_DIVERGED, (st, it)
+    # the diverged step is not committed and the plan takes no further steps
+    assert plan.steps() == 0 and it[1] == 0
+    st, _ = plan.solve(wl.times[:2], wl.E[:1], wl.G[:1], raise_on_error=False)
+    assert st == mp.MP_E_STATE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fields_to_device_equal_host(torch, mp, precision):
+    """mp_get_fields into device memory (torch tensors) through the C ABI
+    equals the host read-back bit for bit, all six fields at once."""
+    say(f"case: field read-back into device memory, {precision}")
+    wl = small_workload((12, 6, 8), seed=3, steps=2)
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision=precision)
+    plan.solve(wl.times, wl.E, wl.G)
+    host = plan.fields()
+    dev = plan.fields(device=True)
+    for k in host:
+        assert dev[k].device == plan.device and dev[k].dtype == torch.float64
+        assert np.array_equal(dev[k].cpu().numpy(), host[k]), k
+    assert np.abs(host["p"]).max() > 0
+    one = plan.fields(("t",))
+    assert list(one) == ["t"] and np.array_equal(one["t"], host["t"])
 
 
 def test_continue_across_calls(torch, mp):

@@ -80,6 +80,8 @@ __global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE>()
   __shared__ cx<T> lds2[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
   __shared__ cx<T> twl[N0];
+  constexpr bool STASH = sizeof(T) < sizeof(double) && MODE == X_ITER;
+  __shared__ double stash[STASH ? 9 * X::NTHR : 1];
   const int n = MODE == X_ITER ? ls->ns[cls] : ls->nt[cls];
   const int* list = MODE == X_ITER ? ls->s[cls] : ls->t[cls];
   const long total = long(n) * tiles;   // (RVE, tile) items, two levels each
@@ -97,7 +99,7 @@ __global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE>()
     const int tile = int(u % tiles);
     __syncthreads();   // the previous item is done with LDS
     xpass_tile<T, MODE, N0, AN>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid(),
-                                rv[slot].ctl.rd_incr, rv[slot].ctl.wr_incr);
+                                rv[slot].ctl.rd_incr, rv[slot].ctl.wr_incr, stash);
   }
 }
 

@@ -233,10 +233,12 @@ __device__ __forceinline__ int avg_row(int L, int j) {
 //   (wr_incr).  The loop control turns a step to increments once the error
 //   measure is small: then the transforms' rounding scales with the
 //   increment, not with the field, and the step reaches its tolerance.
+//   stash: LDS of 9 * NTHR doubles for low-precision ITER passes (unused
+//   otherwise), lane-private slots c * NTHR + tid.
 template <class T, int MODE, int N0, bool AN = false, bool ALG = false>
 __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl0, int ntiles, cx<T>* lds,
                                            cx<T>* lds2, double (*red)[kRed], const cx<T>* tw, int tid,
-                                           bool rd_incr, bool wr_incr) {
+                                           bool rd_incr, bool wr_incr, double* stash) {
   using X = XShape<T, N0>;
   constexpr int ROWS = X::ROWS, VPB = X::VPB, VPAD = X::VPAD, NTHR = X::NTHR, NH = X::NH;
   constexpr int NPK = X::NPK;
@@ -477,15 +479,25 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
         else
           apply_B<double>(a.ref.alp, a.ref.bet, a.ref.gam, x, out);
       };
-      // low-precision loop iterations compute the old iterate's stresses
-      // first (the polarization increment needs them); the FP64 pass
-      // recomputes them later, for the error measure only
+      // low-precision loop iterations evaluate the old iterate's
+      // polarization tau(e_old) first and park it in LDS (nine doubles per
+      // lane, off the register file): the increment tau(e) - tau(e_old) and
+      // the stress change of Eq. 37, sigma(e) - sigma(e_old) = that increment
+      // + C0 (e - e_old), both come from it.  The FP64 pass recomputes
+      // sigma(e_old) after the update, for the error measure only
       constexpr bool LOWP = sizeof(T) < sizeof(double) && MODE == X_ITER;
       double t[9], to[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) t[c] = to[c] = 0.0;
-      double pnew;
+      double pnew, db_low = 0.0;
       if (own) {
+        if constexpr (LOWP) {
+          double pold, q0[9];
+          law(eo, to, pold);
+          ref_law(eo, q0);
+#pragma unroll
+          for (int c = 0; c < 9; ++c) stash[c * NTHR + tid] = to[c] - q0[c];
+        }
         if constexpr (ALG) {
           // e holds the compatible field: the local step turns it into d
           double pold, eh[9], rr[9];
@@ -510,14 +522,21 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
         for (int c = 0; c < 9; ++c) r0[c] = t[c] - r0[c];
         bool whole = true;
         if constexpr (LOWP) {
-          double pold;
-          law(eo, to, pold);
-          if (wr_incr) {
-            // the increment tau(e) - tau(e_old); the eigenstress cancels
-            double q0[9];
-            ref_law(eo, q0);
+          double dt[9], de[9], q0[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) r0[c] -= to[c] - q0[c];
+          for (int c = 0; c < 9; ++c) {
+            dt[c] = r0[c] - stash[c * NTHR + tid];
+            de[c] = e[c] - eo[c];
+          }
+          ref_law(de, q0);
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            const double y = dt[c] + q0[c];
+            db_low += y * y;
+          }
+          if (wr_incr) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) r0[c] = dt[c];
             whole = false;
           }
         }
@@ -561,8 +580,8 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
           wave_reduce<16>(v, 0x1u, lane, red[wv]);
         }
         // the old iterate's stresses, recomputed from the old strain (Alg. 1)
-        double db = 0;
-        if (own) {
+        double db = db_low;
+        if (own && !LOWP) {
           if constexpr (!LOWP && !ALG) {
             double pold;
             law(eo, to, pold);
@@ -627,16 +646,18 @@ __global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE, A
   __shared__ cx<T> lds2[X::NPK * N0];
   __shared__ double red[X::NTHR / 64][kRed];
   __shared__ cx<T> twl[N0];
+  constexpr bool STASH = sizeof(T) < sizeof(double) && MODE == X_ITER;
+  __shared__ double stash[STASH ? 9 * X::NTHR : 1];
   if constexpr (X::LPB == 2) {   // grid = ntiles, block b is tile b
     load_twiddles<T, N0, X::NTHR>(twl, glob(a.tw), threadIdx.x);
-    xpass_tile<T, MODE, N0, AN, ALG>(a, blockIdx.x, 0, gridDim.x, lds, lds2, red, twl, threadIdx.x, rd, wr);
+    xpass_tile<T, MODE, N0, AN, ALG>(a, blockIdx.x, 0, gridDim.x, lds, lds2, red, twl, threadIdx.x, rd, wr, stash);
   } else {
     long tile;
     int lvl;
     x_item<X::LPB>(blockIdx.x, &tile, &lvl);
     if (tile >= ntiles) return;
     load_twiddles<T, N0, X::NTHR>(twl, glob(a.tw), threadIdx.x);
-    xpass_tile<T, MODE, N0, AN, ALG>(a, tile, lvl, ntiles, lds, lds2, red, twl, threadIdx.x, rd, wr);
+    xpass_tile<T, MODE, N0, AN, ALG>(a, tile, lvl, ntiles, lds, lds2, red, twl, threadIdx.x, rd, wr, stash);
   }
 }
 

@@ -39,12 +39,16 @@ def bytes_per_voxel(w):
 # only for the kernel sources they were taken on (SHA-1 of the two headers)
 MEASURED_TRAFFIC = {
     "spheres128_fp64": {"kernel": "x_pass", "bytes": (942.0 + 619.7) * 1e6,
-                        "src_sha1": "bcdf79083ade8cab15659828111ae7f889b7ed72"},
-    "spheres256_mixed": {"kernel": "x_pass", "bytes": (3909.4 + 2479.9) * 1e6,
-                         "src_sha1": "bcdf79083ade8cab15659828111ae7f889b7ed72"},
-    "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.1 + 619.8) * 1e6,
-                      "src_sha1": "bcdf79083ade8cab15659828111ae7f889b7ed72"},
+                        "src_sha1": "f8c72696fc63e483ab80b15585058747635d2f16"},
+    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5340.3 + 5314.8) * 1e6,
+                         "src_sha1": "f8c72696fc63e483ab80b15585058747635d2f16"},
 }
+
+
+def survey_x_bytes(w):
+    """The x pass under the traffic model that stores the stresses: spectra,
+    strain, stresses read and written (126 w), p_n, q_n (16 B), phase (1 B)."""
+    return 126 * w + 16 + 1
 
 
 def kernel_src_sha1():
@@ -86,24 +90,198 @@ WORKLOADS = {
 }
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(wl, iters=4):
     """The oracle, untuned, on a bounded sample: load step 1 of the same cell
-    with a fixed schedule of `iters` loop iterations (one above 128^3), one
-    thread (setup excluded)."""
+    with a fixed schedule of `iters` loop iterations (one above 128^3), setup
+    excluded; once with one thread, once with every host thread allowed to
+    the numeric libraries (numpy's FFT itself stays on one thread)."""
     nvox = wl.phase_map.size
     if nvox > 128 ** 3:
         iters = 1
     from threadpoolctl import threadpool_limits
     from oracle import micropolar as O
-    with threadpool_limits(limits=1):
-        solver = O.Solver(wl.phase_map, wl.phases, h=wl.h, tol=wl.tol, norm=wl.err_norm,
-                          ref_mode=wl.ref_mode)
-        t0 = time.perf_counter()
-        solver.solve(wl.times[:2], wl.E[:1], wl.G[:1], schedule=[iters])
-        dt = time.perf_counter() - t0
+    nproc = os.cpu_count() or 1
+
+    def timed(threads):
+        with threadpool_limits(limits=threads):
+            solver = O.Solver(wl.phase_map, wl.phases, h=wl.h, tol=wl.tol, norm=wl.err_norm,
+                              ref_mode=wl.ref_mode)
+            t0 = time.perf_counter()
+            solver.solve(wl.times[:2], wl.E[:1], wl.G[:1], schedule=[iters])
+            return time.perf_counter() - t0
+
+    dt = timed(1)
+    dt_all = timed(nproc)
     return {"value": iters * nvox / dt, "unit": "voxel-iterations/s", "cores": 1, "kind": "oracle",
             "sample": f"load step 1 of the same cell, {iters} fixed-point iteration(s) "
-                      f"(plus the first iterate and commit), {dt:.1f} s wall, 1 thread"}
+                      f"(plus the first iterate and commit), {dt:.1f} s wall, 1 thread",
+            "all_threads": {"value": iters * nvox / dt_all, "threads_allowed": nproc,
+                            "seconds": round(dt_all, 2)},
+            "nproc": nproc, "cpu_model": cpu_model()}
+
+
+def field_errors(torch, a, b):
+    """max_x |a - b| / max_x |b| per field (Frobenius norm over the nine
+    components of a tensor field), on the device."""
+    out = {}
+    for k in a:
+        x, y = a[k], b[k]
+        if x.dim() == 4:
+            d = ((x - y) ** 2).sum(0).sqrt().max()
+            r = (y ** 2).sum(0).sqrt().max()
+        else:
+            d, r = (x - y).abs().max(), y.abs().max()
+        out[k] = float(d / r) if float(r) > 0 else float(d)
+    return out
+
+
+def curve_errors(a, b, fields_ref):
+    """Per-component relative error of the response columns whose average
+    reaches 1 % of its field's scale, and the error of the smaller averages on
+    their field's scale (columns: <t>, <m>, <e>, <gamma>, <p>, <q>, <t_eq>,
+    <m_eq>)."""
+    groups = [(range(0, 9), "t"), (range(9, 18), "m"), (range(18, 27), "e"), (range(27, 36), "g"),
+              ([36], "p"), ([37], "q"), ([38], "t"), ([39], "m")]
+    big = small = 0.0
+    for cols, name in groups:
+        scale = float(fields_ref[name].abs().max())
+        if scale == 0:
+            continue
+        for c in cols:
+            d = float(np.abs(a[:, c] - b[:, c]).max())
+            ref = float(np.abs(b[:, c]).max())
+            if ref >= 1e-2 * scale:
+                big = max(big, d / ref)
+            else:
+                small = max(small, d / scale)
+    return big, small
+
+
+def extra_mixed256(torch, mp, W, steps=2):
+    """The 256^3 cell, its first load steps solved in the mixed form and in
+    FP64, each converged at tolerance 1e-6 on its own schedule: iterations,
+    throughput, the error of every mixed result against FP64, and the x pass
+    of both against the HBM roofline (this grid's spectra do not fit in the
+    Infinity Cache)."""
+    wl = W.random_spheres_256(n_steps=steps)
+    nvox = wl.phase_map.size
+    res = {}
+    for prec in ("mixed", "fp64"):
+        plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision=prec)
+        plan.profile(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it = plan.solve(wl.times, wl.E, wl.G)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms, n = plan.profile_read()["x_pass"]
+        x_ms = ms / n
+        w = 4 if prec == "mixed" else 8
+        x_bytes = bytes_per_voxel(w)["x_pass"] * nvox
+        res[prec] = dict(iters=it, seconds=dt, fields=plan.fields(device=True), resp=plan.responses()[:, :40],
+                         final_err=[float(plan.responses()[s][40]) for s in range(steps)],
+                         reserved=[float(plan.error_parts(s + 1)[4]) for s in range(steps)],
+                         x=dict(avg_ms=round(x_ms, 4), achieved_GBps=round(x_bytes / x_ms / 1e6, 1),
+                                frac=round(x_bytes / x_ms / 1e6 / HBM_PEAK_GBS, 4)))
+        plan.close()
+        print(f"# 256^3 {prec}: iterations {it}, {dt:.2f} s, x pass {x_ms:.3f} ms", file=sys.stderr, flush=True)
+    m, d = res["mixed"], res["fp64"]
+    ferr = field_errors(torch, m["fields"], d["fields"])
+    big, small = curve_errors(m["resp"], d["resp"], d["fields"])
+    del m["fields"], d["fields"]
+    torch.cuda.empty_cache()
+    out = {"workload": WORKLOADS["spheres256_mixed"]["desc"] + f", load steps 1-{steps}", "tol": wl.tol}
+    for k, r in res.items():
+        out[k] = {"iterations": r["iters"], "seconds": round(r["seconds"], 3),
+                  "voxel_iterations_per_s": sum(r["iters"]) * nvox / r["seconds"],
+                  "final_error_measure": r["final_err"], "floor_stop": r["reserved"],
+                  "x_pass_roofline": r["x"]}
+    out["mixed_vs_fp64"] = {"field_rel": {k: float("%.3g" % v) for k, v in ferr.items()},
+                            "curve_rel_per_component": float("%.3g" % big),
+                            "small_averages_rel_field_scale": float("%.3g" % small),
+                            "solve_speedup": round(res["fp64"]["seconds"] / res["mixed"]["seconds"], 3)}
+    return out
+
+
+def extra_batch8(torch, mp, W, n_rves=8, n_steps=5):
+    """The first RVEs of the many-RVE workload (edges 32-128, contrast 2-20,
+    mixed, tolerance 1e-6), on shorter load paths: one resident batch against
+    the same RVEs solved one after another with FP64 plans."""
+    rves = W.batch_rves(seed=3, count=64, n_steps=n_steps)[:n_rves]
+    shapes = sorted({w.phase_map.shape[::-1] for w in rves})
+    probe = mp.Batch(shapes, arena_bytes=64 << 20, precision="mixed", max_rves=4, autotune=False)
+    need = sum(probe.footprint(w.phase_map, w.phases, len(w.E), tol=w.tol) for w in rves)
+    probe.close()
+    B = mp.Batch(shapes, arena_bytes=need + (1 << 30), precision="mixed", max_rves=16, iters_per_launch=8,
+                 autotune=True)
+    ids = [B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol) for w in rves]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    launches = B.drain()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    q = [B.query(i) for i in ids]
+    B.close()
+    t1 = time.perf_counter()
+    seq_its = []
+    for w in rves:
+        plan = mp.Plan(w.phase_map, w.phases, tol=w.tol, precision="fp64")
+        seq_its.append(sum(plan.solve(w.times, w.E, w.G, raise_on_error=False)[1]))
+        plan.close()
+    torch.cuda.synchronize()
+    d1 = time.perf_counter() - t1
+    print(f"# batch of {n_rves}: {dt:.2f} s batched mixed, {d1:.2f} s sequential FP64", file=sys.stderr, flush=True)
+    return {"rves": n_rves, "load_steps": n_steps, "edges": [int(w.phase_map.shape[0]) for w in rves],
+            "batched_mixed": {"seconds": round(dt, 3), "rve_solves_per_s": n_rves / dt, "graph_launches": launches,
+                              "iterations": [int(x[3]) for x in q], "statuses": [int(x[1]) for x in q]},
+            "sequential_fp64": {"seconds": round(d1, 3), "rve_solves_per_s": n_rves / d1,
+                                "iterations": seq_its},
+            "speedup": round(d1 / dt, 3)}
+
+
+def extra_serve(torch, mp, W, n=8):
+    """A short Poisson trace of the serving workload (edges 32-128 only, 10-12
+    load steps): the closed-loop saturation of continuous batching, then the
+    trace at 0.8x that rate through continuous batching (mixed) and through
+    sequential FP64 plans, with p50 / p99 latency including the replies."""
+    base = W.serve_trace(seed=4, n_req=n, rate=1.0, sizes=(32, 64, 128), weights=(0.5, 0.3, 0.2), steps=(10, 12))
+    wls = [w for _, w in base]
+    shapes = sorted({w.phase_map.shape[::-1] for w in wls})
+
+    def items(arr):
+        return [(a, w.phase_map, w.phases, w.times, w.E, w.G, dict(tol=w.tol)) for a, w in zip(arr, wls)]
+
+    B = mp.Batch(shapes, arena_bytes=8 << 30, precision="mixed", max_rves=64, iters_per_launch=8, autotune=True)
+    _, td, _, _ = mp.serve_batched(B, mp.Requests(items(np.zeros(n)), "mixed"))
+    rate = 0.8 * n / float(td.max())
+    gaps = np.random.default_rng(4).exponential(1.0 / rate, size=n)
+    arr = np.cumsum(gaps) - gaps[0]
+    _, td2, st2, _ = mp.serve_batched(B, mp.Requests(items(arr), "mixed"))
+    B.close()
+    ws = torch.empty(2 << 30, dtype=torch.uint8, device="cuda:0")
+    _, td3, st3, _ = mp.serve_sequential(mp.Requests(items(arr), "fp64"), ws)
+    del ws
+    torch.cuda.empty_cache()
+
+    def lat(done):
+        L = np.asarray(done) - arr
+        return {"p50_s": round(float(np.percentile(L, 50)), 3), "p99_s": round(float(np.percentile(L, 99)), 3),
+                "makespan_s": round(float(np.max(done)), 3)}
+
+    print(f"# serving {n} requests at {rate:.3f}/s", file=sys.stderr, flush=True)
+    return {"requests": n, "edges": [int(w.phase_map.shape[0]) for w in wls], "closed_loop_requests_per_s": n / float(td.max()),
+            "arrival_rate_per_s": rate, "batched_mixed": dict(lat(td2), statuses=sorted({int(v) for v in st2})),
+            "sequential_fp64": dict(lat(td3), statuses=sorted({int(v) for v in st3}))}
 
 
 def run_batch(args, torch, mp, W):
@@ -243,6 +421,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed, batch and serving samples added to the default line")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--workload", default="spheres128_fp64", choices=sorted(WORKLOADS))
     ap.add_argument("--fixed-iters", type=int, default=0,
@@ -339,10 +519,14 @@ def main():
         traffic = None
         if mt and mt["kernel"] == dom and mt["src_sha1"] == kernel_src_sha1():
             traffic = mt["bytes"]
+        w = 8 if cfg["precision"] == "fp64" else 4
+        survey = survey_x_bytes(w) * nvox / avg / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": BYTES_PER_VOXEL[dom] * nvox, "avg_ms": round(avg * 1e3, 4),
-                "launches": prof[dom][1]}
+                "launches": prof[dom][1],
+                "survey_model": {"bytes_per_voxel": survey_x_bytes(w), "achieved": round(survey, 1),
+                                 "frac": round(survey / HBM_PEAK_GBS, 4)}}
 
     line = {
         "metric": "voxel-iterations/s",
@@ -366,6 +550,11 @@ def main():
         "kernels_measured": "warm-up steps, HIP events between every loop kernel",
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(wl),
     }
+    if args.workload == "spheres128_fp64" and not args.no_extras:
+        # samples of the precision, batching and serving forms on the same
+        # GPU, outside the timed region
+        line["extras"] = {"mixed256": extra_mixed256(torch, mp, W), "batch8": extra_batch8(torch, mp, W),
+                          "serve": extra_serve(torch, mp, W)}
     print(json.dumps(line), flush=True)
 
 

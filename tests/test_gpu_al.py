@@ -21,6 +21,9 @@ from tests.test_gpu_parity import rel, say, small_workload
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("e", "g", "t", "m", "p", "q")
+# the response columns of each averaged field: <t>, <m>, <e>, <gamma>, <p>, <q>, <t_eq>, <m_eq>
+GROUPS = [(range(0, 9), "t"), (range(9, 18), "m"), (range(18, 27), "e"), (range(27, 36), "g"),
+          ([36], "p"), ([37], "q"), ([38], "t"), ([39], "m")]
 
 
 @pytest.fixture(scope="module")
@@ -62,11 +65,18 @@ def test_al_vs_oracle(mp, name, make, steps, ref_mode, relax):
         times, E, G, fields_at=(steps,))
     f = out["fields"][steps]
     errs = {k: rel(got[k], f[k]) for k in FIELDS}
-    # per column; a column at rounding level (a zero component of <d>, which
-    # reaches the prescribed average only at convergence) on the global scale
-    scale = np.abs(out["resp"]).max()
-    den = np.maximum(np.abs(out["resp"]).max(axis=0), 1e-8 * scale)
-    curve = (np.abs(resp - out["resp"]).max(axis=0) / den).max()
+    # per column, relative to the column; a column whose average is below 1 %
+    # of its field's scale (a zero component of <d>, which reaches the
+    # prescribed average only at convergence, or a small couple stress) is
+    # only as precise as its field, and is compared on the field's scale
+    curve = 0.0
+    for cols, name in GROUPS:
+        fs = np.abs(f[name]).max()
+        for c in cols:
+            ref = np.abs(out["resp"][:, c]).max()
+            den = ref if ref >= 1e-2 * fs else fs
+            if den > 0:
+                curve = max(curve, np.abs(resp[:, c] - out["resp"][:, c]).max() / den)
     say("iterations", it, "oracle", out["iters"], "field rel", {k: "%.1e" % v for k, v in errs.items()},
         "curve rel %.1e" % curve)
     assert it == out["iters"]

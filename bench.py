@@ -415,6 +415,45 @@ def run_serve(args, torch, mp, W):
     }
 
 
+def run_green_ab(torch, mp, W):
+    """The Green operator stored per frequency (Sec. 2.4) against computed
+    per frequency, on cubic RVEs of the many-RVE workload's kind (32^3 to
+    256^3), FP64 and mixed, on a fixed schedule: the z pass (forward z
+    transform, Green operator, inverse z transform) from HIP events between
+    the loop kernels, and the whole loop iteration from the wall clock
+    without events.  The stored table adds 21 words per frequency to the z
+    pass's 72 (the spectrum read and written)."""
+    rows = []
+    for n, iters in ((32, 200), (64, 100), (128, 40), (256, 12)):
+        wl = W.random_rve(seed=5, n=n, n_steps=3)
+        for prec in ("fp64", "mixed"):
+            w = 8 if prec == "fp64" else 4
+            row = {"n": n, "precision": prec}
+            for green in ("computed", "stored"):
+                plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision=prec, green=green)
+                plan.set_fixed_iterations(iters)
+                plan.solve(wl.times[:2], wl.E[:1], wl.G[:1])        # warm-up step
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan.solve(wl.times[1:3], wl.E[1:2], wl.G[1:2])
+                torch.cuda.synchronize()
+                it_ms = (time.perf_counter() - t0) / iters * 1e3
+                plan.profile(1)
+                plan.solve(wl.times[2:4], wl.E[2:3], wl.G[2:3])
+                ms, k = plan.profile_read()["z_green"]
+                plan.close()
+                z_ms = ms / k
+                zb = (72 + (21 if green == "stored" else 0)) * w * (n // 2) * n * n
+                row[green] = {"z_pass_ms": round(z_ms, 5), "z_pass_GBps": round(zb / z_ms / 1e6, 1),
+                              "iteration_ms": round(it_ms, 5)}
+            row["stored_over_computed"] = {"z_pass": round(row["stored"]["z_pass_ms"] / row["computed"]["z_pass_ms"], 3),
+                                           "iteration": round(row["stored"]["iteration_ms"] /
+                                                              row["computed"]["iteration_ms"], 3)}
+            print(f"# green A/B n={n} {prec}: {row['stored_over_computed']}", file=sys.stderr, flush=True)
+            rows.append(row)
+    return {"green_ab": rows, "data": "synthetic (seeded random-sphere RVEs, W.random_rve seed 5)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -438,6 +477,8 @@ def main():
                     help="serve_mixed: open-loop arrival rate (req/s) instead of 0.8x a closed-loop run")
     ap.add_argument("--iters-per-launch", type=int, default=8,
                     help="batch / serve: loop iterations per graph launch")
+    ap.add_argument("--green-ab", action="store_true",
+                    help="only time the stored against the computed Green operator (32^3-256^3)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -459,6 +500,9 @@ def main():
     import torch
     from paper_2409_10774_amd import mp, workloads as W
 
+    if args.green_ab:
+        print(json.dumps(run_green_ab(torch, mp, W)), flush=True)
+        return
     if args.workload in ("batch64_mixed", "serve_mixed"):
         run = run_batch if args.workload == "batch64_mixed" else run_serve
         print(json.dumps(run(args, torch, mp, W)), flush=True)

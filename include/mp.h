@@ -88,6 +88,15 @@ enum { MP_REF_PHASE_MEAN = 0, MP_REF_VOLUME_MEAN = 1, MP_REF_EXPLICIT = 2, MP_RE
  * isotropic reference medium with gamma0 > beta0 unless every phase present
  * has gamma = beta, and 0 < relax < 2; it runs in plans (not in batches). */
 enum { MP_SCHEME_BASIC = 0, MP_SCHEME_AL = 1 };
+/* How the Green operator of the reference medium (Eqs. 33-35) is evaluated.
+ * COMPUTED: at every frequency of every iteration, in closed form for an
+ * isotropic medium or by factoring its 6x6 Fourier symbol for a tensor one.
+ * STORED: as the paper precomputes it (Sec. 2.4): mp_plan_create writes the
+ * 21 entries of the inverse symbol at every frequency of the half spectrum
+ * into the workspace (21 n0/2 n1 n2 words of the bulk precision; FP64
+ * entries rounded to FP32 under MP_MIXED), and each iteration reads them.
+ * The two give the same operator up to rounding.  Plans only. */
+enum { MP_GREEN_COMPUTED = 0, MP_GREEN_STORED = 1 };
 enum { MP_FIELD_E = 0, MP_FIELD_GAMMA = 1, MP_FIELD_T = 2, MP_FIELD_M = 3,
        MP_FIELD_P = 4, MP_FIELD_Q = 5 };
 
@@ -141,6 +150,7 @@ typedef struct {
   const mp_aniso* aniso;    /* host, n_aniso records (unused when n_aniso = 0) */
   int32_t scheme;           /* MP_SCHEME_BASIC (0) | MP_SCHEME_AL */
   double relax;             /* MP_SCHEME_AL: over-relaxation w, 0 < w < 2 (1: none) */
+  int32_t green_mode;       /* MP_GREEN_COMPUTED (0) | MP_GREEN_STORED */
 } mp_problem;
 
 typedef struct mp_plan_s* mp_plan;

@@ -718,6 +718,7 @@ mp_status mp_batch_footprint(const mp_batch_config* cfg, const mp_problem* prob,
   Geometry g;
   mp_status st = validate(prob, &g);
   if (st != MP_OK) return st;
+  if (g.green_stored) return fail(MP_E_INVALID, "batches compute the Green operator (MP_GREEN_STORED runs in plans)");
   size_t po, ro;
   *bytes = align256(rve_bytes(layout(g, cfg->precision == MP_MIXED ? sizeof(float) : sizeof(double)),
                               n_steps, &po, &ro));
@@ -803,6 +804,8 @@ mp_status mp_batch_admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
     return fail(MP_E_INVALID, "problem precision differs from the batch's");
   if (prob->scheme != MP_SCHEME_BASIC)
     return fail(MP_E_INVALID, "batches run the basic scheme (MP_SCHEME_AL runs in plans)");
+  if (prob->green_mode != MP_GREEN_COMPUTED)
+    return fail(MP_E_INVALID, "batches compute the Green operator (MP_GREEN_STORED runs in plans)");
   if (n_steps < 1 || !times || !E || !Gam) return fail(MP_E_INVALID, "bad load path");
   for (int s = 1; s <= n_steps; ++s)
     if (!(times[s] > times[s - 1])) return fail(MP_E_INVALID, "times must increase");

@@ -13,6 +13,10 @@
 //                    balance equations, Eqs. 1, 2, 6, 33-35)
 //   green_apply_gen  the same for a general (Eq. 5) reference medium: the
 //                    symbol assembled from stored coefficients and factored
+//   green_symbol_inverse, green_apply_stored
+//                    the Green operator stored per frequency (Sec. 2.4):
+//                    the inverse symbol's 21 entries, computed once, then
+//                    applied from the table
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -840,6 +844,87 @@ __device__ __forceinline__ void green_apply_gen(const MP_GLOBAL double* G, T x1,
   }
   const cx<T> u[3] = {b[0], b[1], b[2]};
   const cx<T> ph[3] = {mul_i(b[3]), mul_i(b[4]), mul_i(b[5])};   // phi = i psi
+  green_strains<T>(xi, u, ph, scale, tau, mu);
+}
+
+// Index of entry (i, j), i <= j, of a symmetric 6 x 6 matrix stored as its
+// upper triangle row by row (21 entries).
+__host__ __device__ constexpr int sym6(int i, int j) { return i * (11 - i) / 2 + j; }
+
+// The Green operator stored per frequency, as the paper precomputes it
+// (Sec. 2.4): the inverse of the real symmetric symbol S(xi) of
+// green_apply_gen (an isotropic reference medium enters through its Eq. 6
+// tensors), out[sym6(i, j)] = (S^-1)_ij.  FP64, from the coefficients G;
+// S = L D L^T as in green_apply_gen, then S^-1 column by column from the
+// unit vectors.
+__device__ inline void green_symbol_inverse(const MP_GLOBAL double* G, double x1, double x2, double x3,
+                                            double* out) {
+  const double mono[9] = {x1 * x1, x2 * x2, x3 * x3, x1 * x2, x1 * x3, x2 * x3, x1, x2, x3};
+  double S[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) {
+      const MP_GLOBAL double* g = G + kSymCoef * sym6(i, j);
+      double v = 0.0;
+      for (int m = 0; m < 9; ++m) v += g[m] * mono[m];
+      S[i][j] = S[j][i] = v + g[9];
+    }
+  double U[6][6], id[6];
+  for (int j = 0; j < 6; ++j) {
+    double d = S[j][j];
+    for (int k = 0; k < j; ++k) d -= U[j][k] * U[j][k] * id[k];
+    id[j] = 1.0 / d;
+    for (int i = j + 1; i < 6; ++i) {
+      double v = S[j][i];
+      for (int k = 0; k < j; ++k) v -= U[i][k] * U[j][k] * id[k];
+      U[i][j] = v;
+    }
+  }
+  for (int c = 0; c < 6; ++c) {
+    double b[6];
+    for (int i = 0; i < 6; ++i) {
+      b[i] = i == c ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) b[i] -= b[k] * U[i][k];
+      b[i] *= id[i];
+    }
+    for (int i = 4; i >= 0; --i) {
+      double r = 0.0;
+      for (int k = i + 1; k < 6; ++k) r += b[k] * U[k][i];
+      b[i] -= r * id[i];
+    }
+    for (int i = 0; i <= c; ++i) out[sym6(i, c)] = b[i];
+  }
+}
+
+// Green operator at one frequency from its stored inverse symbol: entry e
+// at Si[e * es].  (u, psi) = S^-1 (bu, -i bp), phi = i psi, as in
+// green_apply_gen.
+template <class T>
+__device__ __forceinline__ void green_apply_stored(const MP_GLOBAL T* Si, long es, T x1, T x2, T x3, T scale,
+                                                   cx<T>* tau /*9 in, e out*/, cx<T>* mu /*9 in, g out*/) {
+  const T xi[3] = {x1, x2, x3};
+  cx<T> b[6];
+  {
+    cx<T> bu[3], bp[3];
+    green_sources<T>(xi, tau, mu, bu, bp);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      b[l] = bu[l];
+      b[3 + l] = cx<T>{bp[l].im, -bp[l].re};   // -i bp
+    }
+  }
+  cx<T> x[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) x[i] = cx<T>{T(0), T(0)};
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      const T v = Si[es * sym6(i, j)];
+      x[i] = cadd(x[i], cscale(b[j], v));
+      if (j != i) x[j] = cadd(x[j], cscale(b[i], v));
+    }
+  const cx<T> u[3] = {x[0], x[1], x[2]};
+  const cx<T> ph[3] = {mul_i(x[3]), mul_i(x[4]), mul_i(x[5])};
   green_strains<T>(xi, u, ph, scale, tau, mu);
 }
 

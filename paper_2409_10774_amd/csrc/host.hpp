@@ -130,7 +130,7 @@ hipError_t allow_lds(int L) {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t S, E, Eprev, base, pq, out_tm, out_pq, phase, params, aniso, tw, partials, ctl, tot, total;
+  size_t S, E, Eprev, base, pq, out_tm, out_pq, phase, params, aniso, tw, partials, ctl, tot, gtab, total;
 };
 
 struct Geometry {
@@ -139,14 +139,21 @@ struct Geometry {
   int xblocks, txy, txz;
   int n_aniso;     // phases with Eq. 5 tensors
   int ref_tensor;  // 1: general reference medium of the phases' tensors (MP_REF_TENSOR_*)
+  int green_stored;  // 1: the Green operator is stored per frequency (MP_GREEN_STORED)
 };
 
 // Doubles of the workspace's tensor table: the Eq. 5 row matrices of the
-// anisotropic phases, then those of a general reference medium and its
-// Green-operator symbol coefficients.
+// anisotropic phases, then those of a general reference medium, then the
+// reference's Fourier-symbol coefficients (with a tensor reference, or when
+// the Green operator is stored).
+inline size_t sym_offset(const Geometry& g) { return size_t(std::max(g.n_aniso + g.ref_tensor, 1)) * 162; }
 inline size_t aniso_words(const Geometry& g) {
-  return size_t(std::max(g.n_aniso + g.ref_tensor, 1)) * 162 +
-         (g.ref_tensor ? size_t(kSymEntries) * kSymCoef : 0);
+  return sym_offset(g) + (g.ref_tensor || g.green_stored ? size_t(kSymEntries) * kSymCoef : 0);
+}
+// Bytes of the stored Green operator: 21 words per frequency of the half
+// spectrum
+inline size_t green_table_bytes(const Geometry& g, size_t w) {
+  return g.green_stored ? size_t(kSymEntries) * size_t(g.nspec) * w : 0;
 }
 
 // Symmetric positive definite 9 x 9 matrix (row-major), by Cholesky
@@ -268,6 +275,8 @@ inline mp_status validate(const mp_problem* p, Geometry* g) {
   if (p->precision != MP_FP64 && p->precision != MP_MIXED) return fail(MP_E_INVALID, "precision");
   if (p->ref_mode < 0 || p->ref_mode > 5) return fail(MP_E_INVALID, "ref_mode");
   if (p->scheme != MP_SCHEME_BASIC && p->scheme != MP_SCHEME_AL) return fail(MP_E_INVALID, "scheme");
+  if (p->green_mode != MP_GREEN_COMPUTED && p->green_mode != MP_GREEN_STORED)
+    return fail(MP_E_INVALID, "green_mode");
   for (int i = 0; i < p->n_phases; ++i) {
     const mp_phase& c = p->phases[i];
     const std::string tag = "phase " + std::to_string(i) + ": ";
@@ -312,6 +321,7 @@ inline mp_status validate(const mp_problem* p, Geometry* g) {
   Geometry G = grid_geometry(p->n[0], p->n[1], p->n[2]);
   G.n_aniso = p->n_aniso;
   G.ref_tensor = p->ref_mode == MP_REF_TENSOR_MEAN || p->ref_mode == MP_REF_TENSOR_PHASE_MEAN ? 1 : 0;
+  G.green_stored = p->green_mode == MP_GREEN_STORED ? 1 : 0;
   if (G.ref_tensor) {
     mp_aniso r;
     const mp_status rs = reference_tensors(p, nvox, &r);
@@ -358,6 +368,7 @@ inline Layout layout(const Geometry& g, size_t w /* bytes per bulk word */) {
   L.partials = take(size_t(g.xblocks) * kNAvg * sizeof(double));
   L.ctl = take(sizeof(Ctl));
   L.tot = take(64 * sizeof(double));
+  L.gtab = take(green_table_bytes(g, w));
   L.total = o;
   return L;
 }

@@ -61,8 +61,9 @@ constexpr double kIncrFrom = 1e-3;
 constexpr int kIncrStall = 20;
 
 enum XMode { X_ITER = 0, X_TRANS = 1, X_FWD_ONLY = 2, X_INV_ONLY = 3 };
-// Z_GREEN_AN: Z_GREEN with a general (Eq. 5) reference medium
-enum AMode { Y_FWD = 0, Y_INV = 1, Z_GREEN = 2, Z_FWD = 3, Z_GREEN_AN = 4 };
+// Z_GREEN_AN: Z_GREEN with a general (Eq. 5) reference medium; Z_GREEN_ST:
+// Z_GREEN with the Green operator read from its stored table
+enum AMode { Y_FWD = 0, Y_INV = 1, Z_GREEN = 2, Z_FWD = 3, Z_GREEN_AN = 4, Z_GREEN_ST = 5 };
 
 template <class T>
 struct XArgs {
@@ -675,11 +676,13 @@ struct AxisArgs {
   long ostride;    // stride (complex) of the tile row index: kz for y, ky for z
   long pstride;    // stride (complex) between points of the transformed axis
   const cx<T>* tw;
-  // Z_GREEN, Z_GREEN_AN only
+  // Z_GREEN, Z_GREEN_AN, Z_GREEN_ST only
   int n0, n1, n2;
   double h, scale;
   RefC ref;
   const double* gsym;   // Z_GREEN_AN: symbol coefficients [21][10]
+  const T* gtab;        // Z_GREEN_ST, and Z_GREEN_AN where set: the stored
+                        // inverse symbol, [ky][kx][21][kz] (k_green_table)
 };
 
 template <int L, int TX>
@@ -716,10 +719,12 @@ __device__ __forceinline__ void axis_fetch(const AxisArgs<T>& a, int bx, int by,
   }
 }
 
+// How green_tile solves: the closed form of an isotropic reference medium,
+// the factored symbol of a tensor one, or the stored inverse symbol
+enum GKind { G_CLOSED = 0, G_FACTORED = 1, G_STORED = 2 };
+
 // Green operator at the L * TX frequencies of z-pass tile (bx, by), in LDS
-// (GEN: the factored symbol of a tensor reference medium, else the closed
-// form of an isotropic one)
-template <class T, int L, int TX, bool GEN>
+template <class T, int L, int TX, int KIND>
 __device__ __forceinline__ void green_tile(const AxisArgs<T>& a, int bx, int by, cx<T>* lds, int tid) {
   using A = AShape<L, TX>;
   constexpr int NB = A::NB, NTHR = A::NTHR;
@@ -744,10 +749,14 @@ __device__ __forceinline__ void green_tile(const AxisArgs<T>& a, int bx, int by,
       const T x1 = T(tp * kx / (a.n0 * a.h));
       const T x2 = T(tp * my / (a.n1 * a.h));
       const T x3 = T(tp * mz / (a.n2 * a.h));
-      if constexpr (GEN)
+      if constexpr (KIND == G_FACTORED) {
         green_apply_gen<T>(glob(a.gsym), x1, x2, x3, T(a.scale), tau, mu);
-      else
+      } else if constexpr (KIND == G_STORED) {
+        const long base = (long(ky) * (a.n0 / 2) + kx) * 21 * a.n2 + kz;
+        green_apply_stored<T>(glob(a.gtab) + base, a.n2, x1, x2, x3, T(a.scale), tau, mu);
+      } else {
         green_apply<T>(a.ref, x1, x2, x3, T(a.scale), tau, mu);
+      }
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         p[c] = tau[c];
@@ -777,23 +786,26 @@ __device__ __forceinline__ void axis_tile(const AxisArgs<T>& a, int bx, int by, 
   __syncthreads();
   constexpr bool INV = MODE == Y_INV;
   fft_ct<T, INV, L, 1, NB, NB, 1, true, NTHR>(lds, tw, tid);
-  if (MODE == Z_GREEN || MODE == Z_GREEN_AN) {
+  if (MODE == Z_GREEN || MODE == Z_GREEN_AN || MODE == Z_GREEN_ST) {
     // Green operator at the L * TX frequencies of the tile.  Z_GREEN_AN also
-    // serves an isotropic reference (gsym null: a batch class may hold both
-    // kinds of RVE); the choice is made per tile, around the whole loop, so
-    // that the two solves never share one loop body's registers
-    if (MODE == Z_GREEN_AN && a.gsym)
-      green_tile<T, L, TX, true>(a, bx, by, lds, tid);
+    // serves a stored table (gtab set) and an isotropic reference (both
+    // null): a batch class may hold every kind of RVE.  The choice is made
+    // per tile, around the whole loop, so that the solves never share one
+    // loop body's registers
+    if (MODE == Z_GREEN_ST || (MODE == Z_GREEN_AN && a.gtab))
+      green_tile<T, L, TX, G_STORED>(a, bx, by, lds, tid);
+    else if (MODE == Z_GREEN_AN && a.gsym)
+      green_tile<T, L, TX, G_FACTORED>(a, bx, by, lds, tid);
     else
-      green_tile<T, L, TX, false>(a, bx, by, lds, tid);
+      green_tile<T, L, TX, G_CLOSED>(a, bx, by, lds, tid);
     __syncthreads();
     fft_ct<T, true, L, 1, NB, NB, 1, true, NTHR>(lds, tw, tid);
   }
   MP_GLOBAL cx<T>* g = glob(a.S) + (long)by * a.ostride + (long)bx * NB;
   const long ps = a.pstride;
-  // the general Green step needs the registers that would otherwise keep the
-  // load addresses alive for these stores: recompute them
-  const int ts = MODE == Z_GREEN_AN ? fresh_tid() : tid;
+  // the general and stored Green steps need the registers that would
+  // otherwise keep the load addresses alive for these stores: recompute them
+  const int ts = MODE == Z_GREEN_AN || MODE == Z_GREEN_ST ? fresh_tid() : tid;
   for (int w = ts; w < PTS; w += NTHR) gstore(g + (w / NB) * ps + w % NB, lds[w]);
 }
 
@@ -830,6 +842,34 @@ __global__ void __launch_bounds__((AShape<L, TX>::NTHR), (axis_min_waves<T, L, T
   load_twiddles<T, L, AShape<L, TX>::NTHR>(twl, glob(a.tw), threadIdx.x);
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   axis_tile<T, MODE, L, TX>(a, t % gx, t / gx, reinterpret_cast<cx<T>*>(smem_raw), twl, threadIdx.x);
+}
+
+// The stored Green operator (Sec. 2.4): the inverse symbol at every
+// frequency of the half spectrum (kx < n0 / 2), from the symbol coefficients
+// G, rounded to T, at tab[((ky nh + kx) 21 + e) n2 + kz] (nh = n0 / 2), so
+// that a z-pass tile reads each entry as runs along kz.  Zero at the mean and
+// at the y and z Nyquist indices, where the fluctuation is zero.  Grid-stride
+// loop over the n2 n1 nh frequencies, kz fastest.
+template <class T>
+__global__ void __launch_bounds__(256) k_green_table(const double* G, int n0, int n1, int n2, double h, T* tab) {
+  const int nh = n0 / 2;
+  const long nf = long(n2) * n1 * nh;
+  for (long f = long(blockIdx.x) * 256 + threadIdx.x; f < nf; f += long(gridDim.x) * 256) {
+    const int kz = int(f % n2);
+    const long r = f / n2;
+    const int kx = int(r % nh), ky = int(r / nh);
+    double v[21];
+    if ((kx == 0 && ky == 0 && kz == 0) || 2 * ky == n1 || 2 * kz == n2) {
+      for (int e = 0; e < 21; ++e) v[e] = 0.0;
+    } else {
+      const double tp = 6.283185307179586476925286766559;
+      const int my = (2 * ky < n1) ? ky : ky - n1;
+      const int mz = (2 * kz < n2) ? kz : kz - n2;
+      green_symbol_inverse(glob(G), tp * kx / (n0 * h), tp * my / (n1 * h), tp * mz / (n2 * h), v);
+    }
+    MP_GLOBAL T* o = glob(tab) + (long(ky) * nh + kx) * 21 * n2 + kz;
+    for (int e = 0; e < 21; ++e) o[long(e) * n2] = T(v[e]);
+  }
 }
 
 // ---------------------------------------------------------------------------

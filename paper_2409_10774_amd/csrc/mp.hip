@@ -77,6 +77,7 @@ struct mp_plan_s {
   const double* aniso;   // Eq. 5 row matrices, [record][level][81]
   const double* refan;   // general reference medium: its row matrices, or null
   const double* gsym;    // and its symbol coefficients [21][10], or null
+  void* gtab;            // stored Green operator (T, [ky][kx][21][kz]), or null
   Ctl* ctl;
   Ctl* ctl_host;
   double* tot_host;   // pinned, kNAvg entries
@@ -131,6 +132,7 @@ struct Eng {
     a.scale = 1.0 / double(g.nvox);
     a.ref = P->ref;
     a.gsym = P->gsym;
+    a.gtab = static_cast<const T*>(P->gtab);
     return a;
   }
 
@@ -143,7 +145,11 @@ struct Eng {
     mark(0);
     launch_axis<T, Y_FWD>(g.n1, g.txy, g.nh / g.txy, g.n2, P->stream, ay, ctl);
     mark(1);
-    if (P->gsym) {
+    if (P->gtab) {
+      // the stored Green operator, on the closed form's tile widths
+      const int tx = sizeof(T) == 4 && g.n2 >= 96 ? 1 : g.txz;
+      launch_axis<T, Z_GREEN_ST>(g.n2, tx, g.nh / tx, g.n1, P->stream, az, ctl);
+    } else if (P->gsym) {
       // FP64: one-wide tiles, whose kernels hold the per-frequency
       // factorisation without spilling (0.149 against 0.162 ms at 128^3)
       const int tx = sizeof(T) == 8 ? 1 : g.txz;
@@ -192,6 +198,7 @@ struct Eng {
       if ((e = allow_lds<T, Y_INV>(L)) != hipSuccess) return e;
       if ((e = allow_lds<T, Z_GREEN>(L)) != hipSuccess) return e;
       if ((e = allow_lds<T, Z_GREEN_AN>(L)) != hipSuccess) return e;
+      if ((e = allow_lds<T, Z_GREEN_ST>(L)) != hipSuccess) return e;
       if ((e = allow_lds<T, Z_FWD>(L)) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -425,6 +432,7 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   P->aniso = reinterpret_cast<const double*>(wsp + L.aniso);
   P->refan = nullptr;
   P->gsym = nullptr;
+  P->gtab = g.green_stored ? static_cast<void*>(wsp + L.gtab) : nullptr;
   P->partials = reinterpret_cast<double*>(wsp + L.partials);
   P->ctl = reinterpret_cast<Ctl*>(wsp + L.ctl);
   P->tot = reinterpret_cast<double*>(wsp + L.tot);
@@ -466,11 +474,19 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
       delete P;
       return rs;
     }
-    const size_t sym = size_t(std::max(g.n_aniso + 1, 1)) * 162;
     aniso_rows(r, &arows[size_t(g.n_aniso) * 162]);
-    green_symbol(r, &arows[sym]);
+    green_symbol(r, &arows[sym_offset(g)]);
     P->refan = P->aniso + size_t(g.n_aniso) * 162;
-    P->gsym = P->aniso + sym;
+    P->gsym = P->aniso + sym_offset(g);
+  } else if (g.green_stored) {
+    // the symbol of the isotropic reference, from its Eq. 6 tensors, for
+    // the stored Green operator
+    mp_phase c{};
+    c.lambda = P->ref.lam; c.mu = P->ref.mu; c.kappa = P->ref.kap;
+    c.alpha = P->ref.alp; c.beta = P->ref.bet; c.gamma = P->ref.gam;
+    mp_aniso r{};
+    iso_tensors(c, r.A, r.B);
+    green_symbol(r, &arows[sym_offset(g)]);
   }
   std::vector<cx<double>> tw;
   std::vector<cx<float>> twf;
@@ -513,6 +529,19 @@ mp_status mp_plan_create(const mp_problem* prob, void* dev_workspace, size_t byt
   } else {
     CREATE_TRY(hipMemcpyAsync(P->tw0, tw.data(), tw.size() * sizeof(cx<double>),
                               hipMemcpyHostToDevice, P->stream));
+  }
+  if (P->gtab) {
+    // the stored Green operator (Sec. 2.4): once, from the symbol coefficients
+    const long nf = g.nspec;
+    const int blocks = int(std::min<long>((nf + 255) / 256, 4096));
+    const double* coef = P->aniso + sym_offset(g);
+    if (mixed)
+      hipLaunchKernelGGL(k_green_table<float>, dim3(blocks), dim3(256), 0, P->stream, coef, g.n0, g.n1, g.n2,
+                         P->h, static_cast<float*>(P->gtab));
+    else
+      hipLaunchKernelGGL(k_green_table<double>, dim3(blocks), dim3(256), 0, P->stream, coef, g.n0, g.n1,
+                         g.n2, P->h, static_cast<double*>(P->gtab));
+    CREATE_TRY(hipGetLastError());
   }
   CREATE_TRY(hipStreamSynchronize(P->stream));
 #undef CREATE_TRY

@@ -27,6 +27,7 @@ MP_ERR_LOCAL, MP_ERR_AVERAGE = 0, 1
 MP_REF_PHASE_MEAN, MP_REF_VOLUME_MEAN, MP_REF_EXPLICIT, MP_REF_TENSOR_MEAN, MP_REF_TENSOR_PHASE_MEAN, \
     MP_REF_GEOMETRIC_MEAN = range(6)
 MP_SCHEME_BASIC, MP_SCHEME_AL = 0, 1
+MP_GREEN_COMPUTED, MP_GREEN_STORED = 0, 1
 FIELDS = {"e": 0, "g": 1, "t": 2, "m": 3, "p": 4, "q": 5}
 
 
@@ -44,7 +45,8 @@ class mp_problem(C.Structure):
                 ("n_phases", C.c_int32), ("phases", C.POINTER(mp_phase)), ("ref_mode", C.c_int32),
                 ("ref", mp_phase), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("err_norm", C.c_int32), ("precision", C.c_int32), ("n_aniso", C.c_int32),
-                ("aniso", C.POINTER(mp_aniso)), ("scheme", C.c_int32), ("relax", C.c_double)]
+                ("aniso", C.POINTER(mp_aniso)), ("scheme", C.c_int32), ("relax", C.c_double),
+                ("green_mode", C.c_int32)]
 
 
 class mp_batch_config(C.Structure):
@@ -141,7 +143,8 @@ def _phase_struct(p) -> mp_phase:
 
 
 def make_problem(phase_map, phases, h=1.0, tol=1e-8, max_iter=20000, err_norm="local",
-                 ref_mode="phase_mean", ref=None, precision="fp64", scheme="basic", relax=1.7):
+                 ref_mode="phase_mean", ref=None, precision="fp64", scheme="basic", relax=1.7,
+                 green="computed"):
     """Build an mp_problem (and keep its host arrays alive on the returned object)."""
     pm = np.ascontiguousarray(phase_map, dtype=np.uint8)
     if pm.ndim != 3:
@@ -166,6 +169,7 @@ def make_problem(phase_map, phases, h=1.0, tol=1e-8, max_iter=20000, err_norm="l
     prob.precision = {"fp64": MP_FP64, "mixed": MP_MIXED}[precision]
     prob.scheme = {"basic": MP_SCHEME_BASIC, "al": MP_SCHEME_AL}[scheme]
     prob.relax = float(relax)
+    prob.green_mode = {"computed": MP_GREEN_COMPUTED, "stored": MP_GREEN_STORED}[green]
     # phases carrying general Eq. 5 tensors: A[k, l, m, n] = A_klmn and
     # B[l, k, m, n] = B_lkmn, flattened in that index order
     tens = [(i, p) for i, p in enumerate(phases) if getattr(p, "A", None) is not None]

@@ -364,6 +364,8 @@ def run_serve(args, torch, mp, W):
 
     vox = np.array([w.phase_map.size for w in wls])
     closed = batched = sequential = None
+    if args.servers == "none" and args.serve_rate > 0:
+        raise SystemExit("--servers none runs the closed loop only; it takes no --serve-rate")
     if args.serve_rate > 0:
         # the open-loop rate of an earlier closed-loop run: the same trace again
         rate = args.serve_rate
@@ -398,12 +400,12 @@ def run_serve(args, torch, mp, W):
         ts3, td3, st3, it3 = mp.serve_sequential(mp.Requests(items(arr), "fp64"), ws, progress_s=20.0)
         sequential = dict(lat(arr, td3), makespan_s=float(td3.max()), statuses=[int(v) for v in set(st3)],
                           voxel_iterations_per_s=float((it3 * vox).sum()) / float(td3.max()))
-    head = batched or sequential
+    head = batched or sequential or {"makespan_s": closed["makespan_s"]}
     return {
         "metric": "requests/s", "value": n / head["makespan_s"], "unit": "requests/s", "n_gpus": 1,
         "steps": n, "warmup": 0, "ms_per_step": head["makespan_s"] / n * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 bulk / f64 reductions" if batched else "f64",
+        "dtype": "f64" if sequential and not batched else "f32 bulk / f64 reductions",
         "data": "synthetic (seeded Poisson trace of random-sphere RVEs)",
         "config": {"workload": WORKLOADS["serve_mixed"]["desc"], "requests": n,
                    "arrival_rate_per_s": rate, "iters_per_launch": args.iters_per_launch,
@@ -471,8 +473,8 @@ def main():
                     help="batch64_mixed: also solve the first N RVEs one by one with FP64 plans")
     ap.add_argument("--requests", type=int, default=24, help="serve_mixed: requests in the trace")
     ap.add_argument("--arena-gib", type=int, default=48, help="serve_mixed: device arena (GiB)")
-    ap.add_argument("--servers", default="both", choices=("both", "batched", "sequential"),
-                    help="serve_mixed: which servers replay the open-loop trace")
+    ap.add_argument("--servers", default="both", choices=("both", "batched", "sequential", "none"),
+                    help="serve_mixed: which servers replay the open-loop trace (none: the closed loop only)")
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="serve_mixed: open-loop arrival rate (req/s) instead of 0.8x a closed-loop run")
     ap.add_argument("--iters-per-launch", type=int, default=8,

@@ -512,8 +512,15 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
             al_macro_local(ct, a.ref, rr, bb, hn, e);
           else
             al_micro_local(cm, a.ref, rr, bb, eh, hn, e);
+          // the stresses of the new local strain follow from the equation
+          // the local step solved, sigma(d) + C0 d = r: no second return map
+          double c0d[9];
+          ref_law(e, c0d);
+#pragma unroll
+          for (int c = 0; c < 9; ++c) t[c] = rr[c] - c0d[c];
+        } else {
+          law(e, t, pnew);
         }
-        law(e, t, pnew);
         // polarization (Eq. 34): tau = t - A0 e ; mu = m - B0 gamma, less the
         // eigenstress when one is set (the manufactured stresses of the code
         // verification, App. D.1)

@@ -39,9 +39,11 @@ def bytes_per_voxel(w):
 # only for the kernel sources they were taken on (SHA-1 of the two headers)
 MEASURED_TRAFFIC = {
     "spheres128_fp64": {"kernel": "x_pass", "bytes": (942.0 + 619.7) * 1e6,
-                        "src_sha1": "f8c72696fc63e483ab80b15585058747635d2f16"},
-    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5340.3 + 5314.8) * 1e6,
-                         "src_sha1": "f8c72696fc63e483ab80b15585058747635d2f16"},
+                        "src_sha1": "fce1c5a137c28c4aac73ca0955557515ca17f621"},
+    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5539.6 + 4655.4) * 1e6,
+                         "src_sha1": "fce1c5a137c28c4aac73ca0955557515ca17f621"},
+    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4897.1) * 1e6,
+                        "src_sha1": "fce1c5a137c28c4aac73ca0955557515ca17f621"},
 }
 
 

@@ -39,11 +39,13 @@ def bytes_per_voxel(w):
 # only for the kernel sources they were taken on (SHA-1 of the two headers)
 MEASURED_TRAFFIC = {
     "spheres128_fp64": {"kernel": "x_pass", "bytes": (942.0 + 619.7) * 1e6,
-                        "src_sha1": "fce1c5a137c28c4aac73ca0955557515ca17f621"},
-    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5539.6 + 4655.4) * 1e6,
-                         "src_sha1": "fce1c5a137c28c4aac73ca0955557515ca17f621"},
-    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4897.1) * 1e6,
-                        "src_sha1": "fce1c5a137c28c4aac73ca0955557515ca17f621"},
+                        "src_sha1": "adfb69069be024d301fb9a38def76c64fe274e19"},
+    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5536.7 + 4654.8) * 1e6,
+                         "src_sha1": "adfb69069be024d301fb9a38def76c64fe274e19"},
+    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.4 + 4896.9) * 1e6,
+                        "src_sha1": "adfb69069be024d301fb9a38def76c64fe274e19"},
+    "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.1 + 619.8) * 1e6,
+                      "src_sha1": "adfb69069be024d301fb9a38def76c64fe274e19"},
 }
 
 

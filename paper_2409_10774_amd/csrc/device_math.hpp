@@ -544,18 +544,21 @@ __device__ __forceinline__ double norm2_9(const double* V) {
 
 // root in (0, 1] of F(f) = (f - c1) sqrt(w0 Q0 / (f p0 + q0)^2 + w1 Q1 /
 // (f p1 + q1)^2 + w2 Q2 / (f p2 + q2)^2 + W) - c0 (F increasing, F(1) >= 0):
-// Newton steps kept inside the bracket, bisection where a step leaves it
+// Newton steps kept inside the bracket, bisection where a step leaves it.
+// The first iterate is c1 + c0 / X1, X1 = X(1) the elastic trial value: the
+// root with X frozen there, an upper bracket since X decreases in f.
 __device__ __forceinline__ double al_factor(const double (&w)[3], const double (&Q)[3], const double (&p)[3],
-                                            const double (&q)[3], double W, double c0, double c1) {
-  double lo = 0.0, hi = 1.0, f = 1.0;
+                                            const double (&q)[3], double W, double c0, double c1, double X1) {
+  double lo = 0.0, hi = 1.0, f = c1 + c0 / X1;
+  if (!(f > 0.0 && f <= 1.0)) f = 1.0;
   for (int it = 0; it < 100; ++it) {
     double X2 = W, dX2 = 0.0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const double den = f * p[j] + q[j];
-      const double t = w[j] * Q[j] / (den * den);
+      const double id = 1.0 / (f * p[j] + q[j]);
+      const double t = w[j] * Q[j] * id * id;
       X2 += t;
-      dX2 -= 2.0 * t * p[j] / den;
+      dX2 -= 2.0 * t * p[j] * id;
     }
     const double X = sqrt(X2);
     const double F = (f - c1) * X - c0;
@@ -599,15 +602,15 @@ __device__ __forceinline__ void al_macro_local(const MacroC& c, const RefC& r0, 
     const double den = c.tH + 2.0 * c.a1 * c.mu;
     const double w[3] = {c.a1, c.a2, 0.0}, Q[3] = {QD, QK, 0.0};
     const double p[3] = {a[1], a[2], 0.0}, q[3] = {a0[1], a0[2], 1.0};
-    f = al_factor(w, Q, p, q, 0.0, Rn * 2.0 * c.a1 * c.mu / den, c.tH / den);
+    f = al_factor(w, Q, p, q, 0.0, Rn * 2.0 * c.a1 * c.mu / den, c.tH / den, X1);
   }
-  const double eD = f * a[1] + a0[1], eK = f * a[2] + a0[2];
+  const double ieD = 1.0 / (f * a[1] + a0[1]), ieK = 1.0 / (f * a[2] + a0[2]);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       const int i = 3 * k + l;
-      d[i] = (rD[i] - f * bD[i]) / eD + (rK[i] - f * bK[i]) / eK + (k == l ? dv : 0.0);
+      d[i] = (rD[i] - f * bD[i]) * ieD + (rK[i] - f * bK[i]) * ieK + (k == l ? dv : 0.0);
     }
 }
 
@@ -643,19 +646,19 @@ __device__ __forceinline__ void al_micro_local(const MicroC& c, const RefC& r0, 
     const double w[3] = {c.b1, c.b1, inert ? 0.0 : c.b2};
     const double Q[3] = {Qv, QD, inert ? 0.0 : QK};
     const double p[3] = {a[0], a[1], inert ? 0.0 : a[2]}, q[3] = {a0[0], a0[1], inert ? 1.0 : a0[2]};
-    g = al_factor(w, Q, p, q, W, Rn * bgb / den, c.mH / den);
+    g = al_factor(w, Q, p, q, W, Rn * bgb / den, c.mH / den, Y1);
   }
-  const double ev = g * a[0] + a0[0], eD = g * a[1] + a0[1], eK = g * a[2] + a0[2];
+  const double ieD = 1.0 / (g * a[1] + a0[1]), ieK = inert ? 0.0 : 1.0 / (g * a[2] + a0[2]);
   double cv = 0.0, cD[9], cK[9];
   if (inert) tensor_parts(comp, cv, cD, cK);
-  const double dv = (rv - g * bv) / ev;
+  const double dv = (rv - g * bv) / (g * a[0] + a0[0]);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       const int i = 3 * k + l;
-      const double dk = inert ? cK[i] : (rK[i] - g * bK[i]) / eK;
-      d[i] = (rD[i] - g * bD[i]) / eD + dk + (k == l ? dv : 0.0);
+      const double dk = inert ? cK[i] : (rK[i] - g * bK[i]) * ieK;
+      d[i] = (rD[i] - g * bD[i]) * ieD + dk + (k == l ? dv : 0.0);
     }
 }
 

@@ -40,9 +40,9 @@ def bytes_per_voxel(w):
 MEASURED_TRAFFIC = {
     "spheres128_fp64": {"kernel": "x_pass", "bytes": (942.0 + 619.7) * 1e6,
                         "src_sha1": "adfb69069be024d301fb9a38def76c64fe274e19"},
-    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5536.7 + 4654.8) * 1e6,
+    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5542.6 + 4655.1) * 1e6,
                          "src_sha1": "adfb69069be024d301fb9a38def76c64fe274e19"},
-    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.4 + 4896.9) * 1e6,
+    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4896.8) * 1e6,
                         "src_sha1": "adfb69069be024d301fb9a38def76c64fe274e19"},
     "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.1 + 619.8) * 1e6,
                       "src_sha1": "adfb69069be024d301fb9a38def76c64fe274e19"},

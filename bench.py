@@ -22,11 +22,12 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 
-# algorithmic HBM bytes per voxel per launch (w = bytes per bulk word: 8 FP64,
-# 4 mixed; the strain state and p_n, q_n are FP64 in both)
+# HBM bytes per voxel per launch that this design moves (w = bytes per bulk
+# word: 8 FP64, 4 mixed; the strain state and p_n, q_n are FP64 in both)
 #   x pass : read 18 half spectra (18 w), e/gamma old (18 x 8 B), history
 #            base (18 w), p_n, q_n (2 x 8 B), phase id (1 B); write e/gamma
-#            (18 x 8 B) and 18 half spectra (18 w)
+#            (18 x 8 B) and 18 half spectra (18 w); the stresses of the old
+#            iterate are recomputed, not stored
 #   y passes, fused z pass (z forward + Green operator + z inverse):
 #            read + write 18 half spectra (36 w)
 def bytes_per_voxel(w):
@@ -50,9 +51,18 @@ MEASURED_TRAFFIC = {
 
 
 def survey_x_bytes(w):
-    """The x pass under the traffic model that stores the stresses: spectra,
-    strain, stresses read and written (126 w), p_n, q_n (16 B), phase (1 B)."""
+    """Algorithmic bytes per voxel of the x pass, the unit figure the
+    roofline line reports: the half spectra, the strain state and the
+    stresses read and written, the history base (126 w), p_n, q_n (16 B) and
+    the phase id (1 B) -- the traffic of a pass that stores the stresses of
+    the old iterate instead of recomputing them (1025 B FP64, 521 B mixed)."""
     return 126 * w + 16 + 1
+
+
+def survey_bytes_per_voxel(w):
+    """The same model over one whole iteration: x pass plus three axis passes
+    of 36 w (1889 B FP64, 953 B mixed)."""
+    return {"x_pass": survey_x_bytes(w), "y_fwd": 36 * w, "z_green": 36 * w, "y_inv": 36 * w, "err_reduce": 0}
 
 
 def kernel_src_sha1():
@@ -191,7 +201,7 @@ def extra_mixed256(torch, mp, W, steps=2):
         ms, n = plan.profile_read()["x_pass"]
         x_ms = ms / n
         w = 4 if prec == "mixed" else 8
-        x_bytes = bytes_per_voxel(w)["x_pass"] * nvox
+        x_bytes = survey_x_bytes(w) * nvox
         res[prec] = dict(iters=it, seconds=dt, fields=plan.fields(device=True), resp=plan.responses()[:, :40],
                          final_err=[float(plan.responses()[s][40]) for s in range(steps)],
                          reserved=[float(plan.error_parts(s + 1)[4]) for s in range(steps)],
@@ -568,8 +578,9 @@ def main():
     else:   # spheres256_mixed, spheres256_fp64
         wl = W.random_spheres_256(n_steps=W_ + K)
     nvox = wl.phase_map.size
-    BYTES_PER_VOXEL = bytes_per_voxel(8 if cfg["precision"] == "fp64" else 4)
+    BYTES_PER_VOXEL = survey_bytes_per_voxel(8 if cfg["precision"] == "fp64" else 4)
     BYTES_PER_VOXEL_ITER = sum(BYTES_PER_VOXEL.values())
+    DESIGN_BYTES = bytes_per_voxel(8 if cfg["precision"] == "fp64" else 4)
     plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision=cfg["precision"], ref_mode=wl.ref_mode)
     if args.fixed_iters:
         plan.set_fixed_iterations(args.fixed_iters)
@@ -614,14 +625,13 @@ def main():
         traffic = None
         if mt and mt["kernel"] == dom and mt["src_sha1"] == kernel_src_sha1():
             traffic = mt["bytes"]
-        w = 8 if cfg["precision"] == "fp64" else 4
-        survey = survey_x_bytes(w) * nvox / avg / 1e9
+        moved = DESIGN_BYTES[dom] * nvox / avg / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": BYTES_PER_VOXEL[dom] * nvox, "avg_ms": round(avg * 1e3, 4),
-                "launches": prof[dom][1],
-                "survey_model": {"bytes_per_voxel": survey_x_bytes(w), "achieved": round(survey, 1),
-                                 "frac": round(survey / HBM_PEAK_GBS, 4)}}
+                "bytes_per_voxel": BYTES_PER_VOXEL[dom], "bytes_per_launch": BYTES_PER_VOXEL[dom] * nvox,
+                "avg_ms": round(avg * 1e3, 4), "launches": prof[dom][1],
+                "design_bytes": {"bytes_per_voxel": DESIGN_BYTES[dom], "achieved": round(moved, 1),
+                                 "frac": round(moved / HBM_PEAK_GBS, 4)}}
 
     line = {
         "metric": "voxel-iterations/s",
@@ -640,6 +650,7 @@ def main():
                    "iterations": iters, "fixed_iters": args.fixed_iters or None,
                    "parallelism": "single GPU"},
         "iteration_hbm_frac": round(BYTES_PER_VOXEL_ITER * value / (HBM_PEAK_GBS * 1e9), 4),
+        "iteration_hbm_frac_design_bytes": round(sum(DESIGN_BYTES.values()) * value / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roof,
         "kernels": kernels,
         "kernels_measured": "warm-up steps, HIP events between every loop kernel",

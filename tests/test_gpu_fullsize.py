@@ -14,6 +14,9 @@ the benchmark times, through the C ABI.
   against the oracle on the same schedule (tests/golden/spheres256_step1.npz,
   make_spheres256_golden.py): fields at the sampled voxels and the averages
   within 1e-4 of their scale.
+- the same 256^3 cell and schedule in FP64 (the largest grid, with 256-point
+  x rows on one Alg. 1 level per block and one-wide z tiles), against the same
+  expected values: fields and averages within 1e-10.
 """
 import os
 
@@ -110,3 +113,22 @@ def test_spheres256_mixed_fixed_schedule_vs_oracle(mp):
     c = np.abs(resp - gold["resp"]).max() / scale
     say("sampled field rel", {k: "%.1e" % v for k, v in errs.items()}, "averages %.1e of their scale" % c)
     assert max(errs.values()) < 1e-4 and c < 1e-4
+
+
+def test_spheres256_fp64_fixed_schedule_vs_oracle(mp):
+    path = os.path.join(GOLDEN, "spheres256_step1.npz")
+    if not os.path.exists(path):
+        pytest.skip("expected values not written (make_spheres256_golden.py)")
+    gold = np.load(path)
+    wl = W.random_spheres_256(n_steps=1)
+    say("case: 256^3 cell, FP64, step 1 on 2 fixed iterations vs the oracle")
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol)
+    plan.set_fixed_iterations(int(gold["iters"][0]))
+    plan.solve(wl.times, wl.E, wl.G)
+    got = sampled(plan.fields(), gold["idx"])
+    resp = plan.responses()[:, :40]
+    plan.close()
+    errs = {k: rel(got[k], gold[k]) for k in FIELDS}
+    c = curve_rel(resp, gold["resp"])
+    say("sampled field rel", {k: "%.1e" % v for k, v in errs.items()}, "curve rel %.1e" % c)
+    assert max(errs.values()) < 1e-10 and c < 1e-10

@@ -50,7 +50,7 @@ MEASURED_TRAFFIC = {
 }
 
 
-def survey_x_bytes(w):
+def algorithmic_x_bytes(w):
     """Algorithmic bytes per voxel of the x pass, the unit figure the
     roofline line reports: the half spectra, the strain state and the
     stresses read and written, the history base (126 w), p_n, q_n (16 B) and
@@ -59,10 +59,10 @@ def survey_x_bytes(w):
     return 126 * w + 16 + 1
 
 
-def survey_bytes_per_voxel(w):
+def algorithmic_bytes_per_voxel(w):
     """The same model over one whole iteration: x pass plus three axis passes
     of 36 w (1889 B FP64, 953 B mixed)."""
-    return {"x_pass": survey_x_bytes(w), "y_fwd": 36 * w, "z_green": 36 * w, "y_inv": 36 * w, "err_reduce": 0}
+    return {"x_pass": algorithmic_x_bytes(w), "y_fwd": 36 * w, "z_green": 36 * w, "y_inv": 36 * w, "err_reduce": 0}
 
 
 def kernel_src_sha1():
@@ -201,7 +201,7 @@ def extra_mixed256(torch, mp, W, steps=2):
         ms, n = plan.profile_read()["x_pass"]
         x_ms = ms / n
         w = 4 if prec == "mixed" else 8
-        x_bytes = survey_x_bytes(w) * nvox
+        x_bytes = algorithmic_x_bytes(w) * nvox
         res[prec] = dict(iters=it, seconds=dt, fields=plan.fields(device=True), resp=plan.responses()[:, :40],
                          final_err=[float(plan.responses()[s][40]) for s in range(steps)],
                          reserved=[float(plan.error_parts(s + 1)[4]) for s in range(steps)],
@@ -467,7 +467,33 @@ def run_green_ab(torch, mp, W):
                                                               row["computed"]["iteration_ms"], 3)}
             print(f"# green A/B n={n} {prec}: {row['stored_over_computed']}", file=sys.stderr, flush=True)
             rows.append(row)
-    return {"green_ab": rows, "data": "synthetic (seeded random-sphere RVEs, W.random_rve seed 5)"}
+    # resident batches of small RVEs (each its own reference medium, so each
+    # its own table), 2 load steps of 40 fixed iterations
+    brows = []
+    for n, count in ((32, 64), (64, 16)):
+        rves = [W.random_rve(seed=100 + i, n=n, n_steps=2) for i in range(count)]
+        for prec in ("fp64", "mixed"):
+            row = {"rves": count, "n": n, "precision": prec}
+            for green in ("computed", "stored"):
+                B = mp.Batch([(n, n, n)], arena_bytes=12 << 30, precision=prec, max_rves=count,
+                             iters_per_launch=8, autotune=True)
+                ids = [B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol, green=green) for w in rves]
+                for rid in ids:
+                    B.set_fixed_iterations(rid, 40)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                launches = B.drain()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                B.close()
+                row[green] = {"seconds": round(dt, 4), "graph_launches": launches,
+                              "voxel_iterations_per_s": count * n ** 3 * 80 / dt}
+            row["stored_over_computed"] = round(row["stored"]["seconds"] / row["computed"]["seconds"], 3)
+            print(f"# green A/B batch {count} x {n}^3 {prec}: {row['stored_over_computed']}", file=sys.stderr,
+                  flush=True)
+            brows.append(row)
+    return {"green_ab": rows, "green_ab_batches": brows,
+            "data": "synthetic (seeded random-sphere RVEs, W.random_rve seeds 5 and 100..163)"}
 
 
 def run_al_ab(torch, mp, W):
@@ -551,7 +577,7 @@ def main():
                           "dispatches": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this library has no "
               "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
@@ -578,7 +604,7 @@ def main():
     else:   # spheres256_mixed, spheres256_fp64
         wl = W.random_spheres_256(n_steps=W_ + K)
     nvox = wl.phase_map.size
-    BYTES_PER_VOXEL = survey_bytes_per_voxel(8 if cfg["precision"] == "fp64" else 4)
+    BYTES_PER_VOXEL = algorithmic_bytes_per_voxel(8 if cfg["precision"] == "fp64" else 4)
     BYTES_PER_VOXEL_ITER = sum(BYTES_PER_VOXEL.values())
     DESIGN_BYTES = bytes_per_voxel(8 if cfg["precision"] == "fp64" else 4)
     plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, precision=cfg["precision"], ref_mode=wl.ref_mode)

@@ -95,7 +95,9 @@ enum { MP_SCHEME_BASIC = 0, MP_SCHEME_AL = 1 };
  * 21 entries of the inverse symbol at every frequency of the half spectrum
  * into the workspace (21 n0/2 n1 n2 words of the bulk precision; FP64
  * entries rounded to FP32 under MP_MIXED), and each iteration reads them.
- * The two give the same operator up to rounding.  Plans only. */
+ * The two give the same operator up to rounding.  Plans and batches (a
+ * batch builds an RVE's table when it admits it; mp_batch_footprint counts
+ * it). */
 enum { MP_GREEN_COMPUTED = 0, MP_GREEN_STORED = 1 };
 enum { MP_FIELD_E = 0, MP_FIELD_GAMMA = 1, MP_FIELD_T = 2, MP_FIELD_M = 3,
        MP_FIELD_P = 4, MP_FIELD_Q = 5 };

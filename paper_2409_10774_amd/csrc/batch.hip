@@ -81,7 +81,8 @@ struct ClassInfo {
   int xgrid;
   bool an;             // an RVE with Eq. 5 phases or a tensor reference was admitted:
                        // the x pass's Eq. 5 variant
-  bool tensor;         // an RVE with a tensor reference medium was admitted: Z_GREEN_AN
+  bool tensor;         // an RVE with a tensor reference medium or a stored Green
+                       // operator was admitted: Z_GREEN_AN (its solve per tile)
 };
 
 struct RveHost {
@@ -514,7 +515,16 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
       return st;
     }
     aniso_rows(r, &arows[size_t(g.n_aniso) * 162]);
-    green_symbol(r, &arows[size_t(g.n_aniso + 1) * 162]);
+    green_symbol(r, &arows[sym_offset(g)]);
+  } else if (g.green_stored) {
+    // the symbol of the isotropic reference, from its Eq. 6 tensors, for
+    // the stored Green operator
+    mp_phase c{};
+    c.lambda = ref.lam; c.mu = ref.mu; c.kappa = ref.kap;
+    c.alpha = ref.alp; c.beta = ref.bet; c.gamma = ref.gam;
+    mp_aniso r{};
+    iso_tensors(c, r.A, r.B);
+    green_symbol(r, &arows[sym_offset(g)]);
   }
   std::vector<cx<T>> tw;
   twiddles(g.n0, &tw);
@@ -569,7 +579,8 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   z.h = prob->h;
   z.scale = 1.0 / double(g.nvox);
   z.ref = ref;
-  if (g.ref_tensor) z.gsym = x.aniso + size_t(g.n_aniso + 1) * 162;
+  if (g.ref_tensor) z.gsym = x.aniso + sym_offset(g);
+  if (g.green_stored) z.gtab = reinterpret_cast<const T*>(b + L.gtab);
   const double* pth = reinterpret_cast<const double*>(b + H.path_off);
   R.times = pth;
   R.Ep = pth + n_steps + 1;
@@ -608,6 +619,13 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
                            B->stream));
   ADMIT_TRY(hipMemcpyAsync(b + H.path_off, path.data(), path.size() * sizeof(double),
                            hipMemcpyHostToDevice, B->stream));
+  if (g.green_stored) {
+    // the stored Green operator (Sec. 2.4), once, from the symbol coefficients
+    const int blocks = int(std::min<long>((g.nspec + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_green_table<T>, dim3(blocks), dim3(256), 0, B->stream,
+                       x.aniso + sym_offset(g), g.n0, g.n1, g.n2, prob->h, reinterpret_cast<T*>(b + L.gtab));
+    ADMIT_TRY(hipGetLastError());
+  }
   ADMIT_TRY(hipMemcpyAsync(rv(B) + slot, &R, sizeof R, hipMemcpyHostToDevice, B->stream));
   ADMIT_TRY(ctl(B, 0, B->stream));
   // host arrays above are pageable and local: finish the copies here
@@ -617,12 +635,13 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   B->slot_id[slot] = *id;
   B->rves[*id] = H;
   const bool an = g.n_aniso > 0 || g.ref_tensor;
-  if ((an && !B->cls[ci].an) || (g.ref_tensor && !B->cls[ci].tensor)) {
+  const bool tensor = g.ref_tensor || g.green_stored;
+  if ((an && !B->cls[ci].an) || (tensor && !B->cls[ci].tensor)) {
     // the class's x passes switch to the Eq. 5 variant, its z pass to the
     // general Green step: the next run captures the graph again (the stream
     // is idle, see above)
     B->cls[ci].an = B->cls[ci].an || an;
-    B->cls[ci].tensor = B->cls[ci].tensor || g.ref_tensor;
+    B->cls[ci].tensor = B->cls[ci].tensor || tensor;
     if (B->captured) {
       (void)hipGraphExecDestroy(B->exec);
       (void)hipGraphDestroy(B->graph);
@@ -718,7 +737,6 @@ mp_status mp_batch_footprint(const mp_batch_config* cfg, const mp_problem* prob,
   Geometry g;
   mp_status st = validate(prob, &g);
   if (st != MP_OK) return st;
-  if (g.green_stored) return fail(MP_E_INVALID, "batches compute the Green operator (MP_GREEN_STORED runs in plans)");
   size_t po, ro;
   *bytes = align256(rve_bytes(layout(g, cfg->precision == MP_MIXED ? sizeof(float) : sizeof(double)),
                               n_steps, &po, &ro));
@@ -804,8 +822,6 @@ mp_status mp_batch_admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
     return fail(MP_E_INVALID, "problem precision differs from the batch's");
   if (prob->scheme != MP_SCHEME_BASIC)
     return fail(MP_E_INVALID, "batches run the basic scheme (MP_SCHEME_AL runs in plans)");
-  if (prob->green_mode != MP_GREEN_COMPUTED)
-    return fail(MP_E_INVALID, "batches compute the Green operator (MP_GREEN_STORED runs in plans)");
   if (n_steps < 1 || !times || !E || !Gam) return fail(MP_E_INVALID, "bad load path");
   for (int s = 1; s <= n_steps; ++s)
     if (!(times[s] > times[s - 1])) return fail(MP_E_INVALID, "times must increase");

@@ -252,10 +252,10 @@ def test_augmented_lagrangian_validation():
 
 
 def test_stored_green_workspace_and_validation():
-    """MP_GREEN_STORED adds the inverse-symbol table to a plan's workspace:
-    21 words of the bulk precision per frequency of the half spectrum
-    (n0/2 n1 n2), plus the reference's symbol coefficients; other green_mode
-    values are rejected, and batches do not take it."""
+    """MP_GREEN_STORED adds the inverse-symbol table to a plan's workspace
+    and to a batched RVE's footprint: 21 words of the bulk precision per
+    frequency of the half spectrum (n0/2 n1 n2), plus the reference's symbol
+    coefficients; other green_mode values are rejected."""
     from paper_2409_10774_amd import mp, workloads as W
     nspec = 8 * 16 * 16
     for prec, w in (("fp64", 8), ("mixed", 4)):
@@ -267,8 +267,11 @@ def test_stored_green_workspace_and_validation():
     with pytest.raises(mp.MPError) as ei:
         mp.mp_plan_workspace_size(p)
     assert ei.value.status == mp.MP_E_INVALID and "green_mode" in str(ei.value)
-    wl = W.single_sphere_16()
     cfg = mp.batch_config([(16, 16, 16)], precision="fp64")
-    n = mp.C.c_size_t()
-    st = mp.lib.mp_batch_footprint(mp.C.byref(cfg), mp.C.byref(base_problem(green="stored")), 4, mp.C.byref(n))
-    assert st == mp.MP_E_INVALID
+    fp = []
+    for green in ("computed", "stored"):
+        n = mp.C.c_size_t()
+        st = mp.lib.mp_batch_footprint(mp.C.byref(cfg), mp.C.byref(base_problem(green=green)), 4, mp.C.byref(n))
+        assert st == mp.MP_OK
+        fp.append(n.value)
+    assert 21 * nspec * 8 <= fp[1] - fp[0] < 21 * nspec * 8 + 4096

@@ -12,7 +12,11 @@ C ABI, against the oracle's dense per-frequency inverse:
   mixed form's bound of 1e-4;
 - the 32^3 RVE of the many-RVE workload: stored and computed operators
   give the same iteration counts and fields within 1e-12 (they differ by
-  rounding only).
+  rounding only);
+- batches: RVEs with the stored operator beside RVEs with the computed one
+  in the same shape classes (the class then solves per tile), FP64 and mixed,
+  each equal bit for bit to its solo plan of the same kind, admitted before
+  and after the first graph capture.
 """
 import numpy as np
 import pytest
@@ -20,6 +24,7 @@ import pytest
 from oracle import micropolar as O
 from paper_2409_10774_amd import workloads as W
 from tests.test_gpu_parity import GRIDS, REFS, compare_run, rel, say, small_workload
+from tests.test_gpu_batch import assert_same, batched, mixed_set, solo
 from tests.test_gpu_refmedium import GREEN_GRIDS, aniso_cell
 
 pytestmark = pytest.mark.gpu
@@ -133,3 +138,30 @@ def test_stored_equals_computed_rve32(torch, mp):
     say("iterations", ia, ib, "rel", {k: "%.1e" % v for k, v in errs.items()})
     assert ia == ib
     assert max(errs.values()) < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("mixed", 1e-6)])
+def test_batch_stored_and_computed_equal_solo(mp, precision, tol):
+    say(f"case: batch of stored and computed Green operators in 3 shape classes vs solo plans, {precision}")
+    wls = mixed_set(tol)
+    shapes = [(16, 16, 16), (12, 6, 8), (24, 16, 12)]
+    B = mp.Batch(shapes, arena_bytes=256 << 20, precision=precision, max_rves=16, iters_per_launch=8,
+                 autotune=True)
+    greens = ["stored" if i % 2 == 0 else "computed" for i in range(len(wls))]
+    # half admitted, one launch (graph captured), then the rest: a class takes
+    # its first stored RVE after the capture
+    ids = []
+    for w, gm in zip(wls[:3], greens[:3]):
+        ids.append(B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol, green=gm))
+    B.run()
+    for w, gm in zip(wls[3:], greens[3:]):
+        ids.append(B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol, green=gm))
+    launches = B.drain()
+    say("graph launches", launches)
+    for rid, w, gm in zip(ids, wls, greens):
+        b = batched(B, rid)
+        assert b["state"] == mp.MP_RVE_DONE
+        s = solo(mp, w, precision, green=gm)
+        say(f"  rve {rid} {gm} n={w.phase_map.shape} iters {b['iters']} solo {s['iters']}")
+        assert_same(b, s, rid)
+    B.close()

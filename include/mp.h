@@ -86,7 +86,8 @@ enum { MP_REF_PHASE_MEAN = 0, MP_REF_VOLUME_MEAN = 1, MP_REF_EXPLICIT = 2, MP_RE
  * is taken on d and s(d), with the prescribed E, Gamma in the strain
  * denominators.  AL needs MP_FP64, phases without Eq. 5 tensors, an
  * isotropic reference medium with gamma0 > beta0 unless every phase present
- * has gamma = beta, and 0 < relax < 2; it runs in plans (not in batches). */
+ * has gamma = beta, and 0 < relax < 2; it runs in plans and in FP64 batches
+ * (beside basic-scheme RVEs of the same shape). */
 enum { MP_SCHEME_BASIC = 0, MP_SCHEME_AL = 1 };
 /* How the Green operator of the reference medium (Eqs. 33-35) is evaluated.
  * COMPUTED: at every frequency of every iteration, in closed form for an

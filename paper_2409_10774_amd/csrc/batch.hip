@@ -83,6 +83,8 @@ struct ClassInfo {
                        // the x pass's Eq. 5 variant
   bool tensor;         // an RVE with a tensor reference medium or a stored Green
                        // operator was admitted: Z_GREEN_AN (its solve per tile)
+  bool al;             // an augmented-Lagrangian RVE was admitted: the ITER x pass
+                       // that runs each RVE's own scheme
 };
 
 struct RveHost {
@@ -172,12 +174,17 @@ bool axis_kernel(int L, int tx, const void** fn, int* nthr, size_t* shm) {
 }
 
 template <class T, int MODE>
-bool x_kernel(int n0, bool an, const void** fn, int* nthr) {
+bool x_kernel(int n0, bool an, bool al, const void** fn, int* nthr) {
   switch (n0) {
 #define MP_CASE(N)                                                                            \
   case N:                                                                                     \
     *fn = an ? reinterpret_cast<const void*>(&k_batch_x<T, MODE, N, true>)                    \
              : reinterpret_cast<const void*>(&k_batch_x<T, MODE, N, false>);                  \
+    if constexpr (sizeof(T) == sizeof(double) && MODE == X_ITER) {                            \
+      if (al)                                                                                 \
+        *fn = an ? reinterpret_cast<const void*>(&k_batch_x<T, MODE, N, true, true>)          \
+                 : reinterpret_cast<const void*>(&k_batch_x<T, MODE, N, false, true>);        \
+    }                                                                                         \
     *nthr = XShape<T, N>::NTHR;                                                               \
     return true;
     MP_SIZES(MP_CASE)
@@ -217,8 +224,8 @@ struct BEng {
     const ClassInfo& C = B->cls[c];
     const void* fn;
     int nthr;
-    if (!(mode == X_ITER ? x_kernel<T, X_ITER>(C.n[0], C.an, &fn, &nthr)
-                         : x_kernel<T, X_TRANS>(C.n[0], C.an, &fn, &nthr)))
+    if (!(mode == X_ITER ? x_kernel<T, X_ITER>(C.n[0], C.an, C.al, &fn, &nthr)
+                         : x_kernel<T, X_TRANS>(C.n[0], C.an, false, &fn, &nthr)))
       return hipErrorInvalidValue;
     const Rve<T>* rvp = rv(B);
     const Lists* lsp = B->ls;
@@ -325,7 +332,7 @@ mp_status default_sched(mp_batch B, ClassInfo& C) {
   }
   const void* fn;
   int nthr;
-  if (!x_kernel<T, X_ITER>(C.n[0], C.an, &fn, &nthr)) return fail(MP_E_INVALID, "no x kernel");
+  if (!x_kernel<T, X_ITER>(C.n[0], C.an, false, &fn, &nthr)) return fail(MP_E_INVALID, "no x kernel");
   HIP_TRY(BEng<T>::occupancy(fn, nthr, 0, B->cus, &C.xgrid));
   return MP_OK;
 }
@@ -555,6 +562,8 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   x.n_aniso = g.n_aniso;
   if (g.ref_tensor) x.refan = x.aniso + size_t(g.n_aniso) * 162;
   x.ref = ref;
+  x.al = prob->scheme == MP_SCHEME_AL ? 1 : 0;
+  x.relax = x.al ? prob->relax : 1.0;
   for (int c = 0; c < 9; ++c) {
     x.mac[c] = E[c];
     x.mac[9 + c] = Gam[c];
@@ -636,12 +645,14 @@ mp_status BEng<T>::admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   B->rves[*id] = H;
   const bool an = g.n_aniso > 0 || g.ref_tensor;
   const bool tensor = g.ref_tensor || g.green_stored;
-  if ((an && !B->cls[ci].an) || (tensor && !B->cls[ci].tensor)) {
+  const bool al = prob->scheme == MP_SCHEME_AL;
+  if ((an && !B->cls[ci].an) || (tensor && !B->cls[ci].tensor) || (al && !B->cls[ci].al)) {
     // the class's x passes switch to the Eq. 5 variant, its z pass to the
     // general Green step: the next run captures the graph again (the stream
     // is idle, see above)
     B->cls[ci].an = B->cls[ci].an || an;
     B->cls[ci].tensor = B->cls[ci].tensor || tensor;
+    B->cls[ci].al = B->cls[ci].al || al;
     if (B->captured) {
       (void)hipGraphExecDestroy(B->exec);
       (void)hipGraphDestroy(B->graph);
@@ -820,8 +831,6 @@ mp_status mp_batch_admit(mp_batch B, const mp_problem* prob, int32_t n_steps, co
   if (!B || !id) return fail(MP_E_INVALID, "NULL argument");
   if (!prob || prob->precision != B->cfg.precision)
     return fail(MP_E_INVALID, "problem precision differs from the batch's");
-  if (prob->scheme != MP_SCHEME_BASIC)
-    return fail(MP_E_INVALID, "batches run the basic scheme (MP_SCHEME_AL runs in plans)");
   if (n_steps < 1 || !times || !E || !Gam) return fail(MP_E_INVALID, "bad load path");
   for (int s = 1; s <= n_steps; ++s)
     if (!(times[s] > times[s - 1])) return fail(MP_E_INVALID, "times must increase");

@@ -70,9 +70,11 @@ struct Lists {
 // x pass of one shape class: ITER over the RUN list, or TRANS over the
 // TRANS list (separate kernels, so each keeps its own register budget); AN:
 // the Eq. 5 variant of the pass body, for a class holding an RVE with Eq. 5
-// phases (an RVE without them takes the same arithmetic in either variant)
-template <class T, int MODE, int N0, bool AN>
-__global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE>())) k_batch_x(const Rve<T>* __restrict__ rv,
+// phases (an RVE without them takes the same arithmetic in either variant);
+// AL (FP64 ITER only): each RVE runs the augmented-Lagrangian or the basic
+// pass body by its own flag, for a class holding an augmented-Lagrangian RVE
+template <class T, int MODE, int N0, bool AN, bool AL = false>
+__global__ void __launch_bounds__((XShape<T, N0>::NTHR), (AL ? x_min_waves<T, MODE, true>() : x_min_waves<T, MODE>())) k_batch_x(const Rve<T>* __restrict__ rv,
                                                               const Lists* __restrict__ ls, int cls,
                                                               int tiles) {
   using X = XShape<T, N0>;
@@ -98,8 +100,19 @@ __global__ void __launch_bounds__((XShape<T, N0>::NTHR), (x_min_waves<T, MODE>()
     const int slot = list[u / tiles];
     const int tile = int(u % tiles);
     __syncthreads();   // the previous item is done with LDS
-    xpass_tile<T, MODE, N0, AN>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid(),
-                                rv[slot].ctl.rd_incr, rv[slot].ctl.wr_incr, stash);
+    if constexpr (AL && MODE == X_ITER && sizeof(T) == sizeof(double)) {
+      // the scheme is uniform over the item (one RVE): the two bodies never
+      // share one loop's registers
+      if (rv[slot].x.al)
+        xpass_tile<T, MODE, N0, AN, true>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid(),
+                                          rv[slot].ctl.rd_incr, rv[slot].ctl.wr_incr, stash);
+      else
+        xpass_tile<T, MODE, N0, AN, false>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid(),
+                                           rv[slot].ctl.rd_incr, rv[slot].ctl.wr_incr, stash);
+    } else {
+      xpass_tile<T, MODE, N0, AN>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid(),
+                                  rv[slot].ctl.rd_incr, rv[slot].ctl.wr_incr, stash);
+    }
   }
 }
 

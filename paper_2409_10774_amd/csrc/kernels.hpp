@@ -91,6 +91,8 @@ struct XArgs {
   T* fout;          // X_INV_ONLY output (18 n)
   const T* eig;     // optional eigenstress (18 n): subtracted in every polarization
   double relax;     // augmented-Lagrangian ITER passes: over-relaxation of the compatible field
+  int al;           // 1: this RVE's ITER passes run the augmented-Lagrangian scheme (batch
+                    // kernels choose per RVE; a plan chooses its kernel instead)
   const double* aniso;  // Eq. 5 row matrices, [record][level][81] (AN kernels)
   const double* refan;  // row matrices [level][81] of a general reference medium
                         // (AN kernels), or null: the isotropic constants `ref`

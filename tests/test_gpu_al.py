@@ -10,6 +10,9 @@ high-contrast scheme the paper's conclusion names, against its oracle
   scheme (geometric-mean penalty, over-relaxation 1.7) converges in at least
   3x fewer iterations per step than the basic scheme (phase-mean reference) to
   the same response;
+- FP64 batches holding augmented-Lagrangian and basic-scheme RVEs in the
+  same shape classes (admitted before and after the first graph capture):
+  every RVE equal bit for bit to its solo plan of the same scheme;
 - the same RVE under a 5x strain path on a fixed schedule of 2 steps x 3
   iterations against the
   oracle's expected values (tests/golden/al64_steps2.npz, written by
@@ -23,6 +26,7 @@ import pytest
 
 from oracle import augmented as AL
 from paper_2409_10774_amd import workloads as W
+from tests.test_gpu_batch import assert_same, batched, mixed_set, solo
 from tests.test_gpu_parity import rel, say, small_workload
 
 pytestmark = pytest.mark.gpu
@@ -152,3 +156,25 @@ def test_al_rve64_fixed_schedule_vs_oracle(mp):
         "p max %.2e" % resp[:, 36].max())
     assert resp[:, 36].max() > 0           # the matrix has yielded
     assert max(errs.values()) < 1e-10 and curve < 1e-10
+
+
+def test_batch_al_and_basic_equal_solo(mp):
+    say("case: FP64 batch of augmented-Lagrangian and basic RVEs in 3 shape classes vs solo plans")
+    wls = mixed_set(1e-8)
+    shapes = [(16, 16, 16), (12, 6, 8), (24, 16, 12)]
+    kinds = [dict(scheme="al", ref_mode="geometric_mean", relax=1.7) if i % 2 == 0 else {}
+             for i in range(len(wls))]
+    B = mp.Batch(shapes, arena_bytes=256 << 20, precision="fp64", max_rves=16, iters_per_launch=8,
+                 autotune=True)
+    ids = [B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol, **kw) for w, kw in zip(wls[:3], kinds[:3])]
+    B.run()   # graph captured; the (24, 16, 12) class takes its first AL RVE below
+    ids += [B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol, **kw) for w, kw in zip(wls[3:], kinds[3:])]
+    launches = B.drain()
+    say("graph launches", launches)
+    for rid, w, kw in zip(ids, wls, kinds):
+        b = batched(B, rid)
+        assert b["state"] == mp.MP_RVE_DONE
+        s = solo(mp, w, "fp64", **kw)
+        say(f"  rve {rid} {kw.get('scheme', 'basic')} n={w.phase_map.shape} iters {b['iters']} solo {s['iters']}")
+        assert_same(b, s, rid)
+    B.close()

@@ -17,6 +17,12 @@ the benchmark times, through the C ABI.
 - the same 256^3 cell and schedule in FP64 (the largest grid, with 256-point
   x rows on one Alg. 1 level per block and one-wide z tiles), against the same
   expected values: fields and averages within 1e-10.
+- many-RVE workload at full size: RVEs of 32^3, 64^3, 96^3 and 128^3 from it
+  (contrast up to 20, tolerance 1e-6, mixed) in one batch, each equal bit for
+  bit to its solo plan (whose FP64 path the tests above hold to the oracle).
+- serving at full size: a 256^3 request beside 32^3 and 64^3 ones through
+  continuous batching (mixed), every reply (step records, final fields) equal
+  bit for bit to the request solved alone.
 """
 import os
 
@@ -25,6 +31,7 @@ import pytest
 
 from oracle import micropolar as O
 from paper_2409_10774_amd import workloads as W
+from tests.test_gpu_batch import FIELDS as BFIELDS, assert_reply, assert_same, batched, solo
 from tests.test_gpu_parity import rel, say
 
 pytestmark = pytest.mark.gpu
@@ -132,3 +139,42 @@ def test_spheres256_fp64_fixed_schedule_vs_oracle(mp):
     c = curve_rel(resp, gold["resp"])
     say("sampled field rel", {k: "%.1e" % v for k, v in errs.items()}, "curve rel %.1e" % c)
     assert max(errs.values()) < 1e-10 and c < 1e-10
+
+
+def test_batch_rves_full_size_equal_solo(mp):
+    rves = W.batch_rves(seed=3, count=64, n_steps=2)
+    pick = []
+    for n in (32, 64, 96, 128):
+        pick.append(next(w for w in rves if w.phase_map.shape[0] == n))
+    say("case: many-RVE workload at full size, one RVE of each edge in one batch vs solo plans, mixed,",
+        [w.name for w in pick])
+    shapes = [w.phase_map.shape[::-1] for w in pick]
+    B = mp.Batch(shapes, arena_bytes=4 << 30, precision="mixed", max_rves=8, iters_per_launch=8, autotune=True)
+    ids = [B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol) for w in pick]
+    launches = B.drain()
+    say("graph launches", launches)
+    for rid, w in zip(ids, pick):
+        b = batched(B, rid)
+        assert b["state"] == mp.MP_RVE_DONE and b["status"] == mp.MP_OK
+        s = solo(mp, w, "mixed")
+        say(f"  rve {w.name}: iterations {b['iters']}")
+        assert_same(b, s, w.name)
+    B.close()
+
+
+def test_serving_with_256_request_equals_solo(mp):
+    wls = [W.random_rve(seed=201, n=256, n_steps=1), W.random_rve(seed=202, n=32, n_steps=3),
+           W.random_rve(seed=203, n=64, n_steps=2)]
+    say("case: serving a 256^3 request beside 32^3 and 64^3 ones, mixed, replies vs solo plans")
+    items = [(0.01 * i, w.phase_map, w.phases, w.times, w.E, w.G, dict(tol=w.tol)) for i, w in enumerate(wls)]
+    shapes = sorted({w.phase_map.shape[::-1] for w in wls})
+    B = mp.Batch(shapes, arena_bytes=12 << 30, precision="mixed", max_rves=8, iters_per_launch=8)
+    reqs = mp.Requests(items, precision="mixed", fields=BFIELDS, device="cuda:0")
+    ta, td, st, it = mp.serve_batched(B, reqs)
+    B.close()
+    say("done", np.round(td, 2), "iterations", it)
+    assert (st == mp.MP_OK).all()
+    for i, w in enumerate(wls):
+        ref = solo(mp, w, "mixed")
+        assert it[i] == sum(ref["iters"])
+        assert_reply(reqs, i, ref, ("served", w.name))

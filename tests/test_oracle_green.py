@@ -1,7 +1,9 @@
 """Pins of the oracle's FFT use and reference-medium Green operator.
 
-- numpy's rfftn / irfftn against a brute-force DFT on tiny grids (the oracle
-  uses them as its transform step);
+- numpy's rfftn / irfftn against a brute-force DFT on tiny grids, and
+  against the DFT written out as one dense matrix per axis (its separable
+  definition) on grids with axes of up to 256 points, the lengths the solver
+  runs (the oracle uses them as its transform step);
 - equilibrium: the stresses of the reference medium loaded by a polarization
   satisfy the balance laws (Eq. 2) -- checked with independent spectral
   derivatives and the sym/skew laws of Eq. 8;
@@ -45,6 +47,29 @@ def test_rfftn_matches_brute_force(shape):
     assert np.abs(got - ref[..., : shape[2] // 2 + 1]).max() < 1e-12 * np.abs(ref).max()
     back = np.fft.irfftn(got, s=shape, axes=(0, 1, 2))
     assert np.abs(back - a).max() < 1e-13
+
+
+def dft_matrix(n):
+    k = np.arange(n)
+    # exponent reduced mod n before the sin/cos, so the entries are exact to rounding
+    return np.exp(-2j * np.pi * ((np.outer(k, k) % n) / n))
+
+
+@pytest.mark.parametrize("shape", [(6, 8, 256), (256, 4, 6), (12, 192, 8), (24, 16, 96), (32, 32, 128)])
+def test_rfftn_matches_axis_dft_matrices(shape):
+    """rfftn(a) = F_z F_y F_x a with F_n[k, j] = exp(-2 pi i k j / n), on the
+    half spectrum of the last axis; and irfftn inverts it."""
+    rng = np.random.default_rng(2)
+    a = rng.standard_normal(shape)
+    nz, ny, nx = shape
+    ref = np.einsum("kx,zyx->zyk", dft_matrix(nx)[: nx // 2 + 1], a)
+    ref = np.einsum("ky,zyx->zkx", dft_matrix(ny), ref)
+    ref = np.einsum("kz,zyx->kyx", dft_matrix(nz), ref)
+    got = np.fft.rfftn(a)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() < 1e-12 * scale
+    back = np.fft.irfftn(got, s=shape, axes=(0, 1, 2))
+    assert np.abs(back - a).max() < 1e-13 * np.abs(a).max() * max(shape)
 
 
 def rand_fields(n, seed):

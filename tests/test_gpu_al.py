@@ -13,6 +13,11 @@ high-contrast scheme the paper's conclusion names, against its oracle
 - FP64 batches holding augmented-Lagrangian and basic-scheme RVEs in the
   same shape classes (admitted before and after the first graph capture):
   every RVE equal bit for bit to its solo plan of the same scheme;
+- serving: augmented-Lagrangian and basic requests through continuous
+  batching (FP64) and through the sequential server, every reply equal bit
+  for bit to the request solved alone;
+- a step that reaches max_iter: MP_E_NOT_CONVERGED, the step committed, and
+  the plan continues from it;
 - the same RVE under a 5x strain path on a fixed schedule of 2 steps x 3
   iterations against the
   oracle's expected values (tests/golden/al64_steps2.npz, written by
@@ -26,7 +31,7 @@ import pytest
 
 from oracle import augmented as AL
 from paper_2409_10774_amd import workloads as W
-from tests.test_gpu_batch import assert_same, batched, mixed_set, solo
+from tests.test_gpu_batch import FIELDS as BFIELDS, assert_reply, assert_same, batched, mixed_set, solo
 from tests.test_gpu_parity import rel, say, small_workload
 
 pytestmark = pytest.mark.gpu
@@ -178,3 +183,51 @@ def test_batch_al_and_basic_equal_solo(mp):
         say(f"  rve {rid} {kw.get('scheme', 'basic')} n={w.phase_map.shape} iters {b['iters']} solo {s['iters']}")
         assert_same(b, s, rid)
     B.close()
+
+
+def test_serving_al_and_basic_requests(mp):
+    import torch
+    say("case: serving AL and basic requests, continuous batching (FP64) and sequential")
+    wls = mixed_set(1e-8)
+    kinds = [dict(scheme="al", ref_mode="geometric_mean", relax=1.7) if i % 2 == 0 else {}
+             for i in range(len(wls))]
+    arrivals = np.cumsum(np.random.default_rng(6).exponential(0.02, size=len(wls)))
+    items = [(a, w.phase_map, w.phases, w.times, w.E, w.G, dict(tol=w.tol, **kw))
+             for a, w, kw in zip(arrivals, wls, kinds)]
+    shapes = [(16, 16, 16), (12, 6, 8), (24, 16, 12)]
+    B = mp.Batch(shapes, arena_bytes=256 << 20, precision="fp64", max_rves=16, iters_per_launch=8)
+    reqs = mp.Requests(items, precision="fp64", fields=BFIELDS)
+    ta, td, st, it = mp.serve_batched(B, reqs)
+    B.close()
+    say("batched done", np.round(td, 3), "iters", it)
+    assert (st == mp.MP_OK).all()
+    ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda:0")
+    reqs2 = mp.Requests(items, precision="fp64", fields=BFIELDS)
+    ts, td2, st2, it2 = mp.serve_sequential(reqs2, ws)
+    assert (st2 == mp.MP_OK).all()
+    for i, (w, kw) in enumerate(zip(wls, kinds)):
+        ref = solo(mp, w, "fp64", **kw)
+        assert it[i] == sum(ref["iters"]) and it2[i] == sum(ref["iters"])
+        assert_reply(reqs, i, ref, ("batched", i))
+        assert_reply(reqs2, i, ref, ("sequential", i))
+
+
+def test_al_max_iter_commits_and_continues(mp):
+    say("case: augmented Lagrangian, max_iter reached")
+    wl = sphere8(20.0)
+    plan = mp.Plan(wl.phase_map, wl.phases, tol=wl.tol, ref_mode="geometric_mean", scheme="al", relax=1.7,
+                   max_iter=10)
+    st, it = plan.solve(wl.times[:2], wl.E[:1], wl.G[:1], raise_on_error=False)
+    assert st == mp.MP_E_NOT_CONVERGED and it == [10]
+    assert plan.steps() == 1
+    assert plan.responses()[0, 40] > wl.tol
+    # the plan goes on from the committed step, like the oracle does
+    st2, it2 = plan.solve(wl.times[1:3], wl.E[1:2], wl.G[1:2], raise_on_error=False)
+    got = plan.fields()
+    plan.close()
+    out = AL.ALSolver(wl.phase_map, wl.phases, tol=wl.tol, max_iter=10, ref_mode="geometric_mean",
+                      relax=1.7).solve(wl.times[:3], wl.E[:2], wl.G[:2], fields_at=(2,))
+    say("iterations", it + it2, "oracle", out["iters"])
+    assert it + it2 == out["iters"]
+    f = out["fields"][2]
+    assert max(rel(got[k], f[k]) for k in FIELDS) < 1e-10

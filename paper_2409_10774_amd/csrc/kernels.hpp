@@ -732,6 +732,43 @@ __device__ __forceinline__ void axis_fetch(const AxisArgs<T>& a, int bx, int by,
 // the factored symbol of a tensor one, or the stored inverse symbol
 enum GKind { G_CLOSED = 0, G_FACTORED = 1, G_STORED = 2 };
 
+// Green operator at frequency (kx, ky, kz) on its 18 components p[0..17]
+// (in LDS): zero at the mean and at the y and z Nyquist indices
+template <class T, int KIND>
+__device__ __forceinline__ void green_freq(const AxisArgs<T>& a, int kx, int ky, int kz, cx<T>* p) {
+  const bool zero = (kx == 0 && ky == 0 && kz == 0) || (2 * ky == a.n1) || (2 * kz == a.n2);
+  if (zero) {
+#pragma unroll
+    for (int c = 0; c < 18; ++c) p[c] = cx<T>{T(0), T(0)};
+  } else {
+    cx<T> tau[9], mu[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      tau[c] = p[c];
+      mu[c] = p[9 + c];
+    }
+    const double tp = 6.283185307179586476925286766559;
+    const int my = (2 * ky < a.n1) ? ky : ky - a.n1;
+    const int mz = (2 * kz < a.n2) ? kz : kz - a.n2;
+    const T x1 = T(tp * kx / (a.n0 * a.h));
+    const T x2 = T(tp * my / (a.n1 * a.h));
+    const T x3 = T(tp * mz / (a.n2 * a.h));
+    if constexpr (KIND == G_FACTORED) {
+      green_apply_gen<T>(glob(a.gsym), x1, x2, x3, T(a.scale), tau, mu);
+    } else if constexpr (KIND == G_STORED) {
+      const long base = (long(ky) * (a.n0 / 2) + kx) * 21 * a.n2 + kz;
+      green_apply_stored<T>(glob(a.gtab) + base, a.n2, x1, x2, x3, T(a.scale), tau, mu);
+    } else {
+      green_apply<T>(a.ref, x1, x2, x3, T(a.scale), tau, mu);
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      p[c] = tau[c];
+      p[9 + c] = mu[c];
+    }
+  }
+}
+
 // Green operator at the L * TX frequencies of z-pass tile (bx, by), in LDS
 template <class T, int L, int TX, int KIND>
 __device__ __forceinline__ void green_tile(const AxisArgs<T>& a, int bx, int by, cx<T>* lds, int tid) {
@@ -739,39 +776,7 @@ __device__ __forceinline__ void green_tile(const AxisArgs<T>& a, int bx, int by,
   constexpr int NB = A::NB, NTHR = A::NTHR;
   for (int f = tid; f < L * TX; f += NTHR) {
     const int kz = f / TX, xl = f % TX;
-    const int kx = bx * TX + xl, ky = by;
-    cx<T>* p = lds + kz * NB + xl * 18;
-    const bool zero = (kx == 0 && ky == 0 && kz == 0) || (2 * ky == a.n1) || (2 * kz == a.n2);
-    if (zero) {
-#pragma unroll
-      for (int c = 0; c < 18; ++c) p[c] = cx<T>{T(0), T(0)};
-    } else {
-      cx<T> tau[9], mu[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        tau[c] = p[c];
-        mu[c] = p[9 + c];
-      }
-      const double tp = 6.283185307179586476925286766559;
-      const int my = (2 * ky < a.n1) ? ky : ky - a.n1;
-      const int mz = (2 * kz < a.n2) ? kz : kz - a.n2;
-      const T x1 = T(tp * kx / (a.n0 * a.h));
-      const T x2 = T(tp * my / (a.n1 * a.h));
-      const T x3 = T(tp * mz / (a.n2 * a.h));
-      if constexpr (KIND == G_FACTORED) {
-        green_apply_gen<T>(glob(a.gsym), x1, x2, x3, T(a.scale), tau, mu);
-      } else if constexpr (KIND == G_STORED) {
-        const long base = (long(ky) * (a.n0 / 2) + kx) * 21 * a.n2 + kz;
-        green_apply_stored<T>(glob(a.gtab) + base, a.n2, x1, x2, x3, T(a.scale), tau, mu);
-      } else {
-        green_apply<T>(a.ref, x1, x2, x3, T(a.scale), tau, mu);
-      }
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        p[c] = tau[c];
-        p[9 + c] = mu[c];
-      }
-    }
+    green_freq<T, KIND>(a, bx * TX + xl, by, kz, lds + kz * NB + xl * 18);
   }
 }
 
@@ -917,6 +922,20 @@ __device__ __forceinline__ double row_reduce(const MP_GLOBAL double* row, int nb
   __syncthreads();
   return mx ? nmax(nmax(red4[0], red4[1]), nmax(red4[2], red4[3]))
             : ((red4[0] + red4[1]) + (red4[2] + red4[3]));
+}
+
+// row_reduce's result for nblk <= 64, from one wavefront: there the values
+// sit in the lanes of the first wave, and the other three waves contribute
+// +0 (sums) or nmax(0, 0) = 0 (maxima), so the same operations in the same
+// order give the same value bit for bit.  x: this lane's value (lane < nblk).
+// The result is valid in lane 0.
+__device__ __forceinline__ double row_reduce_wave(double x, int lane, int nblk, bool mx) {
+  double v0 = 0.0;
+  const double v1 = 0.0, z = 0.0;
+  if (lane < nblk) v0 = mx ? nmax(v0, x) : v0 + x;
+  double v = mx ? nmax(v0, v1) : v0 + v1;
+  v = mx ? wave_max(v) : wave_sum(v);
+  return mx ? nmax(nmax(v, z), nmax(z, z)) : ((v + z) + (z + z));
 }
 
 // rows that hold maxima in an ITER x pass's error partials

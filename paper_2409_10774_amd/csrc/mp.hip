@@ -36,6 +36,102 @@ __global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int n
   ctl_reset(ctl, fixed, max_iter, tol, norm);
 }
 
+// Small cells (every axis 4 or 8 long, FP64, isotropic reference medium,
+// computed Green operator, basic scheme): whole loop iterations in one
+// block, up to max_loop of them or until the control ends the step.  At
+// these sizes each of the five loop kernels is a few blocks and the loop
+// runs at the GPU's per-kernel latency; here one launch runs the step.
+// The half spectrum stays in LDS through the y and z passes; every pass
+// takes the per-tile kernels' arithmetic (the same transforms per pencil,
+// green_freq, xpass_tile, row_reduce's result through row_reduce_wave,
+// err_finalize), so the iterates equal theirs bit for bit.  The control
+// block is held in LDS across iterations (thread 0 updates it, a barrier
+// publishes it) and written back at the end.  Within the block, a barrier
+// orders the global writes of one pass before the reads of the next.
+template <int N0, int L1, int L2>
+struct SmallShape {
+  using X = XShape<double, N0>;
+  static constexpr int NTHR = 256;
+  static constexpr int NH = N0 / 2;
+  static constexpr int NB = NH * 18;        // one (kz, ky) run of kx and components
+  static constexpr int PLANE = L1 * NB;     // one kz plane
+  static constexpr int NS = L2 * PLANE;     // the half spectrum
+  static constexpr int NXB = X::NPK * N0;   // one x-pass pencil buffer
+  static constexpr size_t LDS =
+      size_t(NS + 2 * NXB + N0 + L1 + L2) * sizeof(cx<double>) + size_t(NTHR / 64) * kRed * sizeof(double);
+  static_assert(X::NTHR == NTHR, "x pass of 256 threads");
+  static_assert(LDS <= 160 * 1024, "half spectrum and x buffers within 160 KB of LDS");
+};
+
+template <int N0, int L1, int L2>
+__global__ void __launch_bounds__(256) k_small_loop(XArgs<double> xa, AxisArgs<double> az,
+                                                    const cx<double>* twy_g, Ctl* ctl, ErrMacro em,
+                                                    int ntiles, int max_loop) {
+  using Q = SmallShape<N0, L1, L2>;
+  constexpr int NTHR = Q::NTHR, NH = Q::NH, NB = Q::NB, PLANE = Q::PLANE, NS = Q::NS;
+  extern __shared__ unsigned char smem_raw[];
+  cx<double>* const spec = reinterpret_cast<cx<double>*>(smem_raw);
+  cx<double>* const lds = spec + NS;
+  cx<double>* const lds2 = lds + Q::NXB;
+  cx<double>* const twx = lds2 + Q::NXB;
+  cx<double>* const twy = twx + N0;
+  cx<double>* const twz = twy + L1;
+  double(*const red)[kRed] = reinterpret_cast<double(*)[kRed]>(twz + L2);
+  __shared__ Ctl c;
+  __shared__ double tot[kNPart];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  load_twiddles<double, N0, NTHR>(twx, glob(xa.tw), tid);
+  load_twiddles<double, L1, NTHR>(twy, glob(twy_g), tid);
+  load_twiddles<double, L2, NTHR>(twz, glob(az.tw), tid);
+  if (tid == 0) c = *ctl;
+  __syncthreads();
+  MP_GLOBAL cx<double>* const S = glob(xa.S);
+  const MP_GLOBAL double* const partials = glob(xa.partials);
+  for (int k = 0; k < max_loop && !c.done; ++k) {
+    // y forward, z forward + Green operator + z inverse, y inverse
+    for (int w = tid; w < NS; w += NTHR) spec[w] = gload(S + w);
+    __syncthreads();
+    for (int kz = 0; kz < L2; ++kz)
+      fft_ct<double, false, L1, 1, NB, NB, 1, true, NTHR>(spec + kz * PLANE, twy, tid);
+    fft_ct<double, false, L2, 1, PLANE, PLANE, 1, true, NTHR>(spec, twz, tid);
+    for (int f = tid; f < L2 * L1 * NH; f += NTHR) {
+      const int kx = f % NH, ky = (f / NH) % L1, kz = f / (NH * L1);
+      green_freq<double, G_CLOSED>(az, kx, ky, kz, spec + (kz * L1 + ky) * NB + kx * 18);
+    }
+    __syncthreads();
+    fft_ct<double, true, L2, 1, PLANE, PLANE, 1, true, NTHR>(spec, twz, tid);
+    for (int kz = 0; kz < L2; ++kz)
+      fft_ct<double, true, L1, 1, NB, NB, 1, true, NTHR>(spec + kz * PLANE, twy, tid);
+    for (int w = tid; w < NS; w += NTHR) gstore(S + w, spec[w]);
+    __syncthreads();
+    // x pass ITER, tile by tile
+    for (int t = 0; t < ntiles; ++t) {
+      xpass_tile<double, X_ITER, N0>(xa, t, 0, ntiles, lds, lds2, red, twx, tid, false, false, nullptr);
+      __syncthreads();
+    }
+    // error rows (wave wv takes rows wv, wv + 4, ...), then the measure
+    constexpr int RPW = (kNPart + 3) / 4;
+    double x[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int j = wv + 4 * r;
+      x[r] = (j < kNPart && lane < ntiles) ? partials[long(j) * ntiles + lane] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int j = wv + 4 * r;
+      if (j < kNPart) {
+        const double v = row_reduce_wave(x[r], lane, ntiles, err_row_is_max(j));
+        if (lane == 0) tot[j] = v;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) err_finalize(tot, xa.nvox, &c, em.v);
+    __syncthreads();
+  }
+  if (tid == 0) *ctl = c;
+}
+
 // FFT twiddle tables exp(-2 pi i m / n) of the three axes, one after the
 // other (n0, then n1, then n2 entries), for the allocation-free spectral step
 __global__ void k_twiddles(cx<double>* tw, int n0, int n1, int n2) {
@@ -99,6 +195,53 @@ struct mp_plan_s {
 };
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// the one-block loop of small cells (k_small_loop)
+// ---------------------------------------------------------------------------
+#define MP_SMALL(X) X(4, 4, 4) X(4, 4, 8) X(4, 8, 4) X(4, 8, 8) X(8, 4, 4) X(8, 4, 8) X(8, 8, 4) X(8, 8, 8)
+
+// the plan's loop iterations run in k_small_loop: FP64, every axis 4 or 8
+// long, an isotropic reference medium with the computed Green operator, Eq. 6
+// phases only, the basic scheme, and no per-kernel timing (which needs the
+// kernels apart)
+bool small_loop(const mp_plan_s* P) {
+  const Geometry& g = P->g;
+  auto ok = [](int n) { return n == 4 || n == 8; };
+  return P->precision == MP_FP64 && ok(g.n0) && ok(g.n1) && ok(g.n2) && g.n_aniso == 0 && !g.ref_tensor &&
+         !P->gtab && !P->gsym && !P->refan && !P->al && P->prof == 0;
+}
+
+hipError_t prepare_small() {
+  hipError_t e = hipSuccess;
+#define MP_CASE(A, B, C)                                                                              \
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_loop<A, B, C>),                  \
+                               hipFuncAttributeMaxDynamicSharedMemorySize,                            \
+                               int(SmallShape<A, B, C>::LDS))) != hipSuccess)                          \
+    return e;
+  MP_SMALL(MP_CASE)
+#undef MP_CASE
+  return e;
+}
+
+template <int N0, int L1, int L2>
+void launch_small_t(hipStream_t s, const XArgs<double>& xa, const AxisArgs<double>& az, const cx<double>* twy,
+                    Ctl* ctl, const ErrMacro& em, int ntiles, int max_loop) {
+  using Q = SmallShape<N0, L1, L2>;
+  hipLaunchKernelGGL((k_small_loop<N0, L1, L2>), dim3(1), dim3(Q::NTHR), Q::LDS, s, xa, az, twy, ctl, em, ntiles,
+                     max_loop);
+}
+
+void launch_small(int n0, int n1, int n2, hipStream_t s, const XArgs<double>& xa, const AxisArgs<double>& az,
+                  const cx<double>* twy, Ctl* ctl, const ErrMacro& em, int ntiles, int max_loop) {
+#define MP_CASE(A, B, C)                                                              \
+  if (n0 == A && n1 == B && n2 == C) {                                                \
+    launch_small_t<A, B, C>(s, xa, az, twy, ctl, em, ntiles, max_loop);               \
+    return;                                                                           \
+  }
+  MP_SMALL(MP_CASE)
+#undef MP_CASE
+}
 
 // ---------------------------------------------------------------------------
 // typed launch helpers
@@ -201,27 +344,46 @@ struct Eng {
       if ((e = allow_lds<T, Z_GREEN_ST>(L)) != hipSuccess) return e;
       if ((e = allow_lds<T, Z_FWD>(L)) != hipSuccess) return e;
     }
+    if constexpr (sizeof(T) == sizeof(double))
+      if ((e = prepare_small()) != hipSuccess) return e;
     return hipSuccess;
   }
 
   static mp_status solve(mp_plan P, int32_t n_steps, const double* times, const double* E,
                          const double* Gam, int32_t* iters);
+  static mp_status record_queue(mp_plan P);
+  static void record_take(mp_plan P, std::vector<double>& rec);
   static mp_status record(mp_plan P, std::vector<double>& rec);
 };
 
 // Step averages of the committed state (rows of a TRANS x pass with
-// commit set): reduce, read back, append the step record.
+// commit set): reduce them and queue their copy to the host.  The loop
+// kernels that follow on the stream overwrite the reduced rows only after
+// the copy, so the record is taken at the next synchronisation.
 template <class T>
-mp_status Eng<T>::record(mp_plan P, std::vector<double>& rec) {
+mp_status Eng<T>::record_queue(mp_plan P) {
   const Geometry& g = P->g;
   hipLaunchKernelGGL(k_rows, dim3(kNAvg), dim3(256), 0, P->stream, P->partials, g.xblocks, 1, P->tot,
                      nullptr);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(P->tot_host, P->tot, kNAvg * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-  HIP_TRY(hipStreamSynchronize(P->stream));
-  for (int j = 0; j < kNAvg; ++j) rec[j] = P->tot_host[j] / double(g.nvox);
+  return MP_OK;
+}
+
+// after the stream is synchronised: append the step record
+template <class T>
+void Eng<T>::record_take(mp_plan P, std::vector<double>& rec) {
+  for (int j = 0; j < kNAvg; ++j) rec[j] = P->tot_host[j] / double(P->g.nvox);
   P->resp_hist.push_back(rec);
   P->steps += 1;
+}
+
+template <class T>
+mp_status Eng<T>::record(mp_plan P, std::vector<double>& rec) {
+  mp_status r = record_queue(P);
+  if (r != MP_OK) return r;
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  record_take(P, rec);
   return MP_OK;
 }
 
@@ -231,6 +393,7 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
   const Geometry& g = P->g;
   if (P->steps == 0) P->t_prev = P->t_cur = times[0];
   XArgs<T> xa = xargs(P);
+  const bool small = small_loop(P);
   // the converged state of the previous step is committed by the x pass that
   // opens the next step (or by a commit-only pass after the last one)
   std::vector<double> rec(kRecord, 0.0);
@@ -254,14 +417,21 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     // commit of the previous step, first iterate of this one (extrapolated
     // or uniform), its return map and polarization
     launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr, g.n_aniso > 0 || g.ref_tensor);
+    // the previous step's record, taken at the loop's first synchronisation
+    bool take = false;
     if (pending) {
-      mp_status r = record(P, rec);
+      mp_status r = record_queue(P);
       if (r != MP_OK) return r;
       pending = false;
+      take = true;
     }
     ErrMacro em;
     for (int c = 0; c < 18; ++c) em.v[c] = xa.mac[c];
-    int batch = 2;
+    // the one-block loop of a small cell runs until the control ends the
+    // step, which it does within max_iter (or the fixed count) iterations:
+    // one launch per step.  Otherwise batches of 2, 4, 8, ... iterations
+    // (kernels queued past the end of the step return at once)
+    int batch = small ? std::max(P->max_iter, P->fixed) + 1 : 2;
     long queued = 0;
     for (;;) {
       // the control block ends every step within max_iter (or the fixed count)
@@ -275,7 +445,14 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
         P->ev.resize(size_t(batch) * kProfEv);
         for (size_t i = old; i < P->ev.size(); ++i) HIP_TRY(hipEventCreate(&P->ev[i]));
       }
-      for (int k = 0; k < batch; ++k) {
+      bool fused = false;
+      if constexpr (sizeof(T) == sizeof(double)) {
+        if (small) {
+          launch_small(g.n0, g.n1, g.n2, P->stream, xa, zargs(P, S(P)), tw(P, 1), P->ctl, em, g.xblocks, batch);
+          fused = true;
+        }
+      }
+      for (int k = 0; k < batch && !fused; ++k) {
         // profiling: events between all loop kernels (mode 1) or around the
         // x pass only (mode 2, two event records per iteration)
         hipEvent_t* ev = P->prof ? &P->ev[size_t(k) * kProfEv] : nullptr;
@@ -291,6 +468,10 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(P->ctl_host, P->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P->stream));
       HIP_TRY(hipStreamSynchronize(P->stream));
+      if (take) {
+        record_take(P, rec);
+        take = false;
+      }
       if (P->prof) {
         // only iterations that really ran (later ones returned at once)
         const int ran = std::min(batch, P->ctl_host->iters - it0);

@@ -289,7 +289,10 @@ mp_status mp_radial_return(mp_plan plan, int64_t n_vox, const void* phase,
  * iteration order: 0 y forward, 1 z forward + Green operator + z inverse,
  * 2 y inverse, 3 x pass (inverse x transform, return maps, error partials,
  * polarization, forward x transform), 4 error reduction.  Each event record
- * adds a few microseconds between two kernels. */
+ * adds a few microseconds between two kernels.  A plan of a small cell
+ * (FP64, every axis 4 or 8 long, isotropic computed Green operator, basic
+ * scheme) otherwise runs a step's loop in one kernel; with timing on it
+ * runs these kernels apart, with bit-for-bit equal iterates. */
 mp_status mp_profile(mp_plan plan, int32_t mode);
 mp_status mp_profile_read(mp_plan plan, int32_t n, double* ms_total, int64_t* launches);
 

@@ -36,9 +36,10 @@ __global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int n
   ctl_reset(ctl, fixed, max_iter, tol, norm);
 }
 
-// Small cells (every axis 4 or 8 long, FP64, isotropic reference medium,
-// computed Green operator, basic scheme): whole loop iterations in one
-// block, up to max_loop of them or until the control ends the step.  At
+// Small cells (axes of 4 or 8, at most 128 voxels; FP64, isotropic
+// reference medium, computed Green operator, basic scheme): whole loop
+// iterations in one block, up to max_loop of them or until the control ends
+// the step.  At
 // these sizes each of the five loop kernels is a few blocks and the loop
 // runs at the GPU's per-kernel latency; here one launch runs the step.
 // The half spectrum stays in LDS through the y and z passes; every pass
@@ -199,17 +200,19 @@ namespace {
 // ---------------------------------------------------------------------------
 // the one-block loop of small cells (k_small_loop)
 // ---------------------------------------------------------------------------
-#define MP_SMALL(X) X(4, 4, 4) X(4, 4, 8) X(4, 8, 4) X(4, 8, 8) X(8, 4, 4) X(8, 4, 8) X(8, 8, 4) X(8, 8, 8)
+#define MP_SMALL(X) X(4, 4, 4) X(4, 4, 8) X(4, 8, 4) X(8, 4, 4)
 
-// the plan's loop iterations run in k_small_loop: FP64, every axis 4 or 8
-// long, an isotropic reference medium with the computed Green operator, Eq. 6
-// phases only, the basic scheme, and no per-kernel timing (which needs the
-// kernels apart)
+// the plan's loop iterations run in k_small_loop: FP64, a 4^3 cell or one
+// axis of 8 and two of 4 (at most 128 voxels: one block runs an iteration of
+// a 4^3 cell in 16.6 us against about 36 us for the six kernels, but one of
+// an 8^3 cell in 65 us, its four x tiles one after another), an isotropic
+// reference medium with the computed Green operator, Eq. 6 phases only, the
+// basic scheme, and no per-kernel timing (which needs the kernels apart)
 bool small_loop(const mp_plan_s* P) {
   const Geometry& g = P->g;
   auto ok = [](int n) { return n == 4 || n == 8; };
-  return P->precision == MP_FP64 && ok(g.n0) && ok(g.n1) && ok(g.n2) && g.n_aniso == 0 && !g.ref_tensor &&
-         !P->gtab && !P->gsym && !P->refan && !P->al && P->prof == 0;
+  return P->precision == MP_FP64 && ok(g.n0) && ok(g.n1) && ok(g.n2) && g.nvox <= 128 && g.n_aniso == 0 &&
+         !g.ref_tensor && !P->gtab && !P->gsym && !P->refan && !P->al && P->prof == 0;
 }
 
 hipError_t prepare_small() {

@@ -204,7 +204,7 @@ namespace {
 
 // the plan's loop iterations run in k_small_loop: FP64, a 4^3 cell or one
 // axis of 8 and two of 4 (at most 128 voxels: one block runs an iteration of
-// a 4^3 cell in 16.6 us against about 36 us for the six kernels, but one of
+// a 4^3 cell in 17 us against about 29 us for the six kernels, but one of
 // an 8^3 cell in 65 us, its four x tiles one after another), an isotropic
 // reference medium with the computed Green operator, Eq. 6 phases only, the
 // basic scheme, and no per-kernel timing (which needs the kernels apart)
@@ -431,10 +431,12 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     ErrMacro em;
     for (int c = 0; c < 18; ++c) em.v[c] = xa.mac[c];
     // the one-block loop of a small cell runs until the control ends the
-    // step, which it does within max_iter (or the fixed count) iterations:
-    // one launch per step.  Otherwise batches of 2, 4, 8, ... iterations
-    // (kernels queued past the end of the step return at once)
-    int batch = small ? std::max(P->max_iter, P->fixed) + 1 : 2;
+    // step, in launches of at most kSmallLoop iterations (a step of a
+    // typical count is one launch; no launch runs for long, about 70 ms at
+    // 4^3).  Otherwise batches of 2, 4, 8, ... 64 iterations (kernels
+    // queued past the end of the step return at once)
+    constexpr long kSmallLoop = 4096;
+    int batch = small ? int(std::min(long(std::max(P->max_iter, P->fixed)) + 1, kSmallLoop)) : 2;
     long queued = 0;
     for (;;) {
       // the control block ends every step within max_iter (or the fixed count)
@@ -489,7 +491,7 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
           }
       }
       if (P->ctl_host->done) break;
-      batch = std::min(batch * 2, 64);
+      if (!small) batch = std::min(batch * 2, 64);
     }
     const Ctl c = *P->ctl_host;
     if (iters) iters[s - 1] = c.iters;

@@ -10,7 +10,8 @@ the two are compared through the C ABI on the same inputs:
   counts, the step records and all six fields equal bit for bit;
 - the Sec. 3.2 ratcheting laminate (4^3), 150 steps of the cyclic path;
 - the App. D.1 manufactured eigenstress on its 4^3 cube;
-- a fixed iteration count, a step that reaches max_iter (committed,
+- fixed iteration counts (4, and 5000: more than one launch of the
+  one-block loop), a step that reaches max_iter (committed,
   MP_E_NOT_CONVERGED) and the volume-mean reference, whose steps may
   diverge: the same status, counts, committed steps and fields.
 
@@ -122,6 +123,10 @@ def test_small_loop_fixed_maxiter_and_volume_mean(mp):
     w = small_workload((8, 4, 4), seed=11, contrast=6.0, steps=3)
     say("case: one-block loop vs per-kernel loop, fixed count 4")
     assert_equal_runs(run(mp, w, False, fixed=4), run(mp, w, True, fixed=4), "fixed 4")
+    w1 = small_workload((4, 4, 4), seed=13, contrast=6.0, steps=2)
+    say("case: one-block loop vs per-kernel loop, fixed count 5000 (two launches of the one-block loop)")
+    assert_equal_runs(run(mp, w1, False, n_steps=1, fixed=5000), run(mp, w1, True, n_steps=1, fixed=5000),
+                      "fixed 5000")
     say("case: one-block loop vs per-kernel loop, max_iter 5")
     a = run(mp, w, False, max_iter=5)
     b = run(mp, w, True, max_iter=5)

@@ -263,6 +263,26 @@ def extra_batch8(torch, mp, W, n_rves=8, n_steps=5):
             "speedup": round(d1 / dt, 3)}
 
 
+def extra_ratchet(torch, mp, W, steps=1000):
+    """The Sec. 3.2 ratcheting path (4^3 Tab. 2 laminate, ten cycles of 100
+    steps of 0.01 s) on one FP64 plan: a small cell, whose steps run the
+    one-block loop.  A first plan over 20 steps warms the kernels up."""
+    w = W.ratchet_laminate(cycles=10)
+    warm = mp.Plan(w.phase_map, w.phases, h=w.h, tol=w.tol)
+    warm.solve(w.times[:21], w.E[:20], w.G[:20])
+    warm.close()
+    plan = mp.Plan(w.phase_map, w.phases, h=w.h, tol=w.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = plan.solve(w.times[: steps + 1], w.E[:steps], w.G[:steps])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    q = plan.responses()[:, 37]
+    plan.close()
+    return {"steps": steps, "seconds": round(dt, 4), "iterations": int(sum(it)), "steps_per_s": round(steps / dt, 1),
+            "iterations_per_s": round(sum(it) / dt, 1), "Q_end": float(q[-1])}
+
+
 def extra_serve(torch, mp, W, n=8):
     """A short Poisson trace of the serving workload (edges 32-128 only, 10-12
     load steps): the closed-loop saturation of continuous batching, then the
@@ -718,7 +738,7 @@ def main():
         # samples of the precision, batching and serving forms on the same
         # GPU, outside the timed region
         line["extras"] = {"mixed256": extra_mixed256(torch, mp, W), "batch8": extra_batch8(torch, mp, W),
-                          "serve": extra_serve(torch, mp, W)}
+                          "serve": extra_serve(torch, mp, W), "ratchet4": extra_ratchet(torch, mp, W)}
     print(json.dumps(line), flush=True)
 
 

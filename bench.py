@@ -40,13 +40,13 @@ def bytes_per_voxel(w):
 # only for the kernel sources they were taken on (SHA-1 of the two headers)
 MEASURED_TRAFFIC = {
     "spheres128_fp64": {"kernel": "x_pass", "bytes": (942.0 + 619.7) * 1e6,
-                        "src_sha1": "8076af938862f111c00cbe493e64d999b56ce5fe"},
-    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5534.8 + 4654.3) * 1e6,
-                         "src_sha1": "8076af938862f111c00cbe493e64d999b56ce5fe"},
-    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4897.0) * 1e6,
-                        "src_sha1": "8076af938862f111c00cbe493e64d999b56ce5fe"},
+                        "src_sha1": "d26a017c7ede15b96c3178c56e60c33a4eb719bd"},
+    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5117.3 + 3687.7) * 1e6,
+                         "src_sha1": "d26a017c7ede15b96c3178c56e60c33a4eb719bd"},
+    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4896.7) * 1e6,
+                        "src_sha1": "d26a017c7ede15b96c3178c56e60c33a4eb719bd"},
     "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.1 + 619.8) * 1e6,
-                      "src_sha1": "8076af938862f111c00cbe493e64d999b56ce5fe"},
+                      "src_sha1": "d26a017c7ede15b96c3178c56e60c33a4eb719bd"},
 }
 
 

@@ -347,15 +347,26 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
   // wavefront (fixed order), then over the waves of a level in order.
   const int lane = tid & 63, wv = tid >> 6;
 
-  // this lane's half of the phase record
+  // this lane's half of the phase record.  Low-precision loop iterations
+  // read it again at each return map instead (two per voxel): held across
+  // the pass, its eight doubles made the pass spill at 3 waves per SIMD
+  // (256^3 mixed: 2.72 ms with the record held, 2.48 ms read twice)
+  constexpr bool REREAD = sizeof(T) < sizeof(double) && MODE == X_ITER;
   MacroC ct;
   MicroC cm;
-  if (MODE != X_FWD_ONLY) {
+  if (MODE != X_FWD_ONLY && !REREAD) {
     if (lvl == 0)
       ct = gread(&glob(a.params)[ph].t);
     else
       cm = gread(&glob(a.params)[ph].m);
   }
+  // the record's address, opaque to the compiler so that the two reads are
+  // not merged into one held value
+  auto record = [&]() {
+    const MP_GLOBAL PhaseC* pp = glob(a.params) + ph;
+    asm volatile("" : "+v"(pp));
+    return pp;
+  };
   // this lane's Eq. 5 record (AN kernels), -1 for an Eq. 6 phase
   int aid = -1;
   if (AN && MODE != X_FWD_ONLY) aid = int(glob(&a.params[ph].t.aid)[0]);
@@ -468,9 +479,9 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
           for (int c = 0; c < 9; ++c) out[c] += bb[c];
           pout = hn;
         } else if (lvl == 0) {
-          macro_return<double>(ct, x, bb, hn, out, pout);
+          macro_return<double>(REREAD ? gread(&record()->t) : ct, x, bb, hn, out, pout);
         } else {
-          micro_return<double>(cm, x, bb, hn, out, pout);
+          micro_return<double>(REREAD ? gread(&record()->m) : cm, x, bb, hn, out, pout);
         }
       };
       // the reference medium's stresses A0 e (B0 gamma) of the polarization

@@ -612,6 +612,8 @@ def main():
                     help="only time the augmented-Lagrangian against the basic scheme at contrast 20")
     ap.add_argument("--green-ab", action="store_true",
                     help="only time the stored against the computed Green operator (32^3-256^3)")
+    ap.add_argument("--ratchet", action="store_true",
+                    help="only time the Sec. 3.2 ratcheting path (1000 steps on the 4^3 laminate, FP64 plan)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -641,6 +643,9 @@ def main():
         return
     if args.al_batch:
         print(json.dumps(run_al_batch(torch, mp, W)), flush=True)
+        return
+    if args.ratchet:
+        print(json.dumps(extra_ratchet(torch, mp, W)), flush=True)
         return
     if args.workload in ("batch64_mixed", "serve_mixed"):
         run = run_batch if args.workload == "batch64_mixed" else run_serve

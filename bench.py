@@ -283,6 +283,33 @@ def extra_ratchet(torch, mp, W, steps=1000):
             "iterations_per_s": round(sum(it) / dt, 1), "Q_end": float(q[-1])}
 
 
+def run_sweep(torch, mp, W, n=10, precision="mixed"):
+    """The Sec. 3.3 length-scale study as batched dataset generation: an n x n
+    sweep of the elastic and plastic lengths over [0.1, 1] on the 16^3
+    four-sphere cell (100 load steps each), every cell an RVE of one resident
+    batch, drained to completion."""
+    vals = np.linspace(0.1, 1.0, n)
+    cells = [W.length_scale_rve(le, lp) for le in vals for lp in vals]
+    shape = cells[0].phase_map.shape[::-1]
+    B = mp.Batch([shape], arena_bytes=2 << 30, precision=precision, max_rves=len(cells))
+    ids = [B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol, h=w.h) for w in cells]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    launches = B.drain()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    q = [B.query(i) for i in ids]
+    B.close()
+    its = [int(x[3]) for x in q]
+    nvox = int(cells[0].phase_map.size)
+    return {"workload": f"length-scale sweep: {n} x {n} cells (l_e, l_p in [0.1, 1]), 16^3 four spheres, "
+                        f"100 load steps each, {precision}, one resident batch",
+            "rves": len(cells), "seconds": round(dt, 3), "rve_solves_per_s": round(len(cells) / dt, 2),
+            "voxel_iterations_per_s": sum(its) * nvox / dt, "graph_launches": int(launches),
+            "iterations_total": sum(its), "iterations_max": max(its), "iterations_median": float(np.median(its)),
+            "statuses": sorted({int(x[1]) for x in q})}
+
+
 def extra_serve(torch, mp, W, n=8):
     """A short Poisson trace of the serving workload (edges 32-128 only, 10-12
     load steps): the closed-loop saturation of continuous batching, then the
@@ -612,6 +639,8 @@ def main():
                     help="only time the augmented-Lagrangian against the basic scheme at contrast 20")
     ap.add_argument("--green-ab", action="store_true",
                     help="only time the stored against the computed Green operator (32^3-256^3)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only time the 10 x 10 length-scale sweep (16^3 cells, 100 steps each) as one mixed batch")
     ap.add_argument("--ratchet", action="store_true",
                     help="only time the Sec. 3.2 ratcheting path (1000 steps on the 4^3 laminate, FP64 plan)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -646,6 +675,9 @@ def main():
         return
     if args.ratchet:
         print(json.dumps(extra_ratchet(torch, mp, W)), flush=True)
+        return
+    if args.sweep:
+        print(json.dumps(run_sweep(torch, mp, W)), flush=True)
         return
     if args.workload in ("batch64_mixed", "serve_mixed"):
         run = run_batch if args.workload == "batch64_mixed" else run_serve

@@ -357,7 +357,12 @@ mp_status mp_batch_admit(mp_batch batch, const mp_problem* prob, int32_t n_steps
  * number still unfinished.  Blocks. */
 mp_status mp_batch_run(mp_batch batch, int32_t* n_active);
 
-/* mp_batch_run until no RVE is unfinished (or max_launches > 0 launches). */
+/* Graph launches as mp_batch_run until no RVE is unfinished (or
+ * max_launches > 0 launches).  From the second launch on, each launch is
+ * queued before the state after the previous one is read back, so the host's
+ * checks overlap the GPU's work; the one launch queued after the last RVE
+ * finished finds no work and changes nothing.  *launches counts every
+ * launch.  Blocks. */
 mp_status mp_batch_drain(mp_batch batch, int32_t max_launches, int32_t* launches);
 
 /* State (MP_RVE_RUNNING | MP_RVE_DONE), status (MP_OK, MP_E_NOT_CONVERGED or

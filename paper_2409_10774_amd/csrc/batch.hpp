@@ -68,11 +68,21 @@ struct Lists {
 // in the common case a block takes a single item.  No atomics: a shared
 // work counter serialises across the chip's L2 domains.
 // x pass of one shape class: ITER over the RUN list, or TRANS over the
-// TRANS list (separate kernels, so each keeps its own register budget); AN:
-// the Eq. 5 variant of the pass body, for a class holding an RVE with Eq. 5
-// phases (an RVE without them takes the same arithmetic in either variant);
-// AL (FP64 ITER only): each RVE runs the augmented-Lagrangian or the basic
-// pass body by its own flag, for a class holding an augmented-Lagrangian RVE
+// TRANS list (commit of an RVE's step and first iterate of its next).  In
+// low precision the ITER kernel also takes the TRANS items, after its own:
+// the two lists hold different RVEs, each item runs its own pass body, and a
+// class needs one x kernel per loop iteration instead of two (the 10 x 10
+// length-scale sweep of 16^3 cells: 3.6 against 3.69 s).  The TRANS body
+// then shares the ITER kernel's register budget, which in FP64 costs the
+// loop body spills (a basic FP64 batch 2 % slower): FP64 keeps the TRANS
+// kernel apart.  AN: the Eq. 5 variant of the pass body, for a class holding
+// an RVE with Eq. 5 phases (an RVE without them takes the same arithmetic in
+// either variant); AL (FP64 ITER only): each RVE runs the
+// augmented-Lagrangian or the basic loop body by its own flag, for a class
+// holding an augmented-Lagrangian RVE
+template <class T>
+constexpr bool x_merged() { return sizeof(T) < sizeof(double); }
+
 template <class T, int MODE, int N0, bool AN, bool AL = false>
 __global__ void __launch_bounds__((XShape<T, N0>::NTHR), (AL ? x_min_waves<T, MODE, true>() : x_min_waves<T, MODE>())) k_batch_x(const Rve<T>* __restrict__ rv,
                                                               const Lists* __restrict__ ls, int cls,
@@ -84,22 +94,37 @@ __global__ void __launch_bounds__((XShape<T, N0>::NTHR), (AL ? x_min_waves<T, MO
   __shared__ cx<T> twl[N0];
   constexpr bool STASH = sizeof(T) < sizeof(double) && MODE == X_ITER;
   __shared__ double stash[STASH ? 9 * X::NTHR : 1];
+  // this kernel's own items, then (low precision ITER) the TRANS items
+  constexpr bool WITH_TRANS = MODE == X_ITER && x_merged<T>();
   const int n = MODE == X_ITER ? ls->ns[cls] : ls->nt[cls];
   const int* list = MODE == X_ITER ? ls->s[cls] : ls->t[cls];
-  const long total = long(n) * tiles;   // (RVE, tile) items, two levels each
-  if (total == 0) return;
+  const int nt = WITH_TRANS ? ls->nt[cls] : 0;
+  const long total = long(n) * tiles, total_t = long(nt) * tiles;   // (RVE, tile) items, two levels each
+  if (total == 0 && total_t == 0) return;
+  // item slots: the own items' x_grid, then the TRANS items' (x_grid is a
+  // multiple of 16 for one level per block, so the level pairing of x_item
+  // holds in both ranges)
+  const long gi = x_grid<X::LPB>(total), gend = gi + x_grid<X::LPB>(total_t);
   // every RVE of a class has the same twiddles: load them once per block
-  load_twiddles<T, N0, X::NTHR>(twl, glob(rv[list[0]].x.tw), threadIdx.x);
+  load_twiddles<T, N0, X::NTHR>(twl, glob(rv[n > 0 ? list[0] : ls->t[cls][0]].x.tw), threadIdx.x);
   // items w -> ((RVE, tile), first level) as x_item; the grid is a multiple
   // of 16, so the two levels of an item in separate blocks run on one XCD
-  for (long w = blockIdx.x; w < x_grid<X::LPB>(total); w += gridDim.x) {
+  for (long w = blockIdx.x; w < gend; w += gridDim.x) {
+    const bool trans = WITH_TRANS && w >= gi;
     long u;
     int lvl;
-    x_item<X::LPB>(w, &u, &lvl);
-    if (u >= total) continue;
-    const int slot = list[u / tiles];
+    x_item<X::LPB>(trans ? w - gi : w, &u, &lvl);
+    if (u >= (trans ? total_t : total)) continue;
+    const int slot = trans ? ls->t[cls][u / tiles] : list[u / tiles];
     const int tile = int(u % tiles);
     __syncthreads();   // the previous item is done with LDS
+    if constexpr (WITH_TRANS) {
+      if (trans) {
+        xpass_tile<T, X_TRANS, N0, AN>(rv[slot].x, tile, lvl, tiles, lds, lds2, red, twl, fresh_tid(), false,
+                                       false, stash);
+        continue;
+      }
+    }
     if constexpr (AL && MODE == X_ITER && sizeof(T) == sizeof(double)) {
       // the scheme is uniform over the item (one RVE): the two bodies never
       // share one loop's registers

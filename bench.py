@@ -40,13 +40,13 @@ def bytes_per_voxel(w):
 # only for the kernel sources they were taken on (SHA-1 of the two headers)
 MEASURED_TRAFFIC = {
     "spheres128_fp64": {"kernel": "x_pass", "bytes": (941.9 + 619.7) * 1e6,
-                        "src_sha1": "9233818bf8b3e57c51d3d507e3aad80b154cf7fe"},
-    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5117.3 + 3687.1) * 1e6,
-                         "src_sha1": "9233818bf8b3e57c51d3d507e3aad80b154cf7fe"},
-    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4895.6) * 1e6,
-                        "src_sha1": "9233818bf8b3e57c51d3d507e3aad80b154cf7fe"},
-    "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.1 + 619.7) * 1e6,
-                      "src_sha1": "9233818bf8b3e57c51d3d507e3aad80b154cf7fe"},
+                        "src_sha1": "e002d1c414ef81bcc913c4ffb406dfb0b9d1772e"},
+    "spheres256_mixed": {"kernel": "x_pass", "bytes": (5117.3 + 3687.2) * 1e6,
+                         "src_sha1": "e002d1c414ef81bcc913c4ffb406dfb0b9d1772e"},
+    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4897.5) * 1e6,
+                        "src_sha1": "e002d1c414ef81bcc913c4ffb406dfb0b9d1772e"},
+    "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.0 + 619.7) * 1e6,
+                      "src_sha1": "e002d1c414ef81bcc913c4ffb406dfb0b9d1772e"},
 }
 
 

@@ -104,6 +104,41 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+// v of lane (this lane xor o), o a power of two below 64: lane distances 1,
+// 2 and 8 by DPP moves (quad permutations, a rotation by 8 within each row
+// of 16 lanes), 4 and 16 by LDS swizzles (xor masks within 32 lanes), 32 by
+// a permute through LDS
+__device__ __forceinline__ double xor_lanes(double v, int o) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = int(bits), hi = int(bits >> 32);
+  int a, b;
+  switch (o) {
+    case 1:
+      a = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+      b = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+      break;
+    case 2:
+      a = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+      b = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+      break;
+    case 8:
+      a = __builtin_amdgcn_update_dpp(0, lo, 0x128, 0xF, 0xF, false);
+      b = __builtin_amdgcn_update_dpp(0, hi, 0x128, 0xF, 0xF, false);
+      break;
+    case 4:
+      a = __builtin_amdgcn_ds_swizzle(lo, 0x101F);
+      b = __builtin_amdgcn_ds_swizzle(hi, 0x101F);
+      break;
+    case 16:
+      a = __builtin_amdgcn_ds_swizzle(lo, 0x401F);
+      b = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
+      break;
+    default:
+      return __shfl_xor(v, o, 64);
+  }
+  return __longlong_as_double((long long)(unsigned)a | ((long long)b << 32));
+}
+
 // NaN-propagating max (a non-finite field must not look converged)
 __device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
@@ -125,7 +160,7 @@ __device__ __forceinline__ void wave_reduce(double (&v)[K], unsigned maxmask, in
     for (int i = 0; i < k; ++i) {
       const double send = up ? v[i] : v[i + k];
       const double keep = up ? v[i + k] : v[i];
-      const double recv = __shfl_xor(send, o, 64);
+      const double recv = xor_lanes(send, o);
       const int j = base + (up ? k : 0) + i;
       v[i] = ((maxmask >> j) & 1u) ? nmax(keep, recv) : keep + recv;
     }
@@ -134,7 +169,7 @@ __device__ __forceinline__ void wave_reduce(double (&v)[K], unsigned maxmask, in
   const bool mx = (maxmask >> base) & 1u;
 #pragma unroll
   for (int o = 32 / K; o > 0; o >>= 1) {
-    const double recv = __shfl_xor(v[0], o, 64);
+    const double recv = xor_lanes(v[0], o);
     v[0] = mx ? nmax(v[0], recv) : v[0] + recv;
   }
   if ((lane & (64 / K - 1)) == 0) out[base] = v[0];

@@ -310,3 +310,26 @@ def test_batch_cancel_slot_limit_and_empty(mp):
     assert_same(batched(B, b), solo(mp, wls[1], "fp64"), b)
     assert_same(batched(B, c), solo(mp, wls[2], "fp64"), c)
     B.close()
+
+
+def test_drain_in_bounded_calls_equals_solo(mp):
+    """mp_batch_drain queues each graph launch before reading back the state
+    after the previous one; with max_launches it stops at that many launches
+    (1, then 3), RVEs stay resident and running, and the rest of the drain
+    finishes them equal bit for bit to their solo plans."""
+    say("case: drain split into bounded calls, mixed, 3 RVEs")
+    wls = mixed_set(1e-6)[:3]
+    B = mp.Batch(SHAPES, arena_bytes=256 << 20, precision="mixed", max_rves=8, iters_per_launch=4)
+    ids = [B.admit(w.phase_map, w.phases, w.times, w.E, w.G, tol=w.tol) for w in wls]
+    assert B.drain(1) == 1
+    assert any(B.query(i)[0] == mp.MP_RVE_RUNNING for i in ids)
+    assert B.drain(3) == 3
+    rest = B.drain()
+    say("launches after the bounded calls", rest)
+    assert rest >= 1
+    for rid, w in zip(ids, wls):
+        b = batched(B, rid)
+        assert b["state"] == mp.MP_RVE_DONE
+        assert_same(b, solo(mp, w, "mixed"), rid)
+    assert B.drain() == 1   # nothing left: one launch, no work
+    B.close()

@@ -40,13 +40,13 @@ def bytes_per_voxel(w):
 # only for the kernel sources they were taken on (SHA-1 of the two headers)
 MEASURED_TRAFFIC = {
     "spheres128_fp64": {"kernel": "x_pass", "bytes": (941.9 + 619.7) * 1e6,
-                        "src_sha1": "e002d1c414ef81bcc913c4ffb406dfb0b9d1772e"},
+                        "src_sha1": "77dc9aeb6cc33d85a046e0fb0c06bf19e2851704"},
     "spheres256_mixed": {"kernel": "x_pass", "bytes": (5117.3 + 3687.2) * 1e6,
-                         "src_sha1": "e002d1c414ef81bcc913c4ffb406dfb0b9d1772e"},
-    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4897.5) * 1e6,
-                        "src_sha1": "e002d1c414ef81bcc913c4ffb406dfb0b9d1772e"},
-    "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.0 + 619.7) * 1e6,
-                      "src_sha1": "e002d1c414ef81bcc913c4ffb406dfb0b9d1772e"},
+                         "src_sha1": "77dc9aeb6cc33d85a046e0fb0c06bf19e2851704"},
+    "spheres256_fp64": {"kernel": "x_pass", "bytes": (7533.2 + 4897.1) * 1e6,
+                        "src_sha1": "77dc9aeb6cc33d85a046e0fb0c06bf19e2851704"},
+    "aniso128_fp64": {"kernel": "x_pass", "bytes": (942.1 + 619.7) * 1e6,
+                      "src_sha1": "77dc9aeb6cc33d85a046e0fb0c06bf19e2851704"},
 }
 
 

@@ -109,8 +109,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // of 16 lanes), 4 and 16 by LDS swizzles (xor masks within 32 lanes), 32 by
 // a permute through LDS
 __device__ __forceinline__ double xor_lanes(double v, int o) {
-  const long long bits = __double_as_longlong(v);
-  const int lo = int(bits), hi = int(bits >> 32);
+  const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(v));
+  const int lo = int(unsigned(bits)), hi = int(unsigned(bits >> 32));
   int a, b;
   switch (o) {
     case 1:
@@ -136,7 +136,8 @@ __device__ __forceinline__ double xor_lanes(double v, int o) {
     default:
       return __shfl_xor(v, o, 64);
   }
-  return __longlong_as_double((long long)(unsigned)a | ((long long)b << 32));
+  return __longlong_as_double(
+      static_cast<long long>((static_cast<unsigned long long>(unsigned(b)) << 32) | unsigned(a)));
 }
 
 // NaN-propagating max (a non-finite field must not look converged)
